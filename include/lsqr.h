@@ -1,0 +1,173 @@
+/*
+ * lsqr.h - C ABI of the MI355X (gfx950) AVU-GSR LSQR library.
+ *
+ * The library solves the overdetermined sparse system A x = b of the Gaia
+ * AVU-GSR solver (Cesare et al., "The MPI + CUDA Gaia AVU-GSR Parallel Solver
+ * Toward Next-generation Exascale Infrastructures", Eq. (1)) in the least
+ * squares sense with LSQR (Paige & Saunders, ACM TOMS 8, 1982), entirely on
+ * one GPU. Each row of A is one observation and holds exactly
+ *     n_astro = 5 astrometric coefficients  (columns n_astro*star + j),
+ *     n_axes * n_par_axis = 3 * 4 attitude coefficients (axis a, parameter q:
+ *         column att_base + a*n_dfa + att_start + q, one att_start per row
+ *         shared by the three axes),
+ *     n_instr = 6 instrumental coefficients (columns instr_base + instr_idx),
+ *     n_glob  = 1 global coefficient (column glob_base),
+ * the row layout of the paper's Sect. 2 (dense per-row coefficient array A_d
+ * with index arrays M_i and I_c). Columns are ordered
+ *     astrometric [0, att_base) | attitude [att_base, instr_base) |
+ *     instrumental [instr_base, glob_base) | global [glob_base, n)
+ * with att_base = 5*n_stars, instr_base = att_base + 3*n_dfa,
+ * glob_base = instr_base + n_instr_cols, n = glob_base + 1.
+ *
+ * All array arguments are DEVICE pointers (memory of the GPU the handle was
+ * created on) unless stated otherwise. lsqr_aprod1/lsqr_aprod2 run
+ * asynchronously on the stream given in the system descriptor; lsqr_create
+ * and the solves first synchronize with that stream, run on a stream owned by
+ * the handle and return when done. Calls on one handle must not overlap. No
+ * function aborts or exits; each returns an lsqr_status, and on failure
+ * lsqr_last_error() describes it.
+ */
+#ifndef AVUGSR_LSQR_H
+#define AVUGSR_LSQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lsqr_status;
+#define LSQR_OK 0
+#define LSQR_E_INVALID (-1)     /* bad argument, descriptor or index out of range */
+#define LSQR_E_HIP (-2)         /* HIP runtime error                                */
+#define LSQR_E_NOMEM (-3)       /* device allocation failed                         */
+#define LSQR_E_STATE (-4)       /* call not valid for this handle                   */
+#define LSQR_E_UNSUPPORTED (-5) /* descriptor valid but outside what is built       */
+
+#define LSQR_F64 0 /* coefficient values stored as double */
+#define LSQR_F32 1 /* coefficient values stored as float  */
+
+/* Sparse system descriptor. The matrix arrays are BORROWED: the library keeps
+ * the pointers (zero copy), never frees them, and the caller keeps them alive
+ * and unchanged until lsqr_destroy. */
+typedef struct lsqr_system {
+    int64_t n_rows;       /* m, number of observation rows (> 0)                 */
+    int64_t n_stars;      /* stars; astrometric columns = 5 * n_stars             */
+    int32_t n_astro;      /* must be 5                                            */
+    int32_t n_axes;       /* must be 3                                            */
+    int32_t n_par_axis;   /* must be 4                                            */
+    int32_t n_instr;      /* must be 6                                            */
+    int64_t n_dfa;        /* attitude degrees of freedom per axis (>= n_par_axis) */
+    int64_t n_instr_cols; /* instrumental columns (> 0)                           */
+    int32_t n_glob;       /* must be 1                                            */
+    int32_t value_type;   /* LSQR_F64 or LSQR_F32                                 */
+    int32_t precondition; /* 1: scale columns to unit norm (Sect. 2), 0: no       */
+    int32_t reserved;
+    /* [24][n_rows] structure of arrays, row i of section c at c*n_rows + i,
+     * section order astro(5) | att axis0(4) axis1(4) axis2(4) | instr(6) | glob */
+    const void* values;
+    const int64_t* star_of_row; /* [n_rows], non-decreasing, in [0, n_stars)      */
+    const int64_t* att_start;   /* [n_rows], in [0, n_dfa - n_par_axis]           */
+    const int32_t* instr_idx;   /* [6][n_rows] SoA, in [0, n_instr_cols)          */
+    void* stream;               /* hipStream_t for all work, NULL = null stream   */
+} lsqr_system;
+
+/* Result of a solve. istop follows Paige & Saunders:
+ * 0 x = 0 solves (b = 0 or A^T b = 0), 1 residual test S1, 2 normal-equation
+ * test S2, 3 condition limit, 4/5/6 the same tests at machine precision,
+ * 7 iteration limit. Non-convergence (7) is not an error. */
+typedef struct lsqr_info {
+    int32_t istop;
+    int32_t itn;          /* LSQR iterations (inner iterations summed for refined) */
+    int32_t outer_steps;  /* refinement steps (lsqr_solve_refined), else 0         */
+    int32_t reserved;
+    double rnorm;         /* ||b - A x|| estimate (phibar)                         */
+    double arnorm;        /* ||Abar^T r|| estimate                                 */
+    double anorm;         /* Frobenius-norm estimate of Abar = A diag(p)           */
+    double acond;         /* condition estimate of Abar                            */
+    double xnorm;         /* ||diag(p)^-1 x||                                      */
+    double bnorm;         /* ||b||                                                 */
+} lsqr_info;
+
+typedef struct lsqr_handle lsqr_handle;
+
+/* Create a handle: validates the descriptor and every index (a scan of the
+ * index arrays on the GPU), computes the column scaling p_j = 1/||A[:,j]||
+ * (1 for an empty column; Sect. 2, preconditioning) and allocates the
+ * workspace (owned by the handle). Synchronous. */
+lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out);
+
+/* Free the workspace. Never touches the borrowed arrays. NULL is a no-op. */
+lsqr_status lsqr_destroy(lsqr_handle* h);
+
+/* Options (lsqr_set_option):
+ *   LSQR_OPT_CONLIM       condition limit of stopping test 3 (default 1e8; 0 off)
+ *   LSQR_OPT_TESTS        1 (default): stopping tests 1..6 on; 0: run exactly
+ *                         itn_limit iterations (istop 7)
+ *   LSQR_OPT_CHUNK        iterations per HIP-graph launch (default 16, >= 1)
+ *   LSQR_OPT_GRAPH        1 (default): iterations replayed from a captured HIP
+ *                         graph; 0: launched one by one
+ *   LSQR_OPT_PROFILE      1: time every aprod1 / aprod2 launch of a solve with
+ *                         HIP events on the handle's stream (forces GRAPH 0);
+ *                         read back with lsqr_kernel_times
+ *   LSQR_OPT_OUTER_TOL    refinement: stop when ||d||_inf <= tol ||x||_inf
+ *                         (default 1e-10)
+ */
+#define LSQR_OPT_CONLIM 1
+#define LSQR_OPT_TESTS 2
+#define LSQR_OPT_CHUNK 3
+#define LSQR_OPT_GRAPH 4
+#define LSQR_OPT_PROFILE 5
+#define LSQR_OPT_OUTER_TOL 6
+lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
+
+/* aprod mode 1, Eq. (2): y[m] += A x[n] with the raw (unscaled) A.
+ * FP64 vectors; float-stored values are widened, accumulation in FP64.
+ * Asynchronous on the handle's stream; x and y must not overlap. */
+lsqr_status lsqr_aprod1(lsqr_handle* h, const double* x, double* y);
+
+/* aprod mode 2, Eq. (3): x[n] += A^T y[m] with the raw A. Same conventions. */
+lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y);
+
+/* Copy the column scaling p (FP64 [n]) into p_out (device). */
+lsqr_status lsqr_get_precond(lsqr_handle* h, double* p_out);
+
+/* Least-squares solve of A x = b by LSQR on Abar = A diag(p), x = p .* y
+ * (Sect. 2, Algorithm 1; Paige & Saunders). b: FP64 [m], not modified.
+ * x: FP64 [n], output (x_0 = 0). atol/btol: stopping tolerances of tests S1,
+ * S2, itn_limit >= 0. On an LSQR_F32 system the float values are widened
+ * and every operation is FP64 (the FP64 reference of the refined solve).
+ * Synchronous; info may be NULL. */
+lsqr_status lsqr_solve(lsqr_handle* h, const double* b, double* x, int32_t itn_limit,
+                       double atol, double btol, lsqr_info* info);
+
+/* FP32-stored system: FP64 iterative refinement around an FP32 LSQR.
+ * Outer step k: r = b - A x in FP64 (values widened, FP64 accumulation),
+ * then an inner LSQR on min ||A d - r|| with FP32 products and FP32
+ * accumulation (FP64 norms, Givens scalars and x/w updates), stopped by its
+ * own tests with tolerances atol, btol or after itn_limit iterations; then
+ * x += d in FP64. The outer loop ends when ||d||_inf <= OUTER_TOL ||x||_inf,
+ * when r is zero or orthogonal to the range of A, or after outer_limit steps.
+ * b: FP64 [m]; x: FP64 [n] output (x_0 = 0). info->itn counts the inner
+ * iterations of all steps, info->outer_steps the outer steps, info->istop and
+ * the estimates are those of the last inner solve (its rnorm estimates
+ * ||b - A x||), info->bnorm is ||b||. Synchronous; info may be NULL. */
+lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32_t itn_limit,
+                               double atol, double btol, int32_t outer_limit, lsqr_info* info);
+
+/* Per-kernel timing of the last solve run with LSQR_OPT_PROFILE = 1:
+ * total milliseconds and launch counts of the aprod1 and aprod2 kernels.
+ * Host pointers; any may be NULL. */
+lsqr_status lsqr_kernel_times(lsqr_handle* h, double* ms_aprod1, int64_t* n_aprod1,
+                              double* ms_aprod2, int64_t* n_aprod2);
+
+/* Number of columns n of the handle's system. Host pointer out. */
+lsqr_status lsqr_num_cols(lsqr_handle* h, int64_t* n_out);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* lsqr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AVUGSR_LSQR_H */

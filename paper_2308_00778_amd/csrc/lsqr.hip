@@ -1,0 +1,727 @@
+// Host side of the AVU-GSR LSQR library: handle, workspace, the LSQR
+// iteration driven on one GPU, and the C ABI declared in include/lsqr.h.
+//
+// One LSQR iteration (Paige & Saunders 1982; the paper's Algorithm 1 loop) is
+// eight kernels on one stream, with every scalar kept on the device:
+//   aprod1      u~ <- A (p.*v) - (alpha/beta) u~      [+ ||u~||^2 partials]
+//   beta        beta = ||u~||, anorm
+//   aprod2      q  <- A^T u~                           [astro/att/instr/glob]
+//   glob_sum    second stage of the global-column reduction
+//   col_a       v~ = p.*q/beta - beta v               [+ ||v~||^2 partials]
+//   alpha       alpha = ||v~||, plane rotation, estimates
+//   col_b       v = v~/alpha, y += (phi/rho) w, w = v - (theta/rho) w
+//   stop        ddnorm, xnorm, acond, stopping tests, itn
+// u~ is the unnormalised left vector (u = u~/beta); keeping it unnormalised
+// saves a pass over the row-sized vector per iteration. Preconditioning
+// (column scaling by p, Sect. 2) is applied on the column vectors, so the
+// borrowed matrix is never modified.
+//
+// Iterations are launched in chunks, replayed from a captured HIP graph; a
+// finished solve leaves a `done` flag that makes the rest of the chunk a
+// sequence of empty kernels. The host reads one flag per chunk.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lsqr.h"
+
+using namespace avugsr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lsqr_status fail(lsqr_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(e_ == hipErrorOutOfMemory ? LSQR_E_NOMEM : LSQR_E_HIP,             \
+                        "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,   \
+                        __LINE__);                                                         \
+    } while (0)
+
+#define LSQR_TRY(expr)                           \
+    do {                                         \
+        lsqr_status s_ = (expr);                 \
+        if (s_ != LSQR_OK) return s_;            \
+    } while (0)
+
+template <typename V>
+lsqr_status dalloc(V** p, int64_t count)
+{
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), (size_t)count * sizeof(V));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? LSQR_E_NOMEM : LSQR_E_HIP,
+                    "hipMalloc of %lld bytes failed: %s", (long long)(count * sizeof(V)),
+                    hipGetErrorString(e));
+    }
+    return LSQR_OK;
+}
+
+template <typename V>
+void dfree(V*& p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+constexpr int64_t kLdsInstrBudget = 64 * 1024;  // bytes of LDS for the instrumental histogram
+
+// Working vectors of one arithmetic precision of the LSQR loop.
+template <typename Acc>
+struct Path {
+    Acc* u = nullptr;      // [m] unnormalised left vector u~
+    Acc* vp = nullptr;     // [n] p .* v, gathered by aprod1
+    Acc* q = nullptr;      // [n] aprod2 accumulator (zero between uses)
+    Acc* gpart = nullptr;  // [nb2] global-column partials
+    size_t lds = 0;        // dynamic LDS bytes of aprod2
+    int lds_instr = 0;
+    hipGraphExec_t graph = nullptr;
+    int graph_chunk = 0;
+    bool ready = false;
+};
+
+}  // namespace
+
+struct lsqr_handle {
+    SysView sv{};
+    int value_type = LSQR_F64;
+    int precondition = 1;
+    int device = 0;
+    int num_cu = 0;
+    hipStream_t user_stream = nullptr;  // aprod1/aprod2 entry points
+    hipStream_t stream = nullptr;       // solves (capturable, owned)
+
+    int nb1 = 0;  // aprod1 grid
+    int nb2 = 0;  // aprod2 grid (4 star-aligned row ranges per block)
+    int nbc = 0;  // column-kernel grid
+
+    int64_t* wb = nullptr;  // [nb2*4 + 1] row boundaries
+    double* p = nullptr;    // [n] column scaling
+    double* v = nullptr;    // [n]
+    double* w = nullptr;    // [n]
+    double* y = nullptr;    // [n] iterate in the scaled space
+    double* part1 = nullptr;                    // [nb1]
+    double* partc = nullptr;                    // [nbc]
+    double* partdd = nullptr;                   // [nbc]
+    double* partxx = nullptr;                   // [nbc]
+    double* gpart_raw = nullptr;                // [nb2] FP64 partials of lsqr_aprod2
+    int32_t* flag = nullptr;                    // validation flags
+    Scalars* sc = nullptr;                      // device scalars
+    Scalars* sc_host = nullptr;                 // pinned mirror
+
+    Path<double> p64;
+    Path<float> p32;
+
+    // options
+    double conlim = 1e8;
+    int tests = 1;
+    int chunk = 16;
+    int use_graph = 1;
+    int profile = 0;
+    double outer_tol = 1e-10;
+
+    // profiling
+    std::vector<hipEvent_t> events;
+    double ms1 = 0.0, ms2 = 0.0;
+    int64_t n1 = 0, n2 = 0;
+};
+
+namespace {
+
+// ------------------------------------------------------------ launch helpers
+template <typename T, typename Acc>
+lsqr_status launch_aprod2_lsqr(lsqr_handle* h, Path<Acc>& P, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false>), dim3(h->nb2), dim3(kBlock), P.lds, st,
+                       h->sv, P.u, P.q, h->wb, P.gpart, P.lds_instr, h->sc);
+    hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), dim3(kBlock), 0, st, P.gpart, h->nb2,
+                       P.q + h->sv.glob_base, h->sc);
+    return LSQR_OK;
+}
+
+// One LSQR iteration; ev (optional) = 4 events bracketing aprod1 and aprod2.
+template <typename T, typename Acc>
+void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* ev)
+{
+    const int64_t n = h->sv.n;
+    if (ev) (void)hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL((k_aprod1<T, Acc, Acc, Acc, A1_LSQR>), dim3(h->nb1), dim3(kBlock), 0, st,
+                       h->sv, (const Acc*)P.vp, P.u, (const double*)nullptr, h->sc, h->part1);
+    if (ev) (void)hipEventRecord(ev[1], st);
+    hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
+    if (ev) (void)hipEventRecord(ev[2], st);
+    hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false>), dim3(h->nb2), dim3(kBlock), P.lds, st,
+                       h->sv, (const Acc*)P.u, P.q, h->wb, P.gpart, P.lds_instr, h->sc);
+    if (ev) (void)hipEventRecord(ev[3], st);
+    hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), dim3(kBlock), 0, st, P.gpart, h->nb2,
+                       P.q + h->sv.glob_base, h->sc);
+    hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
+                       h->sc, h->partc);
+    hipLaunchKernelGGL(k_scalar_alpha, dim3(1), dim3(kBlock), 0, st, h->partc, h->nbc, h->sc);
+    hipLaunchKernelGGL((k_col_b<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, h->v, h->w,
+                       h->y, P.vp, h->sc, h->partdd, h->partxx);
+    hipLaunchKernelGGL(k_scalar_stop, dim3(1), dim3(kBlock), 0, st, h->partdd, h->partxx, h->nbc,
+                       h->sc);
+}
+
+// Initialisation given u~ (already written) and ||u~||^2 partials in part1.
+template <typename T, typename Acc>
+void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st)
+{
+    const int64_t n = h->sv.n;
+    hipLaunchKernelGGL(k_scalar_init_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
+    hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, P.q, (Acc)0);
+    hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->v, 0.0);
+    hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false>), dim3(h->nb2), dim3(kBlock), P.lds, st,
+                       h->sv, (const Acc*)P.u, P.q, h->wb, P.gpart, P.lds_instr, h->sc);
+    hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), dim3(kBlock), 0, st, P.gpart, h->nb2,
+                       P.q + h->sv.glob_base, h->sc);
+    hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
+                       h->sc, h->partc);
+    hipLaunchKernelGGL(k_scalar_init_alpha, dim3(1), dim3(kBlock), 0, st, h->partc, h->nbc, h->sc);
+    hipLaunchKernelGGL((k_col_init<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, h->v, h->w,
+                       h->y, P.vp, h->sc);
+}
+
+template <typename T, typename Acc>
+lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
+{
+    if (P.ready) return LSQR_OK;
+    const int64_t m = h->sv.m, n = h->sv.n;
+    LSQR_TRY(dalloc(&P.u, m));
+    LSQR_TRY(dalloc(&P.vp, n));
+    LSQR_TRY(dalloc(&P.q, n));
+    LSQR_TRY(dalloc(&P.gpart, h->nb2));
+    const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(Acc);
+    P.lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
+    P.lds = P.lds_instr ? (size_t)bytes : 0;
+    hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n, P.q, (Acc)0);
+    HIP_TRY(hipGetLastError());
+    P.ready = true;
+    return LSQR_OK;
+}
+
+template <typename Acc>
+void release_path(Path<Acc>& P)
+{
+    if (P.graph) (void)hipGraphExecDestroy(P.graph);
+    P.graph = nullptr;
+    dfree(P.u);
+    dfree(P.vp);
+    dfree(P.q);
+    dfree(P.gpart);
+    P.ready = false;
+}
+
+lsqr_status upload_controls(lsqr_handle* h, int32_t itn_limit, double atol, double btol)
+{
+    // The controls are written into the pinned mirror and copied as one block
+    // with the rest of the (reset) state; the kernels then own the state.
+    Scalars* s = h->sc_host;
+    memset(s, 0, sizeof(Scalars));
+    s->atol = atol;
+    s->btol = btol;
+    s->ctol = h->conlim > 0.0 ? 1.0 / h->conlim : 0.0;
+    s->itn_limit = itn_limit;
+    s->tests = h->tests;
+    s->inv_alpha = 1.0;
+    HIP_TRY(hipMemcpyAsync(h->sc, s, sizeof(Scalars), hipMemcpyHostToDevice, h->stream));
+    return LSQR_OK;
+}
+
+lsqr_status read_scalars(lsqr_handle* h)
+{
+    HIP_TRY(hipMemcpyAsync(h->sc_host, h->sc, sizeof(Scalars), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LSQR_OK;
+}
+
+// Runs chunks of iterations until the device reports done.
+template <typename T, typename Acc>
+lsqr_status run_iterations(lsqr_handle* h, Path<Acc>& P)
+{
+    const int chunk = std::max(1, h->chunk);
+    const bool graph = h->use_graph && !h->profile;
+    if (graph && (P.graph == nullptr || P.graph_chunk != chunk)) {
+        if (P.graph) (void)hipGraphExecDestroy(P.graph);
+        P.graph = nullptr;
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < chunk; ++k) launch_iteration<T, Acc>(h, P, h->stream, nullptr);
+        hipError_t e = hipStreamEndCapture(h->stream, &g);
+        if (e != hipSuccess) return fail(LSQR_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&P.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            P.graph = nullptr;
+            return fail(LSQR_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        P.graph_chunk = chunk;
+    }
+    if (h->profile && h->events.size() < (size_t)4 * chunk) {
+        while (h->events.size() < (size_t)4 * chunk) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            h->events.push_back(e);
+        }
+    }
+    for (;;) {
+        const int32_t itn_before = h->sc_host->itn;
+        if (graph) {
+            HIP_TRY(hipGraphLaunch(P.graph, h->stream));
+        } else {
+            for (int k = 0; k < chunk; ++k)
+                launch_iteration<T, Acc>(h, P, h->stream,
+                                         h->profile ? &h->events[4 * k] : nullptr);
+            HIP_TRY(hipGetLastError());
+        }
+        LSQR_TRY(read_scalars(h));
+        if (h->profile) {
+            const int ran = std::min(chunk, h->sc_host->itn - itn_before);
+            for (int k = 0; k < ran; ++k) {
+                float a = 0.f, b = 0.f;
+                HIP_TRY(hipEventElapsedTime(&a, h->events[4 * k], h->events[4 * k + 1]));
+                HIP_TRY(hipEventElapsedTime(&b, h->events[4 * k + 2], h->events[4 * k + 3]));
+                h->ms1 += a;
+                h->ms2 += b;
+                h->n1 += 1;
+                h->n2 += 1;
+            }
+        }
+        if (h->sc_host->done) break;
+        // Every chunk either finishes the solve or advances itn; anything else
+        // means a launch did not run, and looping would never end.
+        if (h->sc_host->itn <= itn_before)
+            return fail(LSQR_E_HIP, "LSQR iteration made no progress (itn %d)", h->sc_host->itn);
+    }
+    return LSQR_OK;
+}
+
+void fill_info(const lsqr_handle* h, lsqr_info* info, int32_t itn, int32_t outer, double bnorm)
+{
+    if (!info) return;
+    const Scalars* s = h->sc_host;
+    memset(info, 0, sizeof(*info));
+    info->istop = s->istop;
+    info->itn = itn;
+    info->outer_steps = outer;
+    info->rnorm = s->rnorm;
+    info->arnorm = s->arnorm;
+    info->anorm = s->anorm;
+    info->acond = s->acond;
+    info->xnorm = s->xnorm;
+    info->bnorm = bnorm;
+}
+
+template <typename T>
+lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_limit, double atol,
+                       double btol, lsqr_info* info)
+{
+    LSQR_TRY((prepare_path<T, double>(h, h->p64)));
+    Path<double>& P = h->p64;
+    const int64_t m = h->sv.m, n = h->sv.n;
+    if (h->profile) {
+        h->ms1 = h->ms2 = 0.0;
+        h->n1 = h->n2 = 0;
+    }
+    LSQR_TRY(upload_controls(h, itn_limit, atol, btol));
+    hipLaunchKernelGGL((k_copy_ssq<double>), dim3(h->nb1), dim3(kBlock), 0, h->stream, m, b, P.u,
+                       h->part1);
+    launch_init<T, double>(h, P, h->stream);
+    HIP_TRY(hipGetLastError());
+    LSQR_TRY(read_scalars(h));
+    if (!h->sc_host->done && itn_limit > 0) LSQR_TRY((run_iterations<T, double>(h, P)));
+    hipLaunchKernelGGL(k_unprecond, dim3(h->nbc), dim3(kBlock), 0, h->stream, n, h->p, h->y, x);
+    HIP_TRY(hipGetLastError());
+    LSQR_TRY(read_scalars(h));
+    fill_info(h, info, h->sc_host->itn, 0, h->sc_host->bnorm);
+    return LSQR_OK;
+}
+
+lsqr_status check_handle(lsqr_handle* h)
+{
+    if (!h) return fail(LSQR_E_INVALID, "null handle");
+    HIP_TRY(hipSetDevice(h->device));
+    return LSQR_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* lsqr_last_error(void) { return g_last_error.c_str(); }
+
+lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
+{
+    g_last_error.clear();
+    if (!out) return fail(LSQR_E_INVALID, "out is null");
+    *out = nullptr;
+    if (!sys) return fail(LSQR_E_INVALID, "system descriptor is null");
+    if (sys->n_rows <= 0) return fail(LSQR_E_INVALID, "n_rows must be > 0");
+    if (sys->n_stars <= 0) return fail(LSQR_E_INVALID, "n_stars must be > 0");
+    if (sys->n_astro != kAstro || sys->n_axes != kAxes || sys->n_par_axis != kParAxis ||
+        sys->n_instr != kInstr || sys->n_glob != 1)
+        return fail(LSQR_E_UNSUPPORTED,
+                    "only the 5 astrometric + 3x4 attitude + 6 instrumental + 1 global row "
+                    "layout is built (got %d, %dx%d, %d, %d)",
+                    sys->n_astro, sys->n_axes, sys->n_par_axis, sys->n_instr, sys->n_glob);
+    if (sys->n_dfa < sys->n_par_axis) return fail(LSQR_E_INVALID, "n_dfa must be >= n_par_axis");
+    if (sys->n_instr_cols < sys->n_instr)
+        return fail(LSQR_E_INVALID, "n_instr_cols must be >= n_instr");
+    if (sys->n_instr_cols > INT32_MAX) return fail(LSQR_E_INVALID, "n_instr_cols too large");
+    if (sys->value_type != LSQR_F64 && sys->value_type != LSQR_F32)
+        return fail(LSQR_E_INVALID, "value_type must be LSQR_F64 or LSQR_F32");
+    if (!sys->values || !sys->star_of_row || !sys->att_start || !sys->instr_idx)
+        return fail(LSQR_E_INVALID, "matrix array pointer is null");
+    if (sys->n_rows > ((int64_t)1 << 40)) return fail(LSQR_E_INVALID, "n_rows too large");
+
+    lsqr_handle* h = new (std::nothrow) lsqr_handle();
+    if (!h) return fail(LSQR_E_NOMEM, "host allocation failed");
+    auto bail = [&](lsqr_status st) {
+        lsqr_destroy(h);
+        return st;
+    };
+
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) return bail(fail(LSQR_E_HIP, "hipGetDevice: %s", hipGetErrorString(e)));
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, h->device);
+    if (e != hipSuccess)
+        return bail(fail(LSQR_E_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e)));
+    h->num_cu = prop.multiProcessorCount;
+
+    SysView& s = h->sv;
+    s.val = sys->values;
+    s.star = sys->star_of_row;
+    s.att = sys->att_start;
+    s.instr = sys->instr_idx;
+    s.m = sys->n_rows;
+    s.n_stars = sys->n_stars;
+    s.n_dfa = sys->n_dfa;
+    s.n_instr_cols = sys->n_instr_cols;
+    s.att_base = (int64_t)kAstro * sys->n_stars;
+    s.instr_base = s.att_base + (int64_t)kAxes * sys->n_dfa;
+    s.glob_base = s.instr_base + sys->n_instr_cols;
+    s.n = s.glob_base + 1;
+    h->value_type = sys->value_type;
+    h->precondition = sys->precondition ? 1 : 0;
+    h->user_stream = static_cast<hipStream_t>(sys->stream);
+
+    e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return bail(fail(LSQR_E_HIP, "stream: %s", hipGetErrorString(e)));
+
+    // grids
+    const int64_t m = s.m, n = s.n;
+    {
+        int occ = 0;
+        if (h->value_type == LSQR_F64)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &occ, k_aprod1<double, double, double, double, A1_LSQR>, kBlock, 0);
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &occ, k_aprod1<float, float, float, float, A1_LSQR>, kBlock, 0);
+        if (e != hipSuccess || occ <= 0) occ = 4;
+        h->nb1 = (int)std::max<int64_t>(
+            1, std::min<int64_t>((int64_t)h->num_cu * occ, cdiv(m, 2 * kBlock)));
+    }
+    {
+        // aprod2 grid: as many resident workgroups as the LDS histogram allows
+        const size_t lds = (size_t)std::min<int64_t>(s.n_instr_cols * 8, kLdsInstrBudget);
+        int occ = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, k_aprod2<double, double, double, false>, kBlock, lds);
+        if (e != hipSuccess || occ <= 0) occ = 2;
+        occ = std::min(occ, 4);
+        h->nb2 = (int)std::max<int64_t>(
+            1, std::min<int64_t>((int64_t)h->num_cu * occ, cdiv(m, (int64_t)kWave * kWavesPerBlock)));
+    }
+    h->nbc = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)h->num_cu * 4, cdiv(n, kBlock)));
+
+    lsqr_status st;
+    const int64_t nw = (int64_t)h->nb2 * kWavesPerBlock;
+    if ((st = dalloc(&h->wb, nw + 1)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->p, n)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->v, n)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->w, n)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->y, n)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->part1, h->nb1)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->partc, h->nbc)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->partdd, h->nbc)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->partxx, h->nbc)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->gpart_raw, h->nb2)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->flag, 1)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->sc, 1)) != LSQR_OK) return bail(st);
+    e = hipHostMalloc(reinterpret_cast<void**>(&h->sc_host), sizeof(Scalars), hipHostMallocDefault);
+    if (e != hipSuccess) return bail(fail(LSQR_E_NOMEM, "pinned scalars: %s", hipGetErrorString(e)));
+    memset(h->sc_host, 0, sizeof(Scalars));
+
+    // Work ordered after whatever produced the matrix on the caller's stream.
+    e = hipStreamSynchronize(h->user_stream);
+    if (e != hipSuccess) return bail(fail(LSQR_E_HIP, "sync: %s", hipGetErrorString(e)));
+    hipStream_t st0 = h->stream;
+
+    // 1. validate every index before any kernel gathers or scatters with it
+    int32_t zero = 0;
+    e = hipMemcpyAsync(h->flag, &zero, sizeof zero, hipMemcpyHostToDevice, st0);
+    if (e != hipSuccess) return bail(fail(LSQR_E_HIP, "flag: %s", hipGetErrorString(e)));
+    hipLaunchKernelGGL(k_validate, dim3(std::min<int64_t>(cdiv(m, kBlock), 8192)), dim3(kBlock), 0,
+                       st0, s, h->flag);
+    int32_t bad = 0;
+    e = hipMemcpyAsync(&bad, h->flag, sizeof bad, hipMemcpyDeviceToHost, st0);
+    if (e == hipSuccess) e = hipStreamSynchronize(st0);
+    if (e != hipSuccess) return bail(fail(LSQR_E_HIP, "validate: %s", hipGetErrorString(e)));
+    if (bad) {
+        return bail(fail(LSQR_E_INVALID,
+                         "index validation failed:%s%s%s%s",
+                         (bad & 1) ? " star_of_row out of [0,n_stars)" : "",
+                         (bad & 2) ? " star_of_row not non-decreasing" : "",
+                         (bad & 4) ? " att_start out of [0,n_dfa-4]" : "",
+                         (bad & 8) ? " instr_idx out of [0,n_instr_cols)" : ""));
+    }
+
+    // 2. star-aligned row ranges of the aprod2 waves
+    hipLaunchKernelGGL(k_wave_bounds, dim3(cdiv(nw + 1, kBlock)), dim3(kBlock), 0, st0, s.star, m,
+                       nw, h->wb);
+
+    // 3. column scaling p from the column norms (squared-coefficient aprod2)
+    double* ssq = nullptr;
+    if ((st = dalloc(&ssq, n)) != LSQR_OK) return bail(st);
+    const int64_t bytes64 = s.n_instr_cols * 8;
+    const int lds_instr = bytes64 <= kLdsInstrBudget ? 1 : 0;
+    const size_t lds = lds_instr ? (size_t)bytes64 : 0;
+    hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st0, n, ssq, 0.0);
+    if (h->value_type == LSQR_F64)
+        hipLaunchKernelGGL((k_aprod2<double, double, double, true>), dim3(h->nb2), dim3(kBlock), lds,
+                           st0, s, (const double*)nullptr, ssq, h->wb, h->gpart_raw, lds_instr,
+                           (const Scalars*)nullptr);
+    else
+        hipLaunchKernelGGL((k_aprod2<float, double, double, true>), dim3(h->nb2), dim3(kBlock), lds,
+                           st0, s, (const double*)nullptr, ssq, h->wb, h->gpart_raw, lds_instr,
+                           (const Scalars*)nullptr);
+    hipLaunchKernelGGL((k_glob_sum<double>), dim3(1), dim3(kBlock), 0, st0, h->gpart_raw, h->nb2,
+                       ssq + s.glob_base, (const Scalars*)nullptr);
+    hipLaunchKernelGGL(k_make_p, dim3(h->nbc), dim3(kBlock), 0, st0, n, ssq, h->p, h->precondition);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st0);
+    (void)hipFree(ssq);
+    if (e != hipSuccess) return bail(fail(LSQR_E_HIP, "set-up kernels: %s", hipGetErrorString(e)));
+
+    *out = h;
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_destroy(lsqr_handle* h)
+{
+    if (!h) return LSQR_OK;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    release_path(h->p64);
+    release_path(h->p32);
+    dfree(h->wb);
+    dfree(h->p);
+    dfree(h->v);
+    dfree(h->w);
+    dfree(h->y);
+    dfree(h->part1);
+    dfree(h->partc);
+    dfree(h->partdd);
+    dfree(h->partxx);
+    dfree(h->gpart_raw);
+    dfree(h->flag);
+    dfree(h->sc);
+    if (h->sc_host) (void)hipHostFree(h->sc_host);
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
+{
+    if (!h) return fail(LSQR_E_INVALID, "null handle");
+    switch (option) {
+    case LSQR_OPT_CONLIM:
+        if (!(value >= 0.0)) return fail(LSQR_E_INVALID, "conlim must be >= 0");
+        h->conlim = value;
+        return LSQR_OK;
+    case LSQR_OPT_TESTS:
+        h->tests = value != 0.0 ? 1 : 0;
+        return LSQR_OK;
+    case LSQR_OPT_CHUNK:
+        if (!(value >= 1.0 && value <= 4096.0)) return fail(LSQR_E_INVALID, "chunk in [1,4096]");
+        h->chunk = (int)value;
+        return LSQR_OK;
+    case LSQR_OPT_GRAPH:
+        h->use_graph = value != 0.0 ? 1 : 0;
+        return LSQR_OK;
+    case LSQR_OPT_PROFILE:
+        h->profile = value != 0.0 ? 1 : 0;
+        return LSQR_OK;
+    case LSQR_OPT_OUTER_TOL:
+        if (!(value >= 0.0)) return fail(LSQR_E_INVALID, "outer tolerance must be >= 0");
+        h->outer_tol = value;
+        return LSQR_OK;
+    default:
+        return fail(LSQR_E_INVALID, "unknown option %d", option);
+    }
+}
+
+lsqr_status lsqr_aprod1(lsqr_handle* h, const double* x, double* y)
+{
+    LSQR_TRY(check_handle(h));
+    if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
+    if (h->value_type == LSQR_F64)
+        hipLaunchKernelGGL((k_aprod1<double, double, double, double, A1_ACCUM>), dim3(h->nb1),
+                           dim3(kBlock), 0, h->user_stream, h->sv, x, y, (const double*)nullptr,
+                           (const Scalars*)nullptr, (double*)nullptr);
+    else
+        hipLaunchKernelGGL((k_aprod1<float, double, double, double, A1_ACCUM>), dim3(h->nb1),
+                           dim3(kBlock), 0, h->user_stream, h->sv, x, y, (const double*)nullptr,
+                           (const Scalars*)nullptr, (double*)nullptr);
+    HIP_TRY(hipGetLastError());
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y)
+{
+    LSQR_TRY(check_handle(h));
+    if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
+    const int64_t bytes = h->sv.n_instr_cols * 8;
+    const int lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
+    const size_t lds = lds_instr ? (size_t)bytes : 0;
+    if (h->value_type == LSQR_F64)
+        hipLaunchKernelGGL((k_aprod2<double, double, double, false>), dim3(h->nb2), dim3(kBlock),
+                           lds, h->user_stream, h->sv, y, x, h->wb, h->gpart_raw, lds_instr,
+                           (const Scalars*)nullptr);
+    else
+        hipLaunchKernelGGL((k_aprod2<float, double, double, false>), dim3(h->nb2), dim3(kBlock), lds,
+                           h->user_stream, h->sv, y, x, h->wb, h->gpart_raw, lds_instr,
+                           (const Scalars*)nullptr);
+    hipLaunchKernelGGL((k_glob_sum<double>), dim3(1), dim3(kBlock), 0, h->user_stream,
+                       h->gpart_raw, h->nb2, x + h->sv.glob_base, (const Scalars*)nullptr);
+    HIP_TRY(hipGetLastError());
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_get_precond(lsqr_handle* h, double* p_out)
+{
+    LSQR_TRY(check_handle(h));
+    if (!p_out) return fail(LSQR_E_INVALID, "null output");
+    HIP_TRY(hipMemcpyAsync(p_out, h->p, (size_t)h->sv.n * sizeof(double), hipMemcpyDeviceToDevice,
+                           h->user_stream));
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_num_cols(lsqr_handle* h, int64_t* n_out)
+{
+    if (!h || !n_out) return fail(LSQR_E_INVALID, "null argument");
+    *n_out = h->sv.n;
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_solve(lsqr_handle* h, const double* b, double* x, int32_t itn_limit, double atol,
+                       double btol, lsqr_info* info)
+{
+    LSQR_TRY(check_handle(h));
+    if (!b || !x) return fail(LSQR_E_INVALID, "null vector");
+    if (itn_limit < 0) return fail(LSQR_E_INVALID, "itn_limit must be >= 0");
+    if (!(atol >= 0.0) || !(btol >= 0.0)) return fail(LSQR_E_INVALID, "atol, btol must be >= 0");
+    HIP_TRY(hipStreamSynchronize(h->user_stream));
+    if (h->value_type == LSQR_F64)
+        LSQR_TRY(solve_fp64<double>(h, b, x, itn_limit, atol, btol, info));
+    else
+        LSQR_TRY(solve_fp64<float>(h, b, x, itn_limit, atol, btol, info));
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32_t itn_limit,
+                               double atol, double btol, int32_t outer_limit, lsqr_info* info)
+{
+    LSQR_TRY(check_handle(h));
+    if (!b || !x) return fail(LSQR_E_INVALID, "null vector");
+    if (h->value_type != LSQR_F32)
+        return fail(LSQR_E_STATE, "lsqr_solve_refined needs an LSQR_F32 system");
+    if (itn_limit < 0 || outer_limit < 1)
+        return fail(LSQR_E_INVALID, "itn_limit >= 0 and outer_limit >= 1 required");
+    if (!(atol >= 0.0) || !(btol >= 0.0)) return fail(LSQR_E_INVALID, "atol, btol must be >= 0");
+    HIP_TRY(hipStreamSynchronize(h->user_stream));
+    LSQR_TRY((prepare_path<float, float>(h, h->p32)));
+    Path<float>& P = h->p32;
+    const int64_t n = h->sv.n;
+    if (h->profile) {
+        h->ms1 = h->ms2 = 0.0;
+        h->n1 = h->n2 = 0;
+    }
+    double* part_d = h->partdd;  // reused: not live between outer steps
+    double* part_x = h->partxx;
+    hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n, x, 0.0);
+    int32_t total_itn = 0, outer = 0;
+    double bnorm = 0.0;
+    Scalars last{};
+    for (outer = 1; outer <= outer_limit; ++outer) {
+        LSQR_TRY(upload_controls(h, itn_limit, atol, btol));
+        // FP64 residual of the full problem, stored as the FP32 start vector
+        hipLaunchKernelGGL((k_aprod1<float, double, double, float, A1_RESID>), dim3(h->nb1),
+                           dim3(kBlock), 0, h->stream, h->sv, (const double*)x, P.u, b,
+                           (const Scalars*)nullptr, h->part1);
+        launch_init<float, float>(h, P, h->stream);
+        HIP_TRY(hipGetLastError());
+        LSQR_TRY(read_scalars(h));
+        if (outer == 1) bnorm = h->sc_host->bnorm;
+        if (h->sc_host->done) {  // residual zero or orthogonal to range(A)
+            last = *h->sc_host;
+            break;
+        }
+        if (itn_limit > 0) LSQR_TRY((run_iterations<float, float>(h, P)));
+        last = *h->sc_host;
+        total_itn += last.itn;
+        hipLaunchKernelGGL(k_refine_update, dim3(h->nbc), dim3(kBlock), 0, h->stream, n, h->p, h->y,
+                           x, part_d, part_x);
+        hipLaunchKernelGGL(k_refine_norms, dim3(1), dim3(kBlock), 0, h->stream, part_d, part_x,
+                           h->nbc, h->sc);
+        HIP_TRY(hipGetLastError());
+        LSQR_TRY(read_scalars(h));
+        if (h->sc_host->dmax <= h->outer_tol * h->sc_host->xmax) break;
+    }
+    if (outer > outer_limit) outer = outer_limit;
+    *h->sc_host = last;
+    fill_info(h, info, total_itn, outer, bnorm);
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_kernel_times(lsqr_handle* h, double* ms_aprod1, int64_t* n_aprod1,
+                              double* ms_aprod2, int64_t* n_aprod2)
+{
+    if (!h) return fail(LSQR_E_INVALID, "null handle");
+    if (ms_aprod1) *ms_aprod1 = h->ms1;
+    if (n_aprod1) *n_aprod1 = h->n1;
+    if (ms_aprod2) *ms_aprod2 = h->ms2;
+    if (n_aprod2) *n_aprod2 = h->n2;
+    return LSQR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by
+element, on seeded synthetic systems.
+
+Tolerances. aprod outputs are sums of products; the summation orders differ
+(FMA, wave trees, atomics), so each element is compared against the bound
+c * eps * sum |terms| computed with the oracle on |A| and |x| (|y|), with c
+covering the term count of that element (24 per row for aprod1; up to m for
+the global column of aprod2). LSQR solutions must agree to a relative
+infinity-norm of 1e-10 at equal iteration count (the target of this solver).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+SPECS = {
+    "c0": synth.CONFIGS[0],
+    "ragged": synth.tiny(seed=21, n_stars=37, obs=(1, 140), n_dfa=50, n_instr_cols=17),
+    "one_star": synth.tiny(seed=22, n_stars=1, obs=(70, 70), n_dfa=8, n_instr_cols=6),
+    "few_rows": synth.tiny(seed=23, n_stars=3, obs=(5, 9), n_dfa=5, n_instr_cols=7),
+    "wide_instr": synth.tiny(seed=24, n_stars=200, obs=(20, 60), n_dfa=300,
+                             n_instr_cols=9000),  # instrumental histogram beyond the LDS budget
+}
+
+_SYS = {}
+
+
+def system(name):
+    if name not in _SYS:
+        S = synth.make_system(SPECS[name])
+        _SYS[name] = (S, oracle.OracleSystem.from_synth(S))
+    return _SYS[name]
+
+
+def gpu_system(torch, S, precondition=True):
+    from paper_2308_00778_amd import LsqrSystem
+
+    return LsqrSystem.from_host(S, "cuda:0", precondition=precondition)
+
+
+def abs_system(S):
+    sp = S.spec
+    return oracle.OracleSystem(np.abs(S.values.astype(np.float64)), S.star_of_row, S.att_start,
+                               S.instr_idx, n_stars=sp.n_stars, n_dfa=sp.n_dfa,
+                               n_instr_cols=sp.n_instr_cols)
+
+
+def rel_inf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("name", list(SPECS))
+def test_aprod1_parity(torch_cuda, name):
+    torch = torch_cuda
+    S, o = system(name)
+    say(f"aprod1 parity: {name} m={S.m} n={o.n} seed={S.spec.seed}")
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(o.n)
+    y0 = rng.standard_normal(o.m)
+    want = o.aprod1(x, y0)
+    bound = abs_system(S).aprod1(np.abs(x), np.abs(y0))
+    g = gpu_system(torch, S)
+    yd = torch.from_numpy(y0).cuda()
+    g.aprod1(torch.from_numpy(x).cuda(), yd)
+    torch.cuda.synchronize()
+    got = yd.cpu().numpy()
+    g.close()
+    assert np.all(np.abs(got - want) <= 32 * EPS * bound + 1e-300)
+
+
+@pytest.mark.parametrize("name", list(SPECS))
+def test_aprod2_parity(torch_cuda, name):
+    torch = torch_cuda
+    S, o = system(name)
+    say(f"aprod2 parity: {name} m={S.m} n={o.n} seed={S.spec.seed}")
+    rng = np.random.default_rng(6)
+    y = rng.standard_normal(o.m)
+    x0 = rng.standard_normal(o.n)
+    want = o.aprod2(y, x0)
+    bound = abs_system(S).aprod2(np.abs(y), np.abs(x0))
+    g = gpu_system(torch, S)
+    xd = torch.from_numpy(x0).cuda()
+    g.aprod2(xd, torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    got = xd.cpu().numpy()
+    g.close()
+    # per-column term count: at most m (global column)
+    c = 2.0 * np.sqrt(S.m) + 32
+    assert np.all(np.abs(got - want) <= c * EPS * bound + 1e-300)
+
+
+@pytest.mark.parametrize("name", ["c0", "ragged", "wide_instr"])
+def test_precond_parity(torch_cuda, name):
+    torch = torch_cuda
+    S, o = system(name)
+    say(f"column norms: {name}")
+    g = gpu_system(torch, S)
+    p = g.precond().cpu().numpy()
+    g.close()
+    assert rel_inf(p, o.precond()) < 1e-13
+
+
+def _b(S, o, rhs=0):
+    xt = synth.x_true(S.spec)
+    return o.aprod1(xt, synth.noise(S.spec, S.m, rhs=rhs))
+
+
+@pytest.mark.parametrize("name,itn", [("c0", 50), ("c0", 200), ("ragged", 120),
+                                       ("one_star", 30), ("few_rows", 25), ("wide_instr", 60)])
+@pytest.mark.parametrize("graph", [1, 0])
+def test_solve_fixed_iterations(torch_cuda, name, itn, graph):
+    torch = torch_cuda
+    S, o = system(name)
+    b = _b(S, o)
+    x_ref, i_ref = o.lsqr(b, itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+    say(f"solve parity: {name} itn={itn} graph={graph}")
+    g = gpu_system(torch, S)
+    g.set_option("tests", 0)
+    g.set_option("graph", graph)
+    g.set_option("chunk", 7)
+    x, info = g.solve(torch.from_numpy(b).cuda(), itn, atol=0.0, btol=0.0)
+    torch.cuda.synchronize()
+    xg = x.cpu().numpy()
+    g.close()
+    assert info.itn == i_ref.itn == itn and info.istop == 7
+    assert rel_inf(xg, x_ref) <= 1e-10
+    for k in ("rnorm", "anorm", "acond", "xnorm", "bnorm"):
+        a, r = getattr(info, k), getattr(i_ref, k)
+        assert abs(a - r) <= 1e-8 * abs(r), (k, a, r)
+
+
+def test_solve_stopping_rules(torch_cuda):
+    torch = torch_cuda
+    S, o = system("c0")
+    b = _b(S, o)
+    x_ref, i_ref = o.lsqr(b, 300, atol=1e-12, btol=1e-12, conlim=1e8)
+    say("solve stopping rules: c0 atol=btol=1e-12")
+    g = gpu_system(torch, S)
+    x, info = g.solve(torch.from_numpy(b).cuda(), 300, atol=1e-12, btol=1e-12)
+    xg = x.cpu().numpy()
+    g.close()
+    assert info.istop == i_ref.istop and abs(info.itn - i_ref.itn) <= 1, (info, i_ref)
+    assert rel_inf(xg, x_ref) <= 1e-10
+    # converged: normal-equation residual of the scaled problem
+    p = o.precond()
+    r = b - o.aprod1(xg)
+    assert np.linalg.norm(p * o.aprod2(r)) <= 1e-11 * info.anorm * np.linalg.norm(r)
+
+
+def test_zero_rhs_and_zero_iterations(torch_cuda):
+    torch = torch_cuda
+    S, o = system("ragged")
+    say("edge: b = 0, itn_limit = 0")
+    g = gpu_system(torch, S)
+    x, info = g.solve(torch.zeros(S.m, dtype=torch.float64, device="cuda"), 50)
+    assert info.istop == 0 and info.itn == 0 and not torch.any(x).item()
+    b = _b(S, o)
+    x, info = g.solve(torch.from_numpy(b).cuda(), 0)
+    assert info.itn == 0 and not torch.any(x).item()
+    g.close()
+
+
+def test_no_preconditioning(torch_cuda):
+    torch = torch_cuda
+    S, o = system("ragged")
+    b = _b(S, o)
+    x_ref, _ = o.lsqr(b, 80, atol=0.0, btol=0.0, conlim=0.0, tests=False, precondition=False)
+    say("solve without preconditioning: ragged itn=80")
+    g = gpu_system(torch, S, precondition=False)
+    g.set_option("tests", 0)
+    x, info = g.solve(torch.from_numpy(b).cuda(), 80, atol=0.0, btol=0.0)
+    xg = x.cpu().numpy()
+    g.close()
+    assert rel_inf(xg, x_ref) <= 1e-10
+
+
+def test_invalid_indices_are_rejected(torch_cuda):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LSQR_E_INVALID, LsqrError, LsqrSystem
+
+    S, _ = system("few_rows")
+    sp = S.spec
+    base = dict(values=torch.from_numpy(S.values).cuda(),
+                star_of_row=torch.from_numpy(S.star_of_row).cuda(),
+                att_start=torch.from_numpy(S.att_start).cuda(),
+                instr_idx=torch.from_numpy(S.instr_idx).cuda())
+    cases = {
+        "star_out_of_range": ("star_of_row", lambda t: t.__setitem__(-1, sp.n_stars)),
+        "star_unsorted": ("star_of_row", lambda t: t.__setitem__(0, 2)),
+        "att_out_of_range": ("att_start", lambda t: t.__setitem__(3, sp.n_dfa - 3)),
+        "instr_out_of_range": ("instr_idx", lambda t: t.__setitem__((5, 2), sp.n_instr_cols)),
+        "instr_negative": ("instr_idx", lambda t: t.__setitem__((0, 0), -1)),
+    }
+    for case, (key, mutate) in cases.items():
+        say(f"invalid descriptor: {case}")
+        arrays = {k: v.clone() for k, v in base.items()}
+        mutate(arrays[key])
+        torch.cuda.synchronize()
+        with pytest.raises(LsqrError) as ei:
+            LsqrSystem(**arrays, n_stars=sp.n_stars, n_dfa=sp.n_dfa,
+                       n_instr_cols=sp.n_instr_cols)
+        assert ei.value.status == LSQR_E_INVALID, case
+
+
+F32_SPEC = synth.tiny(seed=31, n_stars=400, obs=(100, 100), n_dfa=400, n_instr_cols=120,
+                      value_dtype="f32", astro_scale=(-2.0, 2.0))
+
+
+def test_fp64_solve_on_float_values(torch_cuda):
+    torch = torch_cuda
+    S = synth.make_system(F32_SPEC)
+    o = oracle.OracleSystem.from_synth(S)  # widens the float values
+    b = _b(S, o)
+    x_ref, _ = o.lsqr(b, 60, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+    say("FP64 solve on float-stored values: itn=60")
+    g = gpu_system(torch, S)
+    g.set_option("tests", 0)
+    x, info = g.solve(torch.from_numpy(b).cuda(), 60, atol=0.0, btol=0.0)
+    xg = x.cpu().numpy()
+    g.close()
+    assert rel_inf(xg, x_ref) <= 1e-10
+
+
+def test_refined_matches_fp64_oracle(torch_cuda):
+    torch = torch_cuda
+    S = synth.make_system(F32_SPEC)
+    o = oracle.OracleSystem.from_synth(S)
+    b = _b(S, o)
+    x_ref, i_ref = o.lsqr(b, 500, atol=1e-14, btol=1e-14, conlim=0.0)
+    say(f"refined solve: FP32 values m={S.m}; oracle itn={i_ref.itn} istop={i_ref.istop}")
+    g = gpu_system(torch, S)
+    x, info = g.solve_refined(torch.from_numpy(b).cuda(), 200, atol=1e-6, btol=1e-6,
+                              outer_limit=8)
+    xg = x.cpu().numpy()
+    g.close()
+    say(f"refined: outer={info.outer_steps} inner itn={info.itn} "
+        f"err={rel_inf(xg, x_ref):.3e}")
+    assert info.outer_steps <= 6
+    assert rel_inf(xg, x_ref) <= 1e-10
+
+
+def test_profile_counts_launches(torch_cuda):
+    torch = torch_cuda
+    S, o = system("c0")
+    b = _b(S, o)
+    say("profile mode: c0 itn=20")
+    g = gpu_system(torch, S)
+    g.set_option("tests", 0)
+    g.set_option("profile", 1)
+    x, info = g.solve(torch.from_numpy(b).cuda(), 20, atol=0.0, btol=0.0)
+    t = g.kernel_times()
+    g.close()
+    assert t["aprod1_n"] == t["aprod2_n"] == 20
+    assert t["aprod1_ms"] > 0 and t["aprod2_ms"] > 0
+    x_ref, _ = o.lsqr(b, 20, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+    assert rel_inf(x.cpu().numpy(), x_ref) <= 1e-10
