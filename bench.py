@@ -1,0 +1,156 @@
+"""Benchmark: LSQR iterations per second on the AVU-GSR system, one MI355X.
+
+Workload (default): 1,000,000 stars x 100 observations = 1e8 rows, FP64
+values (19.2 GB), 3 x 100,000 attitude columns, 6,000 instrumental columns,
+1 global column (5,306,001 unknowns); synthetic seeded inputs shaped like the
+paper's system. A step is one LSQR iteration (aprod1, beta, aprod2, alpha,
+Givens rotation, x/w update, stopping tests); the timed region is one
+lsqr_solve of exactly `steps` iterations (stopping tests off) with HIP events
+around every aprod1 / aprod2 launch on the stream they run on.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+# algorithmic bytes per row and launch (FP64 values, configured index layout)
+BYTES_PER_ROW = {"aprod1": 24 * 8 + 40 + 16, "aprod2": 24 * 8 + 40 + 8}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(spec, sample_stars=20_000, itn=(1, 6)):
+    """The oracle as it stands, single thread, on the first `sample_stars`
+    stars of the workload (same N_DFA and instrumental columns), per-iteration
+    time from two runs of different length, scaled to the full row count."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    sub = spec.scaled(n_stars=sample_stars)
+    S = synth.make_system(sub)
+    o = oracle.OracleSystem.from_synth(S)
+    b = o.aprod1(synth.x_true(sub), synth.noise(sub, S.m))
+    t = []
+    for k in itn:
+        t0 = time.perf_counter()
+        o.lsqr(b, k, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+        t.append(time.perf_counter() - t0)
+    per_iter = (t[1] - t[0]) / (itn[1] - itn[0])
+    full_rows = spec.n_stars * spec.obs_lo
+    per_iter_full = per_iter * full_rows / S.m
+    return {"value": 1.0 / per_iter_full, "unit": "iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_stars} stars ({S.m} rows) of the workload, LSQR "
+                      f"iterations {itn[0]} and {itn[1]} timed, difference per iteration "
+                      f"({per_iter:.3f} s) scaled by {full_rows}/{S.m} rows",
+            "seconds": sum(t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding "
+              "is a design, not a build, here", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2308_00778_amd import LsqrSystem
+
+    dev = torch.device("cuda:0")
+    spec = synth.CONFIGS[args.config]
+    assert spec.value_dtype == "f64", "the FP64 bench runs on an FP64 workload"
+    t0 = time.perf_counter()
+    arrays, first = synth.device_system(spec, dev)
+    m = int(first[-1])
+    torch.cuda.synchronize()
+    log(f"generated m={m} rows on the GPU in {time.perf_counter() - t0:.1f} s")
+    g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
+                   n_instr_cols=spec.n_instr_cols)
+    n = g.n
+    # b = A x_true + noise, formed on the GPU with the library's aprod1
+    xt = synth.device_x_true(spec, dev)
+    b = synth.device_noise(spec, m, 0, dev)
+    g.aprod1(xt, b)
+    torch.cuda.synchronize()
+    log(f"handle ready n={n} in {time.perf_counter() - t0:.1f} s")
+
+    g.set_option("tests", 0)
+    g.set_option("profile", 1)
+    if args.warmup > 0:
+        g.solve(b, args.warmup, atol=0.0, btol=0.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x, info = g.solve(b, args.steps, atol=0.0, btol=0.0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    kt = g.kernel_times()
+    assert info.itn == args.steps and kt["aprod1_n"] == args.steps == kt["aprod2_n"]
+    ms = {"aprod1": kt["aprod1_ms"] / kt["aprod1_n"], "aprod2": kt["aprod2_ms"] / kt["aprod2_n"]}
+    gbps = {k: BYTES_PER_ROW[k] * m / (ms[k] * 1e-3) / 1e9 for k in ms}
+    dom = max(ms, key=ms.get)
+    log(f"timed {args.steps} iterations in {wall:.3f} s; aprod1 {ms['aprod1']:.3f} ms "
+        f"({gbps['aprod1']:.0f} GB/s), aprod2 {ms['aprod2']:.3f} ms ({gbps['aprod2']:.0f} GB/s)")
+
+    # graph-replayed iterations (no events) for comparison
+    g.set_option("profile", 0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g.solve(b, args.steps, atol=0.0, btol=0.0)
+    torch.cuda.synchronize()
+    wall_graph = time.perf_counter() - t2
+
+    result = {
+        "metric": "LSQR iter/s + aprod HBM GB/s, FP64 vs FP32+refine & batched RHS at 1e-10 err",
+        "value": args.steps / wall,
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"AVU-GSR LSQR FP64, {spec.n_stars} stars x {spec.obs_lo} obs = "
+                               f"{m} rows x {n} unknowns (N_DFA={spec.n_dfa}, "
+                               f"{spec.n_instr_cols} instrumental, 1 global), seed {spec.seed}",
+                   "rows": m, "unknowns": n, "values": "f64"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": gbps[dom], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": gbps[dom] / HBM_PEAK_GBPS, "traffic": None},
+        "kernels": {k: {"ms": ms[k], "GBps": gbps[k], "bytes_per_row": BYTES_PER_ROW[k],
+                        "frac_of_peak": gbps[k] / HBM_PEAK_GBPS} for k in ms},
+        "graph_iter_per_s": args.steps / wall_graph,
+        "solve_info": {"itn": info.itn, "istop": info.istop, "rnorm": info.rnorm},
+    }
+    g.close()
+    del arrays
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a sample ...")
+        result["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -38,6 +38,46 @@ def build(verbose: bool = False) -> str:
     return _LIB_PATH
 
 
+_GPU_LIB_PATH = os.path.join(_HERE, "libsynth_gpu.so")
+_gpu_lib = None
+
+
+def build_gpu(verbose: bool = False) -> str:
+    """Compile libsynth_gpu.so (the on-GPU twin of the generator) for gfx950."""
+    import subprocess
+
+    src = os.path.join(_HERE, "synth_gpu.hip")
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    cmd = [hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-o", _GPU_LIB_PATH + ".tmp", src]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_GPU_LIB_PATH + ".tmp", _GPU_LIB_PATH)
+    return _GPU_LIB_PATH
+
+
+def _load_gpu():
+    global _gpu_lib
+    if _gpu_lib is not None:
+        return _gpu_lib
+    if not os.path.exists(_GPU_LIB_PATH):
+        raise RuntimeError(f"{_GPU_LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(_GPU_LIB_PATH)
+    P = ctypes.c_void_p
+    i64, i32, u64, u32, f64 = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                               ctypes.c_uint32, ctypes.c_double)
+    lib.synth_gpu_star_of_row.argtypes = [P, i64, i64, P, P]
+    lib.synth_gpu_rows.argtypes = [u64, i64, i64, i64, P, i32, i32, i32, i64, i32, i64, i32,
+                                   f64, f64, i32, P, P, P, P]
+    lib.synth_gpu_normals.argtypes = [u64, u32, i64, i64, f64, P, P]
+    for f in (lib.synth_gpu_star_of_row, lib.synth_gpu_rows, lib.synth_gpu_normals):
+        f.restype = ctypes.c_int
+    _gpu_lib = lib
+    return lib
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -59,6 +99,10 @@ def _load():
     lib.synth_rows.restype = None
     lib.synth_normals.argtypes = [u64, u32, i64, i64, f64, P]
     lib.synth_normals.restype = None
+    lib.synth_test_ln.argtypes = [f64]
+    lib.synth_test_ln.restype = f64
+    lib.synth_test_exp.argtypes = [f64]
+    lib.synth_test_exp.restype = f64
     _lib = lib
     return lib
 
@@ -211,3 +255,57 @@ def tiny(seed: int = 7, n_stars: int = 20, obs=(30, 30), n_dfa: int = 20,
     """Small systems for brute-force checks."""
     return Spec(n_stars=n_stars, obs_lo=obs[0], obs_hi=obs[1], n_dfa=n_dfa,
                 n_instr_cols=n_instr_cols, seed=seed, value_dtype=value_dtype, **kw)
+
+
+# ------------------------------------------------------------ on-GPU twin
+def device_system(spec: Spec, device="cuda:0"):
+    """Generate the whole system directly in GPU memory (torch tensors), bit
+    for bit the arrays make_system would produce on the host."""
+    import torch
+
+    lib = _load_gpu()
+    first = star_layout(spec)
+    m = int(first[-1])
+    dev = torch.device(device)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    vdt = torch.float64 if spec.value_dtype == "f64" else torch.float32
+    first_d = torch.from_numpy(first).to(dev)
+    star = torch.empty(m, dtype=torch.int64, device=dev)
+    att = torch.empty(m, dtype=torch.int64, device=dev)
+    instr = torch.empty((spec.n_instr, m), dtype=torch.int32, device=dev)
+    values = torch.empty((spec.n_par, m), dtype=vdt, device=dev)
+    rc = lib.synth_gpu_star_of_row(first_d.data_ptr(), spec.n_stars, m, star.data_ptr(), stream)
+    if rc != 0:
+        raise RuntimeError(f"synth_gpu_star_of_row failed ({rc})")
+    lo, hi = spec.astro_scale if spec.astro_scale else (0.0, 0.0)
+    rc = lib.synth_gpu_rows(spec.seed, 0, m, m, star.data_ptr(), spec.n_astro, spec.n_axes,
+                            spec.n_par_axis, spec.n_dfa, spec.n_instr, spec.n_instr_cols,
+                            spec.n_glob, float(lo), float(hi), 0 if vdt == torch.float64 else 1,
+                            values.data_ptr(), att.data_ptr(), instr.data_ptr(), stream)
+    if rc != 0:
+        raise RuntimeError(f"synth_gpu_rows failed ({rc})")
+    return dict(values=values, star_of_row=star, att_start=att, instr_idx=instr), first
+
+
+def device_normals(spec: Spec, stream_id: int, n: int, sigma: float, device="cuda:0",
+                   i0: int = 0):
+    """sigma * N(0,1) draws i0..i0+n of a stream, generated on the GPU."""
+    import torch
+
+    lib = _load_gpu()
+    dev = torch.device(device)
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    rc = lib.synth_gpu_normals(spec.seed, stream_id, i0, i0 + n, float(sigma), out.data_ptr(),
+                               stream)
+    if rc != 0:
+        raise RuntimeError(f"synth_gpu_normals failed ({rc})")
+    return out
+
+
+def device_x_true(spec: Spec, device="cuda:0"):
+    return device_normals(spec, 2, spec.n_cols, 1.0, device)
+
+
+def device_noise(spec: Spec, m: int, rhs: int = 0, device="cuda:0"):
+    return device_normals(spec, 3 + rhs, m, spec.noise_sigma, device)

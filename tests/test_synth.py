@@ -68,3 +68,19 @@ def test_reproducible_and_range_independent():
     assert np.array_equal(n1[r0:r1], synth.noise(sp, m, rhs=0, i0=r0, i1=r1))
     assert not np.array_equal(n1, synth.noise(sp, m, rhs=1))
     assert abs(np.std(synth.noise(synth.CONFIGS[0], 100_000)) - 1e-6) < 2e-8
+
+
+def test_generator_ln_exp_accuracy():
+    # the generator's own ln / exp (exact-operation builds shared with the
+    # GPU twin) agree with libm to a few ulps
+    import math
+
+    lib = synth._load()
+    rng = np.random.default_rng(0)
+    for x in np.concatenate([rng.uniform(1e-300, 1.0, 2000), rng.uniform(0.5, 2.0, 2000),
+                             [1.0, 0.5, 2.0 ** -1000, 0.7071067811865476, 1.4142135623730951]]):
+        got, want = lib.synth_test_ln(float(x)), math.log(x)
+        assert abs(got - want) <= 4e-16 * max(1.0, abs(want)), x
+    for x in np.concatenate([rng.uniform(-10, 10, 2000), [0.0, 1.0, -4.605170185988091]]):
+        got, want = lib.synth_test_exp(float(x)), math.exp(x)
+        assert abs(got - want) <= 4e-16 * want, x
