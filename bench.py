@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # algorithmic bytes per row and launch (FP64 values, configured index layout)
 BYTES_PER_ROW = {"aprod1": 24 * 8 + 40 + 16, "aprod2": 24 * 8 + 40 + 8}
+# FP32 values with FP32 work vectors (the inner solve of the refinement)
+BYTES_PER_ROW_F32 = {"aprod1": 24 * 4 + 40 + 8, "aprod2": 24 * 4 + 40 + 4}
 
 
 def log(*a):
@@ -58,6 +60,78 @@ def cpu_baseline(spec, sample_stars=20_000, itn=(1, 6)):
             "seconds": sum(t)}
 
 
+def rel_inf(a, b):
+    return float((a - b).abs().max() / b.abs().max())
+
+
+def refine_leg(cfg: int, dev):
+    """FP32 storage + FP64 refinement against the FP64 solve of the same
+    (FP32-stored) system, both to convergence at atol = btol = 1e-12."""
+    import torch
+
+    import synth
+    from paper_2308_00778_amd import LsqrSystem
+
+    spec = synth.CONFIGS[cfg]
+    t0 = time.perf_counter()
+    arrays, first = synth.device_system(spec, dev)
+    m = int(first[-1])
+    g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
+                   n_instr_cols=spec.n_instr_cols)
+    b = synth.device_noise(spec, m, 0, dev)
+    g.aprod1(synth.device_x_true(spec, dev), b)
+    torch.cuda.synchronize()
+    log(f"refine leg: m={m} n={g.n} ready in {time.perf_counter() - t0:.1f} s")
+    out = {"workload": f"{spec.n_stars} stars x {spec.obs_lo} obs = {m} rows x {g.n} unknowns, "
+                       f"FP32 values, astrometric column scale 10^U{spec.astro_scale}"}
+    # warm both paths (graph capture, lazy workspaces) on a short solve
+    g.solve(b, 2, atol=0.0, btol=0.0)
+    g.solve_refined(b, 2, atol=1e-6, btol=1e-6, outer_limit=1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x64, i64 = g.solve(b, 500, atol=1e-12, btol=1e-12)
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    x32, i32 = g.solve_refined(b, 200, atol=1e-6, btol=1e-6, outer_limit=10)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t2
+    # per-iteration kernel times of the FP32 inner loop
+    g.set_option("profile", 1)
+    g.solve_refined(b, 20, atol=0.0, btol=0.0, outer_limit=1)
+    kt = g.kernel_times()
+    g.set_option("profile", 0)
+    ms = {"aprod1": kt["aprod1_ms"] / max(1, kt["aprod1_n"]),
+          "aprod2": kt["aprod2_ms"] / max(1, kt["aprod2_n"])}
+    out.update({
+        "fp64_seconds": t_fp64, "fp64_itn": i64.itn, "fp64_istop": i64.istop,
+        "refined_seconds": t_ref, "refined_inner_itn": i32.itn,
+        "refined_outer_steps": i32.outer_steps, "speedup_vs_fp64": t_fp64 / t_ref,
+        "rel_inf_err_vs_fp64": rel_inf(x32, x64),
+        "inner_kernels": {k: {"ms": ms[k], "GBps": BYTES_PER_ROW_F32[k] * m / (ms[k] * 1e-3) / 1e9,
+                              "bytes_per_row": BYTES_PER_ROW_F32[k]} for k in ms},
+    })
+    log(f"refine leg: fp64 {t_fp64:.2f} s ({i64.itn} it), refined {t_ref:.2f} s "
+        f"({i32.itn} inner, {i32.outer_steps} outer), err {out['rel_inf_err_vs_fp64']:.2e}")
+    g.close()
+    del arrays, b, x64, x32
+    torch.cuda.empty_cache()
+    return out
+
+
+def copy_calibration(dev, gib: float = 4.0, reps: int = 5):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +139,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="refine",
+                    help="comma list of extra legs: refine (FP32 + FP64 refinement), none")
+    ap.add_argument("--copy", action="store_true", help="only run the copy calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding "
@@ -77,6 +154,9 @@ def main():
     from paper_2308_00778_amd import LsqrSystem
 
     dev = torch.device("cuda:0")
+    if args.copy:
+        copy_calibration(dev)
+        return
     spec = synth.CONFIGS[args.config]
     assert spec.value_dtype == "f64", "the FP64 bench runs on an FP64 workload"
     t0 = time.perf_counter()
@@ -144,8 +224,11 @@ def main():
         "solve_info": {"itn": info.itn, "istop": info.istop, "rnorm": info.rnorm},
     }
     g.close()
-    del arrays
+    del arrays, b, xt, x
     torch.cuda.empty_cache()
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    if "refine" in forms:
+        result["fp32_refine"] = refine_leg(2, dev)
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample ...")
         result["cpu_baseline"] = cpu_baseline(spec)

@@ -112,6 +112,17 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         read back with lsqr_kernel_times
  *   LSQR_OPT_OUTER_TOL    refinement: stop when ||d||_inf <= tol ||x||_inf
  *                         (default 1e-10)
+ *   LSQR_OPT_ATT_MODE     attitude part of aprod2: 0 (default) scatter-add with
+ *                         device atomics; 1 a second pass over the rows sorted
+ *                         by attitude start (segmented sums, no atomics; costs
+ *                         a sorted copy of the 12 attitude coefficients and two
+ *                         int32 per row, built on first use, n_rows < 2^31)
+ *   LSQR_OPT_ASTRO_SCAN   astrometric part of aprod2: 1 (default) segmented scan
+ *                         per 64-row chunk; 0 running per-lane partials reduced
+ *                         only where a star ends
+ *   LSQR_OPT_KTILE        batched solves: right-hand sides advanced together per
+ *                         pass over A (1, 2, 4, 8), 0 (default) = autotune once
+ *                         per handle
  */
 #define LSQR_OPT_CONLIM 1
 #define LSQR_OPT_TESTS 2
@@ -119,6 +130,9 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_GRAPH 4
 #define LSQR_OPT_PROFILE 5
 #define LSQR_OPT_OUTER_TOL 6
+#define LSQR_OPT_ATT_MODE 7
+#define LSQR_OPT_ASTRO_SCAN 8
+#define LSQR_OPT_KTILE 9
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
 
 /* aprod mode 1, Eq. (2): y[m] += A x[n] with the raw (unscaled) A.
@@ -154,6 +168,24 @@ lsqr_status lsqr_solve(lsqr_handle* h, const double* b, double* x, int32_t itn_l
  * ||b - A x||), info->bnorm is ||b||. Synchronous; info may be NULL. */
 lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32_t itn_limit,
                                double atol, double btol, int32_t outer_limit, lsqr_info* info);
+
+/* k right-hand sides at once (noise realisations of b for Monte Carlo error
+ * propagation). B: FP64 [m][k] row-interleaved (B[i*k + j] is row i of RHS j),
+ * X: FP64 [n][k] output likewise. The RHS are advanced in k-tiles of K (the
+ * LSQR_OPT_KTILE option or the autotuner's choice): each pass over A serves K
+ * RHS (an SpMM), every RHS keeps its own scalars and stopping tests, and a
+ * RHS that has stopped is frozen (its x, w, v, u and estimates no longer
+ * change) while the others continue. Each x[:, j] is the result lsqr_solve
+ * would give for b[:, j] up to rounding order. infos: host array of k
+ * results (may be NULL); outer_steps is 0. Needs LSQR_OPT_ATT_MODE 0.
+ * Synchronous. */
+lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32_t k,
+                               int32_t itn_limit, double atol, double btol, lsqr_info* infos);
+
+/* Autotuner result of this handle: the chosen k-tile (0 if not tuned yet) and
+ * the measured milliseconds per RHS-iteration for K = 1, 2, 4, 8 (4 host
+ * doubles, 0 where not measured). Host pointers; either may be NULL. */
+lsqr_status lsqr_batch_tuning(lsqr_handle* h, int32_t* k_tile, double* ms_per_rhs_iter);
 
 /* Per-kernel timing of the last solve run with LSQR_OPT_PROFILE = 1:
  * total milliseconds and launch counts of the aprod1 and aprod2 kernels.

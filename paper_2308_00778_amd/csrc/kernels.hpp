@@ -234,13 +234,93 @@ __device__ __forceinline__ void seg_scan5(int64_t key, Acc (&v)[kAstro], int lan
     }
 }
 
+// Wave-wide sum, result in every lane.
+template <typename Acc>
+__device__ __forceinline__ Acc wave_sum(Acc v)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Reduction of NV values per row over segments of equal, non-decreasing keys,
+// one 64-row chunk at a time. Each lane keeps running partials of the segment
+// that is still open at the end of the previous chunk; cross-lane work
+// happens only where a segment ends (a wave sum per finished segment), so a
+// segment longer than a chunk costs one vector add per lane per chunk.
+// Invalid lanes (past the end of the range) carry key kNoStar.
+template <typename Acc, int NV>
+struct SegAcc {
+    int64_t key = -1;  // open segment (wave-uniform), -1: none
+    Acc acc[NV];
+    __device__ SegAcc()
+    {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] = (Acc)0;
+    }
+};
+
+// emit(key, totals) runs on lane 0 once per finished segment.
+template <typename Acc, int NV, typename Emit>
+__device__ __forceinline__ void seg_chunk(SegAcc<Acc, NV>& S, int64_t key, const Acc (&v)[NV],
+                                          int lane, Emit&& emit)
+{
+    const bool cont = key == S.key;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) S.acc[j] += cont ? v[j] : (Acc)0;
+    uint64_t rest = __ballot(!cont);
+    if (rest == 0) return;  // the whole chunk continues the open segment
+    if (S.key >= 0) {       // keys are sorted: the open segment ends here
+        Acc t[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) t[j] = wave_sum(S.acc[j]);
+        if (lane == 0) emit(S.key, t);
+    }
+    S.key = -1;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) S.acc[j] = (Acc)0;
+    while (rest != 0) {
+        const int l0 = __ffsll((unsigned long long)rest) - 1;
+        const int64_t k2 = __shfl(key, l0);
+        if (k2 == kNoStar) break;  // only lanes past the end remain
+        const bool mine = key == k2;
+        const uint64_t same = __ballot(mine);
+        if ((same >> (kWave - 1)) & 1ull) {  // reaches the last lane: stays open
+            S.key = k2;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) S.acc[j] = mine ? v[j] : (Acc)0;
+            break;
+        }
+        Acc t[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) t[j] = wave_sum(mine ? v[j] : (Acc)0);
+        if (lane == 0) emit(k2, t);
+        rest &= ~same;
+    }
+}
+
+template <typename Acc, int NV, typename Emit>
+__device__ __forceinline__ void seg_finish(SegAcc<Acc, NV>& S, int lane, Emit&& emit)
+{
+    if (S.key < 0) return;
+    Acc t[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) t[j] = wave_sum(S.acc[j]);
+    if (lane == 0) emit(S.key, t);
+    S.key = -1;
+}
+
 // x += A^T y (SQUARE: x_j += sum of squared coefficients of column j, used
 // for the column norms). wb: star-aligned row boundaries, one range per wave
 // (gridDim.x * kWavesPerBlock ranges). The instrumental columns are
 // accumulated in LDS when lds_instr != 0 (n_instr_cols * sizeof(Acc) bytes of
 // dynamic shared memory), else by device atomics. gpart[blockIdx.x] gets the
 // workgroup's global-column partial; k_glob_sum adds them up.
-template <typename T, typename Acc, typename VU, bool SQUARE>
+// ATT = false leaves the attitude columns to the row-reordered pass
+// (k_aprod2_att_sorted) and skips loading them. SCAN selects the astrometric
+// reduction: a segmented scan every chunk (true) or the accumulate-and-flush
+// segments of seg_chunk (false).
+template <typename T, typename Acc, typename VU, bool SQUARE, bool ATT = true, bool SCAN = true>
 __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const VU* __restrict__ u,
                                                     Acc* __restrict__ q,
                                                     const int64_t* __restrict__ wb,
@@ -271,16 +351,22 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const VU* __restri
 #pragma unroll
     for (int j = 0; j < kAstro; ++j) carry[j] = (Acc)0;
     Acc gsum = (Acc)0;
+    SegAcc<Acc, kAstro> seg;
+    auto astro_emit = [q](int64_t star, const Acc (&tot)[kAstro]) {
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j) q[kAstro * star + j] += tot[j];
+    };
 
     for (int64_t r0 = rb; r0 < re; r0 += kWave) {
         const int64_t i = r0 + lane;
         const bool ok = i < re;
         const int64_t ic = ok ? i : re - 1;
         const int64_t st = ok ? ldnt(&s.star[ic]) : kNoStar;
-        const int64_t t = ldnt(&s.att[ic]);
+        const int64_t t = ATT ? ldnt(&s.att[ic]) : 0;
         T a[kPar];
 #pragma unroll
-        for (int c = 0; c < kPar; ++c) a[c] = ldnt(&val[c * m + ic]);
+        for (int c = 0; c < kPar; ++c)
+            a[c] = (ATT || c < kOffAtt || c >= kOffInstr) ? ldnt(&val[c * m + ic]) : (T)0;
         int32_t ix[kInstr];
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
@@ -294,12 +380,14 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const VU* __restri
 
         // attitude: 3 axes x 4 consecutive columns from the row's start t
         if (ok) {
+            if (ATT) {
 #pragma unroll
-            for (int ax = 0; ax < kAxes; ++ax) {
-                Acc* dst = qatt + ax * s.n_dfa + t;
+                for (int ax = 0; ax < kAxes; ++ax) {
+                    Acc* dst = qatt + ax * s.n_dfa + t;
 #pragma unroll
-                for (int qq = 0; qq < kParAxis; ++qq)
-                    atomicAdd(dst + qq, contrib[kOffAtt + ax * kParAxis + qq]);
+                    for (int qq = 0; qq < kParAxis; ++qq)
+                        atomicAdd(dst + qq, contrib[kOffAtt + ax * kParAxis + qq]);
+                }
             }
             // instrumental
 #pragma unroll
@@ -314,6 +402,10 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const VU* __restri
         Acc pa[kAstro];
 #pragma unroll
         for (int j = 0; j < kAstro; ++j) pa[j] = contrib[j];
+        if (!SCAN) {
+            seg_chunk(seg, st, pa, lane, astro_emit);
+            continue;
+        }
         if (carry_star >= 0) {
             const int64_t st0 = __shfl(st, 0);
             if (lane == 0) {
@@ -341,6 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const VU* __restri
 #pragma unroll
         for (int j = 0; j < kAstro; ++j) q[kAstro * carry_star + j] += carry[j];
     }
+    if (!SCAN) seg_finish(seg, lane, astro_emit);
 
     // global column: wave shuffle -> LDS -> one partial per workgroup
 #pragma unroll
@@ -685,7 +778,8 @@ __global__ __launch_bounds__(kBlock) void k_validate(SysView s, int32_t* __restr
 
 // Star-aligned row boundaries: range g starts at the first star boundary at
 // or after g*m/nw, so that no star is split between two waves.
-__global__ __launch_bounds__(kBlock) void k_wave_bounds(const int64_t* __restrict__ star,
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_wave_bounds(const K* __restrict__ star,
                                                          int64_t m, int64_t nw,
                                                          int64_t* __restrict__ wb)
 {
@@ -713,4 +807,636 @@ __global__ __launch_bounds__(kBlock) void k_make_p(int64_t n, double* __restrict
     }
 }
 
+// ----------------------------------------------- row-reordered attitude
+// Rows sorted by their attitude start t (a stable radix sort at set-up) turn
+// the attitude scatter into a segmented reduction: every row with the same t
+// contributes to the same 3 x 4 columns.
+__global__ __launch_bounds__(kBlock) void k_att_keys(const int64_t* __restrict__ att, int64_t m,
+                                                      int32_t* __restrict__ keys,
+                                                      int32_t* __restrict__ rows)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kBlock) {
+        keys[i] = (int32_t)att[i];
+        rows[i] = (int32_t)i;
+    }
+}
+
+// att_sorted[c][k] = values[kOffAtt + c][perm[k]], c < 12
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val, int64_t m,
+                                                        const int32_t* __restrict__ perm,
+                                                        T* __restrict__ att_sorted)
+{
+    constexpr int kAtt = kAxes * kParAxis;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = perm[k];
+#pragma unroll
+        for (int c = 0; c < kAtt; ++c) att_sorted[c * m + k] = val[(kOffAtt + c) * m + i];
+    }
+}
+
+// S[t][12] = sum over rows with attitude start t of a_att * u, over t-aligned
+// per-wave ranges of the sorted rows (each t owned by one wave: plain stores).
+template <typename T, typename Acc, typename VU>
+__global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
+    int64_t m, const T* __restrict__ att_sorted, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ tkey, const VU* __restrict__ u, Acc* __restrict__ S,
+    const int64_t* __restrict__ wb, const Scalars* __restrict__ sc)
+{
+    constexpr int kAtt = kAxes * kParAxis;
+    if (sc != nullptr && (sc->done || sc->beta_zero)) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t rb = wb[wave], re = wb[wave + 1];
+    SegAcc<Acc, kAtt> seg;
+    auto emit = [S](int64_t t, const Acc (&tot)[kAtt]) {
+#pragma unroll
+        for (int j = 0; j < kAtt; ++j) S[t * kAtt + j] = tot[j];
+    };
+    for (int64_t r0 = rb; r0 < re; r0 += kWave) {
+        const int64_t k = r0 + lane;
+        const bool ok = k < re;
+        const int64_t kc = ok ? k : re - 1;
+        const int64_t t = ok ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
+        const int32_t i = ldnt(&perm[kc]);
+        const Acc ui = ok ? (Acc)u[i] : (Acc)0;
+        Acc v[kAtt];
+#pragma unroll
+        for (int c = 0; c < kAtt; ++c) v[c] = (Acc)ldnt(&att_sorted[c * m + kc]) * ui;
+        seg_chunk(seg, t, v, lane, emit);
+    }
+    seg_finish(seg, lane, emit);
+}
+
+// q[att_base + a n_dfa + c] += sum_q S[c - q][a][q] over valid starts.
+template <typename Acc>
+__global__ __launch_bounds__(kBlock) void k_att_combine(const Acc* __restrict__ S, int64_t n_dfa,
+                                                         Acc* __restrict__ qatt,
+                                                         const Scalars* __restrict__ sc)
+{
+    constexpr int kAtt = kAxes * kParAxis;
+    if (sc != nullptr && (sc->done || sc->beta_zero)) return;
+    const int64_t nt = n_dfa - kParAxis + 1;  // valid starts 0 .. nt-1
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < kAxes * n_dfa;
+         j += (int64_t)gridDim.x * kBlock) {
+        const int64_t ax = j / n_dfa, c = j - ax * n_dfa;
+        Acc sum = (Acc)0;
+#pragma unroll
+        for (int qq = 0; qq < kParAxis; ++qq) {
+            const int64_t t = c - qq;
+            if (t >= 0 && t < nt) sum += S[t * kAtt + ax * kParAxis + qq];
+        }
+        qatt[j] += sum;
+    }
+}
+
+// ====================================================== batched right-hand sides
+// K right-hand sides advance together: one row per lane, K values per lane,
+// so every coefficient and index of A is read once per K RHS (an SpMM).
+// Layouts of one k-tile: U [m][K] (row-interleaved), column vectors [n][K].
+// sc points at the tile's K Scalars; a RHS with sc[r].done set is frozen:
+// no kernel changes its vectors or scalars any more.
+namespace batched {
+
+// Running masks: bit r set when RHS r is still iterating.
+template <int K>
+__device__ __forceinline__ uint32_t live_mask(const Scalars* __restrict__ sc)
+{
+    uint32_t mk = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) mk |= (sc[r].done ? 0u : 1u) << r;
+    return mk;
+}
+
+// K-wide gather of a column vector row [n][K].
+template <typename V, int K>
+__device__ __forceinline__ void load_k(const V* __restrict__ p, V (&out)[K])
+{
+#pragma unroll
+    for (int r = 0; r < K; ++r) out[r] = p[r];
+}
+
+// Deterministic block sums of K doubles per thread into part[blk*K + r].
+template <int K>
+__device__ __forceinline__ void block_sums_k(double (&v)[K], double* __restrict__ part,
+                                             double* lds /* >= K * kWavesPerBlock */)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v[r] += __shfl_down(v[r], off);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int r = 0; r < K; ++r) lds[r * kWavesPerBlock + w] = v[r];
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double s = 0.0;
+        for (int k = 0; k < kWavesPerBlock; ++k) s += lds[threadIdx.x * kWavesPerBlock + k];
+        part[(int64_t)blockIdx.x * K + threadIdx.x] = s;
+    }
+}
+
+// U[i][r] = B[i][r] (B row stride ldb), FP64 sums of squares per RHS.
+template <typename VU, int K>
+__global__ __launch_bounds__(kBlock) void k_copy_ssq(int64_t m, const double* __restrict__ B,
+                                                      int64_t ldb, VU* __restrict__ U,
+                                                      double* __restrict__ part)
+{
+    __shared__ double red[K * kWavesPerBlock];
+    double ssq[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) ssq[r] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const VU v = (VU)B[i * ldb + r];
+            U[i * K + r] = v;
+            ssq[r] += (double)v * (double)v;
+        }
+    }
+    block_sums_k<K>(ssq, part, red);
+}
+
+// U = A VP - coef_r U per live RHS; sums of squares of the new U per RHS.
+template <typename T, typename Acc, int K>
+__global__ __launch_bounds__(kBlock) void k_aprod1(SysView s, const Acc* __restrict__ VP,
+                                                    Acc* __restrict__ U,
+                                                    const Scalars* __restrict__ sc,
+                                                    double* __restrict__ part)
+{
+    __shared__ double red[K * kWavesPerBlock];
+    const uint32_t live = live_mask<K>(sc);
+    if (live == 0) return;
+    Acc coef[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) coef[r] = (Acc)sc[r].coef_u;
+    const T* __restrict__ val = static_cast<const T*>(s.val);
+    const int64_t m = s.m;
+    double ssq[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) ssq[r] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int64_t st = ldnt(&s.star[i]);
+        const int64_t t = ldnt(&s.att[i]);
+        T a[kPar];
+#pragma unroll
+        for (int c = 0; c < kPar; ++c) a[c] = ldnt(&val[c * m + i]);
+        int32_t ic[kInstr];
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) ic[j] = ldnt(&s.instr[j * m + i]);
+        Acc sum[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) sum[r] = (Acc)0;
+        Acc xv[K];
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j) {
+            load_k<Acc, K>(VP + (kAstro * st + j) * K, xv);
+#pragma unroll
+            for (int r = 0; r < K; ++r) sum[r] += (Acc)a[j] * xv[r];
+        }
+#pragma unroll
+        for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+            for (int qq = 0; qq < kParAxis; ++qq) {
+                load_k<Acc, K>(VP + (s.att_base + ax * s.n_dfa + t + qq) * K, xv);
+#pragma unroll
+                for (int r = 0; r < K; ++r) sum[r] += (Acc)a[kOffAtt + ax * kParAxis + qq] * xv[r];
+            }
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) {
+            load_k<Acc, K>(VP + (s.instr_base + ic[j]) * K, xv);
+#pragma unroll
+            for (int r = 0; r < K; ++r) sum[r] += (Acc)a[kOffInstr + j] * xv[r];
+        }
+        load_k<Acc, K>(VP + s.glob_base * K, xv);
+#pragma unroll
+        for (int r = 0; r < K; ++r) sum[r] += (Acc)a[kOffGlob] * xv[r];
+        Acc* u = U + i * K;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            if (!((live >> r) & 1u)) continue;
+            const Acc nu = sum[r] - coef[r] * u[r];
+            u[r] = nu;
+            ssq[r] += (double)nu * (double)nu;
+        }
+    }
+    block_sums_k<K>(ssq, part, red);
+}
+
+// Q += A^T U over star-aligned per-wave ranges (astrometric: accumulate-and-
+// flush segments, attitude: device atomics, instrumental: LDS histogram
+// [n_instr_cols][K] when lds_instr, else device atomics, global: partials
+// gpart[blk][K]). Frozen RHS contribute nothing.
+template <typename T, typename Acc, int K>
+__global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const Acc* __restrict__ U,
+                                                    Acc* __restrict__ Q,
+                                                    const int64_t* __restrict__ wb,
+                                                    Acc* __restrict__ gpart, int lds_instr,
+                                                    const Scalars* __restrict__ sc)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Acc* lds = reinterpret_cast<Acc*>(smem_raw);
+    __shared__ Acc gred[K * kWavesPerBlock];
+    uint32_t live = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) live |= ((sc[r].done || sc[r].beta_zero) ? 0u : 1u) << r;
+    if (live == 0) return;
+    const T* __restrict__ val = static_cast<const T*>(s.val);
+    const int64_t m = s.m;
+    const int64_t ninst = s.n_instr_cols;
+    if (lds_instr) {
+        for (int64_t j = threadIdx.x; j < ninst * K; j += kBlock) lds[j] = (Acc)0;
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t rb = wb[wave], re = wb[wave + 1];
+    Acc* __restrict__ qatt = Q + s.att_base * K;
+    Acc* __restrict__ qins = Q + s.instr_base * K;
+    Acc gsum[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) gsum[r] = (Acc)0;
+    SegAcc<Acc, kAstro * K> seg;
+    auto astro_emit = [Q](int64_t star, const Acc (&tot)[kAstro * K]) {
+        Acc* dst = Q + kAstro * star * K;
+#pragma unroll
+        for (int j = 0; j < kAstro * K; ++j) dst[j] += tot[j];
+    };
+    for (int64_t r0 = rb; r0 < re; r0 += kWave) {
+        const int64_t i = r0 + lane;
+        const bool ok = i < re;
+        const int64_t ic = ok ? i : re - 1;
+        const int64_t st = ok ? ldnt(&s.star[ic]) : kNoStar;
+        const int64_t t = ldnt(&s.att[ic]);
+        T a[kPar];
+#pragma unroll
+        for (int c = 0; c < kPar; ++c) a[c] = ldnt(&val[c * m + ic]);
+        int32_t ix[kInstr];
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
+        Acc u[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) u[r] = (ok && ((live >> r) & 1u)) ? U[ic * K + r] : (Acc)0;
+
+        if (ok) {
+#pragma unroll
+            for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+                for (int qq = 0; qq < kParAxis; ++qq) {
+                    Acc* dst = qatt + (ax * s.n_dfa + t + qq) * K;
+                    const Acc av = (Acc)a[kOffAtt + ax * kParAxis + qq];
+#pragma unroll
+                    for (int r = 0; r < K; ++r)
+                        if ((live >> r) & 1u) atomicAdd(dst + r, av * u[r]);
+                }
+#pragma unroll
+            for (int j = 0; j < kInstr; ++j) {
+                const Acc av = (Acc)a[kOffInstr + j];
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    if (!((live >> r) & 1u)) continue;
+                    if (lds_instr) atomicAdd(&lds[ix[j] * K + r], av * u[r]);
+                    else atomicAdd(&qins[ix[j] * K + r], av * u[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < K; ++r) gsum[r] += (Acc)a[kOffGlob] * u[r];
+        Acc pa[kAstro * K];
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j)
+#pragma unroll
+            for (int r = 0; r < K; ++r) pa[j * K + r] = (Acc)a[j] * u[r];
+        seg_chunk(seg, st, pa, lane, astro_emit);
+    }
+    seg_finish(seg, lane, astro_emit);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) gsum[r] += __shfl_down(gsum[r], off);
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int r = 0; r < K; ++r) gred[r * kWavesPerBlock + threadIdx.x / kWave] = gsum[r];
+    __syncthreads();
+    if (threadIdx.x < K) {
+        Acc g = (Acc)0;
+        for (int k = 0; k < kWavesPerBlock; ++k) g += gred[threadIdx.x * kWavesPerBlock + k];
+        gpart[(int64_t)blockIdx.x * K + threadIdx.x] = g;
+    }
+    if (lds_instr) {
+        for (int64_t j = threadIdx.x; j < ninst * K; j += kBlock) {
+            const Acc v = lds[j];
+            if (v != (Acc)0) atomicAdd(&qins[j], v);
+        }
+    }
+}
+
+template <typename Acc, int K>
+__global__ __launch_bounds__(kBlock) void k_glob_sum(const Acc* __restrict__ gpart, int nblk,
+                                                      Acc* __restrict__ qglob,
+                                                      const Scalars* __restrict__ sc)
+{
+    __shared__ double red[kWavesPerBlock];
+    for (int r = 0; r < K; ++r) {
+        if (sc[r].done || sc[r].beta_zero) continue;  // uniform over the block
+        double v = 0.0;
+        for (int k = threadIdx.x; k < nblk; k += kBlock) v += (double)gpart[(int64_t)k * K + r];
+        const double tot = block_sum(v, red);
+        if (threadIdx.x == 0) qglob[r] = (Acc)((double)qglob[r] + tot);
+    }
+}
+
+// V~ = p Q / beta_r - beta_r V ; Q = 0 ; alpha^2 partials per RHS.
+template <typename Acc, int K>
+__global__ __launch_bounds__(kBlock) void k_col_a(int64_t n, const double* __restrict__ p,
+                                                   Acc* __restrict__ Q, double* __restrict__ V,
+                                                   const Scalars* __restrict__ sc,
+                                                   double* __restrict__ part)
+{
+    __shared__ double red[K * kWavesPerBlock];
+    double beta[K], ib[K], ssq[K];
+    uint32_t act = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        beta[r] = sc[r].beta;
+        ib[r] = beta[r] > 0.0 ? 1.0 / beta[r] : 0.0;
+        ssq[r] = 0.0;
+        act |= ((sc[r].done || sc[r].beta_zero) ? 0u : 1u) << r;
+    }
+    if (act == 0) return;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * kBlock) {
+        const double pj = p[j];
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            if (!((act >> r) & 1u)) continue;
+            const double qj = (double)Q[j * K + r];
+            Q[j * K + r] = (Acc)0;
+            const double vt = pj * qj * ib[r] - beta[r] * V[j * K + r];
+            V[j * K + r] = vt;
+            ssq[r] += vt * vt;
+        }
+    }
+    block_sums_k<K>(ssq, part, red);
+}
+
+template <typename VP, int K>
+__global__ __launch_bounds__(kBlock) void k_col_b(int64_t n, const double* __restrict__ p,
+                                                   double* __restrict__ V, double* __restrict__ W,
+                                                   double* __restrict__ Y, VP* __restrict__ VPv,
+                                                   const Scalars* __restrict__ sc,
+                                                   double* __restrict__ part_dd,
+                                                   double* __restrict__ part_xx)
+{
+    __shared__ double red[K * kWavesPerBlock];
+    double ia[K], t1[K], t2[K], ir[K], dd[K], xx[K];
+    uint32_t act = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        ia[r] = sc[r].beta_zero ? 1.0 : sc[r].inv_alpha;
+        t1[r] = sc[r].t1;
+        t2[r] = sc[r].t2;
+        ir[r] = 1.0 / sc[r].rho;
+        dd[r] = 0.0;
+        xx[r] = 0.0;
+        act |= (sc[r].done ? 0u : 1u) << r;
+    }
+    if (act == 0) return;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * kBlock) {
+        const double pj = p[j];
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            if (!((act >> r) & 1u)) continue;
+            const int64_t o = j * K + r;
+            const double vj = V[o] * ia[r];
+            V[o] = vj;
+            VPv[o] = (VP)(pj * vj);
+            const double wj = W[o];
+            const double dk = wj * ir[r];
+            dd[r] += dk * dk;
+            const double yj = Y[o] + t1[r] * wj;
+            Y[o] = yj;
+            xx[r] += yj * yj;
+            W[o] = vj + t2[r] * wj;
+        }
+    }
+    block_sums_k<K>(dd, part_dd, red);
+    block_sums_k<K>(xx, part_xx, red);
+}
+
+template <typename VP, int K>
+__global__ __launch_bounds__(kBlock) void k_col_init(int64_t n, const double* __restrict__ p,
+                                                      double* __restrict__ V,
+                                                      double* __restrict__ W,
+                                                      double* __restrict__ Y,
+                                                      VP* __restrict__ VPv,
+                                                      const Scalars* __restrict__ sc)
+{
+    double ia[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) ia[r] = sc[r].inv_alpha;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * kBlock) {
+        const double pj = p[j];
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const int64_t o = j * K + r;
+            const double vj = V[o] * ia[r];
+            V[o] = vj;
+            W[o] = vj;
+            VPv[o] = (VP)(pj * vj);
+            Y[o] = 0.0;
+        }
+    }
+}
+
+// X[j][r] (row stride ldx) = p_j Y[j][r]
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_unprecond(int64_t n, const double* __restrict__ p,
+                                                       const double* __restrict__ Y,
+                                                       double* __restrict__ X, int64_t ldx)
+{
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * kBlock) {
+        const double pj = p[j];
+#pragma unroll
+        for (int r = 0; r < K; ++r) X[j * ldx + r] = pj * Y[j * K + r];
+    }
+}
+
+// Sum of column r of part[nblk][K], one block, fixed order; thread 0.
+template <int K>
+__device__ __forceinline__ double sum_col(const double* part, int nblk, int r, double* lds)
+{
+    double v = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += kBlock) v += part[(int64_t)k * K + r];
+    return block_sum(v, lds);
+}
+
+// The single-RHS scalar steps applied per RHS. Each kernel loops over the K
+// RHS of the tile (uniformly over the block) and skips frozen ones.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_scalar_init_beta(const double* __restrict__ part,
+                                                              int nblk, Scalars* __restrict__ sc)
+{
+    __shared__ double red[kWavesPerBlock];
+    for (int r = 0; r < K; ++r) {
+        const double ssq = sum_col<K>(part, nblk, r, red);
+        if (threadIdx.x == 0) {
+            Scalars& s = sc[r];
+            const double beta = sqrt(ssq);
+            s.beta = beta;
+            s.bnorm = beta;
+            s.alpha = s.anorm = s.ddnorm = s.acond = s.xnorm = s.arnorm = 0.0;
+            s.rnorm = beta;
+            s.inv_alpha = 1.0;
+            s.itn = 0;
+            s.istop = 0;
+            s.beta_zero = 0;
+            s.done = beta > 0.0 ? 0 : 1;
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_scalar_init_alpha(const double* __restrict__ part,
+                                                               int nblk, Scalars* __restrict__ sc)
+{
+    __shared__ double red[kWavesPerBlock];
+    for (int r = 0; r < K; ++r) {
+        const double ssq = sum_col<K>(part, nblk, r, red);
+        if (threadIdx.x == 0 && !sc[r].done) {
+            Scalars& s = sc[r];
+            const double alpha = sqrt(ssq);
+            s.alpha = alpha;
+            s.rhobar = alpha;
+            s.phibar = s.beta;
+            s.arnorm = alpha * s.beta;
+            s.inv_alpha = alpha > 0.0 ? 1.0 / alpha : 1.0;
+            s.coef_u = alpha / s.beta;
+            if (s.arnorm == 0.0) s.done = 1;
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_scalar_beta(const double* __restrict__ part, int nblk,
+                                                         Scalars* __restrict__ sc)
+{
+    __shared__ double red[kWavesPerBlock];
+    for (int r = 0; r < K; ++r) {
+        if (sc[r].done) continue;
+        const double ssq = sum_col<K>(part, nblk, r, red);
+        if (threadIdx.x == 0) {
+            Scalars& s = sc[r];
+            const double beta = sqrt(ssq);
+            s.beta = beta;
+            if (beta > 0.0) {
+                s.anorm = sqrt(s.anorm * s.anorm + s.alpha * s.alpha + beta * beta);
+                s.beta_zero = 0;
+            } else {
+                s.beta_zero = 1;
+            }
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_scalar_alpha(const double* __restrict__ part,
+                                                          int nblk, Scalars* __restrict__ sc)
+{
+    __shared__ double red[kWavesPerBlock];
+    for (int r = 0; r < K; ++r) {
+        if (sc[r].done) continue;
+        const double ssq = sum_col<K>(part, nblk, r, red);
+        if (threadIdx.x == 0) {
+            Scalars& s = sc[r];
+            double alpha = s.alpha;
+            if (!s.beta_zero) alpha = sqrt(ssq);
+            const double beta = s.beta;
+            const double rho = sqrt(s.rhobar * s.rhobar + beta * beta);
+            const double c = s.rhobar / rho;
+            const double sn = beta / rho;
+            const double theta = sn * alpha;
+            const double phi = c * s.phibar;
+            s.alpha = alpha;
+            s.rho = rho;
+            s.c = c;
+            s.s = sn;
+            s.theta = theta;
+            s.rhobar = -c * alpha;
+            s.phi = phi;
+            s.phibar = sn * s.phibar;
+            s.t1 = phi / rho;
+            s.t2 = -theta / rho;
+            s.inv_alpha = alpha > 0.0 ? 1.0 / alpha : 1.0;
+            s.coef_u = beta > 0.0 ? alpha / beta : 0.0;
+            s.rnorm = s.phibar;
+            s.arnorm = alpha * fabs(c) * s.phibar;
+        }
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_scalar_stop(const double* __restrict__ part_dd,
+                                                         const double* __restrict__ part_xx,
+                                                         int nblk, Scalars* __restrict__ sc)
+{
+    __shared__ double red[kWavesPerBlock];
+    for (int r = 0; r < K; ++r) {
+        if (sc[r].done) continue;
+        const double dd = sum_col<K>(part_dd, nblk, r, red);
+        const double xx = sum_col<K>(part_xx, nblk, r, red);
+        if (threadIdx.x == 0) {
+            Scalars& s = sc[r];
+            const double ddnorm = s.ddnorm + dd;
+            const double xnorm = sqrt(xx);
+            const double anorm = s.anorm;
+            const double acond = anorm * sqrt(ddnorm);
+            const double rnorm = s.rnorm, arnorm = s.arnorm, bnorm = s.bnorm;
+            s.ddnorm = ddnorm;
+            s.xnorm = xnorm;
+            s.acond = acond;
+            const int32_t itn = s.itn + 1;
+            s.itn = itn;
+            const double test1 = rnorm / bnorm;
+            const double test2 = (anorm * rnorm) > 0.0 ? arnorm / (anorm * rnorm) : 0.0;
+            const double test3 = acond > 0.0 ? 1.0 / acond : 0.0;
+            const double t1 = test1 / (1.0 + anorm * xnorm / bnorm);
+            const double rtol = s.btol + s.atol * anorm * xnorm / bnorm;
+            int32_t istop = 0;
+            if (itn >= s.itn_limit) istop = 7;
+            if (s.tests) {
+                if (1.0 + test3 <= 1.0) istop = 6;
+                if (1.0 + test2 <= 1.0) istop = 5;
+                if (1.0 + t1 <= 1.0) istop = 4;
+                if (test3 <= s.ctol) istop = 3;
+                if (test2 <= s.atol) istop = 2;
+                if (test1 <= rtol) istop = 1;
+            }
+            s.istop = istop;
+            if (istop != 0) s.done = 1;
+        }
+    }
+}
+
+// Tile-wide flag for the host: 1 when every RHS of the tile is done.
+template <int K>
+__global__ void k_all_done(Scalars* __restrict__ sc, int32_t* __restrict__ flag)
+{
+    if (threadIdx.x != 0) return;
+    int32_t all = 1;
+    for (int r = 0; r < K; ++r) all &= sc[r].done ? 1 : 0;
+    *flag = all;
+}
+
+}  // namespace batched
 }  // namespace avugsr

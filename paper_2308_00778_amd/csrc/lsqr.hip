@@ -20,6 +20,7 @@
 // finished solve leaves a `done` flag that makes the rest of the chunk a
 // sequence of empty kernels. The host reads one flag per chunk.
 #include <hip/hip_runtime.h>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cstdarg>
@@ -96,6 +97,7 @@ struct Path {
     Acc* vp = nullptr;     // [n] p .* v, gathered by aprod1
     Acc* q = nullptr;      // [n] aprod2 accumulator (zero between uses)
     Acc* gpart = nullptr;  // [nb2] global-column partials
+    Acc* S = nullptr;      // [(n_dfa-3)*12] attitude partials of the reordered pass
     size_t lds = 0;        // dynamic LDS bytes of aprod2
     int lds_instr = 0;
     hipGraphExec_t graph = nullptr;
@@ -135,13 +137,38 @@ struct lsqr_handle {
     Path<double> p64;
     Path<float> p32;
 
+    // row-reordered attitude pass (built on first use)
+    int32_t* perm = nullptr;      // [m] rows sorted by attitude start
+    int32_t* tkey = nullptr;      // [m] attitude start of each sorted row
+    void* att_sorted = nullptr;   // [12][m] attitude coefficients in sorted order
+    int64_t* wb_att = nullptr;    // [nb2*4 + 1] t-aligned ranges of the sorted rows
+    double* S_raw = nullptr;      // [(n_dfa-3)*12] partials of lsqr_aprod2
+    bool att_ready = false;
+
+    // batched right-hand sides (tile buffers for the largest K, reused per tile)
+    struct Batch {
+        int kmax = 0;
+        double *U = nullptr, *V = nullptr, *W = nullptr, *Y = nullptr, *VP = nullptr, *Q = nullptr;
+        double *gpart = nullptr, *part1 = nullptr, *partc = nullptr, *partdd = nullptr,
+               *partxx = nullptr;
+        Scalars* sc = nullptr;
+        int32_t* flag = nullptr;
+        hipGraphExec_t graph[9] = {};  // by K
+        int graph_chunk[9] = {};
+        int tuned_k = 0;               // autotuner's choice for this handle
+        double tuned_ms[9] = {};       // measured ms per RHS-iteration by K
+    } batch;
+
     // options
     double conlim = 1e8;
     int tests = 1;
     int chunk = 16;
     int use_graph = 1;
     int profile = 0;
+    int att_mode = 0;    // 0: attitude scatter with device atomics, 1: row-reordered pass
+    int astro_scan = 1;  // 1: segmented scan per chunk, 0: accumulate-and-flush segments
     double outer_tol = 1e-10;
+    int ktile = 0;       // batched k-tile: 0 autotune, else 1, 2, 4 or 8
 
     // profiling
     std::vector<hipEvent_t> events;
@@ -152,14 +179,37 @@ struct lsqr_handle {
 namespace {
 
 // ------------------------------------------------------------ launch helpers
+// q += A^T u for the LSQR loop (and lsqr_aprod2): the main pass over the rows
+// in star order, the global-column second stage and, in the row-reordered
+// attitude mode, the attitude pass over the t-sorted rows.
 template <typename T, typename Acc>
-lsqr_status launch_aprod2_lsqr(lsqr_handle* h, Path<Acc>& P, hipStream_t st)
+void launch_aprod2(lsqr_handle* h, const Acc* u, Acc* q, Acc* gpart, Acc* S, size_t lds,
+                   int lds_instr, const Scalars* sc, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false>), dim3(h->nb2), dim3(kBlock), P.lds, st,
-                       h->sv, P.u, P.q, h->wb, P.gpart, P.lds_instr, h->sc);
-    hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), dim3(kBlock), 0, st, P.gpart, h->nb2,
-                       P.q + h->sv.glob_base, h->sc);
-    return LSQR_OK;
+    const dim3 g(h->nb2), b(kBlock);
+    const bool att = h->att_mode == 0;
+    if (att && h->astro_scan)
+        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, true>), g, b, lds, st, h->sv, u, q,
+                           h->wb, gpart, lds_instr, sc);
+    else if (att)
+        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, false>), g, b, lds, st, h->sv, u, q,
+                           h->wb, gpart, lds_instr, sc);
+    else if (h->astro_scan)
+        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, true>), g, b, lds, st, h->sv, u, q,
+                           h->wb, gpart, lds_instr, sc);
+    else
+        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, false>), g, b, lds, st, h->sv, u,
+                           q, h->wb, gpart, lds_instr, sc);
+    hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), b, 0, st, gpart, h->nb2, q + h->sv.glob_base, sc);
+    if (!att) {
+        const int64_t ns = (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis;
+        hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), b, 0, st, ns, S, (Acc)0);
+        hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc>), g, b, 0, st, h->sv.m,
+                           (const T*)h->att_sorted, (const int32_t*)h->perm,
+                           (const int32_t*)h->tkey, u, S, h->wb_att, sc);
+        hipLaunchKernelGGL((k_att_combine<Acc>), dim3(h->nbc), b, 0, st, (const Acc*)S,
+                           h->sv.n_dfa, q + h->sv.att_base, sc);
+    }
 }
 
 // One LSQR iteration; ev (optional) = 4 events bracketing aprod1 and aprod2.
@@ -173,11 +223,8 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
     if (ev) (void)hipEventRecord(ev[2], st);
-    hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false>), dim3(h->nb2), dim3(kBlock), P.lds, st,
-                       h->sv, (const Acc*)P.u, P.q, h->wb, P.gpart, P.lds_instr, h->sc);
+    launch_aprod2<T, Acc>(h, P.u, P.q, P.gpart, P.S, P.lds, P.lds_instr, h->sc, st);
     if (ev) (void)hipEventRecord(ev[3], st);
-    hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), dim3(kBlock), 0, st, P.gpart, h->nb2,
-                       P.q + h->sv.glob_base, h->sc);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
                        h->sc, h->partc);
     hipLaunchKernelGGL(k_scalar_alpha, dim3(1), dim3(kBlock), 0, st, h->partc, h->nbc, h->sc);
@@ -195,10 +242,7 @@ void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st)
     hipLaunchKernelGGL(k_scalar_init_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, P.q, (Acc)0);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->v, 0.0);
-    hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false>), dim3(h->nb2), dim3(kBlock), P.lds, st,
-                       h->sv, (const Acc*)P.u, P.q, h->wb, P.gpart, P.lds_instr, h->sc);
-    hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), dim3(kBlock), 0, st, P.gpart, h->nb2,
-                       P.q + h->sv.glob_base, h->sc);
+    launch_aprod2<T, Acc>(h, P.u, P.q, P.gpart, P.S, P.lds, P.lds_instr, h->sc, st);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
                        h->sc, h->partc);
     hipLaunchKernelGGL(k_scalar_init_alpha, dim3(1), dim3(kBlock), 0, st, h->partc, h->nbc, h->sc);
@@ -215,6 +259,7 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     LSQR_TRY(dalloc(&P.vp, n));
     LSQR_TRY(dalloc(&P.q, n));
     LSQR_TRY(dalloc(&P.gpart, h->nb2));
+    LSQR_TRY(dalloc(&P.S, (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis));
     const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(Acc);
     P.lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
     P.lds = P.lds_instr ? (size_t)bytes : 0;
@@ -222,6 +267,67 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     HIP_TRY(hipGetLastError());
     P.ready = true;
     return LSQR_OK;
+}
+
+// Row-reordered attitude structures: a stable radix sort of the rows by t,
+// the attitude coefficients gathered into that order, t-aligned wave ranges.
+template <typename T>
+lsqr_status prepare_att_sorted(lsqr_handle* h)
+{
+    if (h->att_ready) return LSQR_OK;
+    const int64_t m = h->sv.m;
+    if (m >= ((int64_t)1 << 31) || h->sv.n_dfa >= ((int64_t)1 << 31))
+        return fail(LSQR_E_UNSUPPORTED,
+                    "row-reordered attitude pass needs n_rows < 2^31 and n_dfa < 2^31");
+    hipStream_t st = h->stream;
+    int32_t *keys = nullptr, *rows = nullptr;
+    void* temp = nullptr;
+    size_t temp_bytes = 0;
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < h->sv.n_dfa) ++bits;
+    LSQR_TRY(dalloc(&h->perm, m));
+    LSQR_TRY(dalloc(&h->tkey, m));
+    LSQR_TRY(dalloc(&h->wb_att, (int64_t)h->nb2 * kWavesPerBlock + 1));
+    LSQR_TRY(dalloc(&h->S_raw, (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis));
+    T* att_sorted = nullptr;
+    LSQR_TRY(dalloc(&att_sorted, (int64_t)kAxes * kParAxis * m));
+    h->att_sorted = att_sorted;
+    LSQR_TRY(dalloc(&keys, m));
+    lsqr_status rc = dalloc(&rows, m);
+    hipError_t e = hipSuccess;
+    if (rc == LSQR_OK) {
+        hipLaunchKernelGGL(k_att_keys, dim3(std::min<int64_t>(cdiv(m, kBlock), 65536)), dim3(kBlock),
+                           0, st, h->sv.att, m, keys, rows);
+        e = rocprim::radix_sort_pairs(nullptr, temp_bytes, keys, h->tkey, rows, h->perm,
+                                      (size_t)m, 0, bits, st);
+        if (e == hipSuccess) rc = dalloc(reinterpret_cast<char**>(&temp), (int64_t)temp_bytes);
+    }
+    if (rc == LSQR_OK && e == hipSuccess)
+        e = rocprim::radix_sort_pairs(temp, temp_bytes, keys, h->tkey, rows, h->perm, (size_t)m, 0,
+                                      bits, st);
+    if (rc == LSQR_OK && e == hipSuccess) {
+        hipLaunchKernelGGL((k_att_gather<T>), dim3(std::min<int64_t>(cdiv(m, kBlock), 65536)),
+                           dim3(kBlock), 0, st, (const T*)h->sv.val, m, (const int32_t*)h->perm,
+                           att_sorted);
+        const int64_t nw = (int64_t)h->nb2 * kWavesPerBlock;
+        hipLaunchKernelGGL((k_wave_bounds<int32_t>), dim3(cdiv(nw + 1, kBlock)), dim3(kBlock), 0, st,
+                           (const int32_t*)h->tkey, m, nw, h->wb_att);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (temp) (void)hipFree(temp);
+    dfree(keys);
+    dfree(rows);
+    if (rc != LSQR_OK) return rc;
+    if (e != hipSuccess) return fail(LSQR_E_HIP, "attitude reordering: %s", hipGetErrorString(e));
+    h->att_ready = true;
+    return LSQR_OK;
+}
+
+lsqr_status ensure_att(lsqr_handle* h)
+{
+    if (h->att_mode == 0) return LSQR_OK;
+    return h->value_type == LSQR_F64 ? prepare_att_sorted<double>(h) : prepare_att_sorted<float>(h);
 }
 
 template <typename Acc>
@@ -233,6 +339,7 @@ void release_path(Path<Acc>& P)
     dfree(P.vp);
     dfree(P.q);
     dfree(P.gpart);
+    dfree(P.S);
     P.ready = false;
 }
 
@@ -340,6 +447,7 @@ template <typename T>
 lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_limit, double atol,
                        double btol, lsqr_info* info)
 {
+    LSQR_TRY(ensure_att(h));
     LSQR_TRY((prepare_path<T, double>(h, h->p64)));
     Path<double>& P = h->p64;
     const int64_t m = h->sv.m, n = h->sv.n;
@@ -358,6 +466,292 @@ lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_l
     HIP_TRY(hipGetLastError());
     LSQR_TRY(read_scalars(h));
     fill_info(h, info, h->sc_host->itn, 0, h->sc_host->bnorm);
+    return LSQR_OK;
+}
+
+// ------------------------------------------------------------- batched RHS
+lsqr_status batch_alloc(lsqr_handle* h, int kmax)
+{
+    auto& B = h->batch;
+    if (B.kmax >= kmax) return LSQR_OK;
+    const int64_t m = h->sv.m, n = h->sv.n;
+    // free the smaller set (graphs reference it)
+    for (auto& g : B.graph)
+        if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+    dfree(B.U); dfree(B.V); dfree(B.W); dfree(B.Y); dfree(B.VP); dfree(B.Q);
+    dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
+    dfree(B.sc); dfree(B.flag);
+    B.kmax = 0;
+    LSQR_TRY(dalloc(&B.U, m * kmax));
+    LSQR_TRY(dalloc(&B.V, n * kmax));
+    LSQR_TRY(dalloc(&B.W, n * kmax));
+    LSQR_TRY(dalloc(&B.Y, n * kmax));
+    LSQR_TRY(dalloc(&B.VP, n * kmax));
+    LSQR_TRY(dalloc(&B.Q, n * kmax));
+    LSQR_TRY(dalloc(&B.gpart, (int64_t)h->nb2 * kmax));
+    LSQR_TRY(dalloc(&B.part1, (int64_t)h->nb1 * kmax));
+    LSQR_TRY(dalloc(&B.partc, (int64_t)h->nbc * kmax));
+    LSQR_TRY(dalloc(&B.partdd, (int64_t)h->nbc * kmax));
+    LSQR_TRY(dalloc(&B.partxx, (int64_t)h->nbc * kmax));
+    LSQR_TRY(dalloc(&B.sc, kmax));
+    LSQR_TRY(dalloc(&B.flag, 1));
+    hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n * kmax, B.Q,
+                       0.0);
+    HIP_TRY(hipGetLastError());
+    B.kmax = kmax;
+    return LSQR_OK;
+}
+
+void batch_free(lsqr_handle* h)
+{
+    auto& B = h->batch;
+    for (auto& g : B.graph)
+        if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+    dfree(B.U); dfree(B.V); dfree(B.W); dfree(B.Y); dfree(B.VP); dfree(B.Q);
+    dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
+    dfree(B.sc); dfree(B.flag);
+    B.kmax = 0;
+}
+
+template <int K>
+size_t batch_lds(const lsqr_handle* h, int* lds_instr)
+{
+    const int64_t bytes = h->sv.n_instr_cols * K * 8;
+    *lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
+    return *lds_instr ? (size_t)bytes : 0;
+}
+
+template <typename T, int K>
+void batch_aprod2(lsqr_handle* h, hipStream_t st)
+{
+    auto& B = h->batch;
+    int li = 0;
+    const size_t lds = batch_lds<K>(h, &li);
+    hipLaunchKernelGGL((batched::k_aprod2<T, double, K>), dim3(h->nb2), dim3(kBlock), lds, st,
+                       h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
+    hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
+                       (const double*)B.gpart, h->nb2, B.Q + h->sv.glob_base * K, B.sc);
+}
+
+template <typename T, int K>
+void batch_iteration(lsqr_handle* h, hipStream_t st, hipEvent_t* ev)
+{
+    auto& B = h->batch;
+    const int64_t n = h->sv.n;
+    if (ev) (void)hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL((batched::k_aprod1<T, double, K>), dim3(h->nb1), dim3(kBlock), 0, st, h->sv,
+                       (const double*)B.VP, B.U, B.sc, B.part1);
+    if (ev) (void)hipEventRecord(ev[1], st);
+    hipLaunchKernelGGL((batched::k_scalar_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1, h->nb1,
+                       B.sc);
+    if (ev) (void)hipEventRecord(ev[2], st);
+    batch_aprod2<T, K>(h, st);
+    if (ev) (void)hipEventRecord(ev[3], st);
+    hipLaunchKernelGGL((batched::k_col_a<double, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, B.Q,
+                       B.V, B.sc, B.partc);
+    hipLaunchKernelGGL((batched::k_scalar_alpha<K>), dim3(1), dim3(kBlock), 0, st, B.partc, h->nbc,
+                       B.sc);
+    hipLaunchKernelGGL((batched::k_col_b<double, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, B.V,
+                       B.W, B.Y, B.VP, B.sc, B.partdd, B.partxx);
+    hipLaunchKernelGGL((batched::k_scalar_stop<K>), dim3(1), dim3(kBlock), 0, st, B.partdd,
+                       B.partxx, h->nbc, B.sc);
+    hipLaunchKernelGGL((batched::k_all_done<K>), dim3(1), dim3(kWave), 0, st, B.sc, B.flag);
+}
+
+// One tile of K right-hand sides: B_tile = B[:, j0:j0+K] (row stride ldb),
+// X_tile likewise. Per-RHS results in infos (host, may be NULL).
+template <typename T, int K>
+lsqr_status batch_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X, int64_t ldx,
+                       int32_t itn_limit, double atol, double btol, lsqr_info* infos,
+                       int max_chunks)
+{
+    auto& B = h->batch;
+    hipStream_t st = h->stream;
+    const int64_t m = h->sv.m, n = h->sv.n;
+    Scalars host[8];
+    memset(host, 0, sizeof host);
+    for (int r = 0; r < K; ++r) {
+        host[r].atol = atol;
+        host[r].btol = btol;
+        host[r].ctol = h->conlim > 0.0 ? 1.0 / h->conlim : 0.0;
+        host[r].itn_limit = itn_limit;
+        host[r].tests = h->tests;
+        host[r].inv_alpha = 1.0;
+    }
+    HIP_TRY(hipMemcpyAsync(B.sc, host, K * sizeof(Scalars), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL((batched::k_copy_ssq<double, K>), dim3(h->nb1), dim3(kBlock), 0, st, m, Bm,
+                       ldb, B.U, B.part1);
+    hipLaunchKernelGGL((batched::k_scalar_init_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1,
+                       h->nb1, B.sc);
+    hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n * K, B.Q, 0.0);
+    hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n * K, B.V, 0.0);
+    batch_aprod2<T, K>(h, st);
+    hipLaunchKernelGGL((batched::k_col_a<double, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, B.Q,
+                       B.V, B.sc, B.partc);
+    hipLaunchKernelGGL((batched::k_scalar_init_alpha<K>), dim3(1), dim3(kBlock), 0, st, B.partc,
+                       h->nbc, B.sc);
+    hipLaunchKernelGGL((batched::k_col_init<double, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p,
+                       B.V, B.W, B.Y, B.VP, B.sc);
+    hipLaunchKernelGGL((batched::k_all_done<K>), dim3(1), dim3(kWave), 0, st, B.sc, B.flag);
+    HIP_TRY(hipGetLastError());
+
+    const int chunk = std::max(1, h->chunk);
+    const bool graph = h->use_graph && !h->profile;
+    if (graph && (B.graph[K] == nullptr || B.graph_chunk[K] != chunk)) {
+        if (B.graph[K]) (void)hipGraphExecDestroy(B.graph[K]);
+        B.graph[K] = nullptr;
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < chunk; ++k) batch_iteration<T, K>(h, st, nullptr);
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (e != hipSuccess) return fail(LSQR_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&B.graph[K], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            B.graph[K] = nullptr;
+            return fail(LSQR_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        B.graph_chunk[K] = chunk;
+    }
+    if (h->profile && h->events.size() < (size_t)4 * chunk) {
+        while (h->events.size() < (size_t)4 * chunk) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            h->events.push_back(e);
+        }
+    }
+    int32_t done = 0;
+    HIP_TRY(hipMemcpyAsync(&done, B.flag, sizeof done, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int32_t itn_seen = 0;
+    for (int c = 0; !done && itn_limit > 0 && (max_chunks <= 0 || c < max_chunks); ++c) {
+        if (graph) {
+            HIP_TRY(hipGraphLaunch(B.graph[K], st));
+        } else {
+            for (int k = 0; k < chunk; ++k)
+                batch_iteration<T, K>(h, st, h->profile ? &h->events[4 * k] : nullptr);
+            HIP_TRY(hipGetLastError());
+        }
+        HIP_TRY(hipMemcpyAsync(host, B.sc, K * sizeof(Scalars), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&done, B.flag, sizeof done, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        int32_t itn_max = 0;
+        for (int r = 0; r < K; ++r) itn_max = std::max(itn_max, host[r].itn);
+        if (h->profile) {
+            const int ran = std::min(chunk, itn_max - itn_seen);
+            for (int k = 0; k < ran; ++k) {
+                float a = 0.f, b = 0.f;
+                HIP_TRY(hipEventElapsedTime(&a, h->events[4 * k], h->events[4 * k + 1]));
+                HIP_TRY(hipEventElapsedTime(&b, h->events[4 * k + 2], h->events[4 * k + 3]));
+                h->ms1 += a;
+                h->ms2 += b;
+                h->n1 += 1;
+                h->n2 += 1;
+            }
+        }
+        if (!done && itn_max <= itn_seen)
+            return fail(LSQR_E_HIP, "batched LSQR made no progress (itn %d)", itn_max);
+        itn_seen = itn_max;
+    }
+    hipLaunchKernelGGL((batched::k_unprecond<K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p,
+                       (const double*)B.Y, X, ldx);
+    HIP_TRY(hipMemcpyAsync(host, B.sc, K * sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (infos) {
+        for (int r = 0; r < K; ++r) {
+            lsqr_info& in = infos[r];
+            memset(&in, 0, sizeof in);
+            in.istop = host[r].istop;
+            in.itn = host[r].itn;
+            in.rnorm = host[r].rnorm;
+            in.arnorm = host[r].arnorm;
+            in.anorm = host[r].anorm;
+            in.acond = host[r].acond;
+            in.xnorm = host[r].xnorm;
+            in.bnorm = host[r].bnorm;
+        }
+    }
+    return LSQR_OK;
+}
+
+template <typename T>
+lsqr_status batch_tile_k(lsqr_handle* h, int K, const double* Bm, int64_t ldb, double* X,
+                         int64_t ldx, int32_t itn_limit, double atol, double btol,
+                         lsqr_info* infos, int max_chunks)
+{
+    switch (K) {
+    case 1: return batch_tile<T, 1>(h, Bm, ldb, X, ldx, itn_limit, atol, btol, infos, max_chunks);
+    case 2: return batch_tile<T, 2>(h, Bm, ldb, X, ldx, itn_limit, atol, btol, infos, max_chunks);
+    case 4: return batch_tile<T, 4>(h, Bm, ldb, X, ldx, itn_limit, atol, btol, infos, max_chunks);
+    case 8: return batch_tile<T, 8>(h, Bm, ldb, X, ldx, itn_limit, atol, btol, infos, max_chunks);
+    default: return fail(LSQR_E_INVALID, "k-tile must be 1, 2, 4 or 8");
+    }
+}
+
+// Autotuner: times a few profiled iterations of the first k-tile for every
+// candidate K <= k and keeps the K with the lowest time per RHS-iteration.
+template <typename T>
+lsqr_status batch_autotune(lsqr_handle* h, const double* Bm, int64_t ldb, int32_t k)
+{
+    auto& B = h->batch;
+    const int saved_profile = h->profile, saved_chunk = h->chunk, saved_tests = h->tests;
+    const double saved[4] = {h->ms1, h->ms2, (double)h->n1, (double)h->n2};
+    double* Xs = nullptr;
+    LSQR_TRY(dalloc(&Xs, h->sv.n * 8));
+    int best = 1;
+    double best_ms = 1e300;
+    lsqr_status rc = LSQR_OK;
+    for (int K = 1; K <= 8 && K <= k; K *= 2) {
+        h->profile = 1;
+        h->tests = 0;
+        h->chunk = 3;
+        h->ms1 = h->ms2 = 0.0;
+        h->n1 = h->n2 = 0;
+        rc = batch_tile_k<T>(h, K, Bm, ldb, Xs, K, 1 << 20, 0.0, 0.0, nullptr, 1);
+        if (rc != LSQR_OK) break;
+        const double per_iter = (h->ms1 + h->ms2) / std::max<int64_t>(1, h->n1);
+        B.tuned_ms[K] = per_iter / K;
+        if (B.tuned_ms[K] < best_ms) {
+            best_ms = B.tuned_ms[K];
+            best = K;
+        }
+    }
+    dfree(Xs);
+    h->profile = saved_profile;
+    h->chunk = saved_chunk;
+    h->tests = saved_tests;
+    h->ms1 = saved[0];
+    h->ms2 = saved[1];
+    h->n1 = (int64_t)saved[2];
+    h->n2 = (int64_t)saved[3];
+    if (rc != LSQR_OK) return rc;
+    B.tuned_k = best;
+    return LSQR_OK;
+}
+
+template <typename T>
+lsqr_status solve_batched(lsqr_handle* h, const double* Bm, double* X, int32_t k,
+                          int32_t itn_limit, double atol, double btol, lsqr_info* infos)
+{
+    int K = h->ktile;
+    if (K == 0) {
+        LSQR_TRY(batch_alloc(h, std::min(8, k >= 8 ? 8 : (k >= 4 ? 4 : (k >= 2 ? 2 : 1)))));
+        if (h->batch.tuned_k == 0) LSQR_TRY(batch_autotune<T>(h, Bm, k, k));
+        K = h->batch.tuned_k;
+    }
+    LSQR_TRY(batch_alloc(h, K));
+    if (h->profile) {
+        h->ms1 = h->ms2 = 0.0;
+        h->n1 = h->n2 = 0;
+    }
+    int32_t j0 = 0;
+    while (j0 < k) {
+        int kt = K;
+        while (kt > k - j0) kt /= 2;  // ragged end: 4, 2, 1
+        LSQR_TRY(batch_tile_k<T>(h, kt, Bm + j0, k, X + j0, k, itn_limit, atol, btol,
+                                 infos ? infos + j0 : nullptr, 0));
+        j0 += kt;
+    }
     return LSQR_OK;
 }
 
@@ -504,8 +898,8 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     }
 
     // 2. star-aligned row ranges of the aprod2 waves
-    hipLaunchKernelGGL(k_wave_bounds, dim3(cdiv(nw + 1, kBlock)), dim3(kBlock), 0, st0, s.star, m,
-                       nw, h->wb);
+    hipLaunchKernelGGL((k_wave_bounds<int64_t>), dim3(cdiv(nw + 1, kBlock)), dim3(kBlock), 0, st0,
+                       s.star, m, nw, h->wb);
 
     // 3. column scaling p from the column norms (squared-coefficient aprod2)
     double* ssq = nullptr;
@@ -541,7 +935,14 @@ lsqr_status lsqr_destroy(lsqr_handle* h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     release_path(h->p64);
     release_path(h->p32);
+    batch_free(h);
     dfree(h->wb);
+    dfree(h->perm);
+    dfree(h->tkey);
+    dfree(h->wb_att);
+    dfree(h->S_raw);
+    if (h->att_sorted) (void)hipFree(h->att_sorted);
+    h->att_sorted = nullptr;
     dfree(h->p);
     dfree(h->v);
     dfree(h->w);
@@ -581,6 +982,24 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
     case LSQR_OPT_PROFILE:
         h->profile = value != 0.0 ? 1 : 0;
         return LSQR_OK;
+    case LSQR_OPT_ATT_MODE:
+    case LSQR_OPT_ASTRO_SCAN: {
+        const int v = value != 0.0 ? 1 : 0;
+        int& slot = option == LSQR_OPT_ATT_MODE ? h->att_mode : h->astro_scan;
+        if (slot != v) {  // captured graphs bake in the kernel choice
+            if (h->p64.graph) (void)hipGraphExecDestroy(h->p64.graph);
+            if (h->p32.graph) (void)hipGraphExecDestroy(h->p32.graph);
+            h->p64.graph = nullptr;
+            h->p32.graph = nullptr;
+        }
+        slot = v;
+        return LSQR_OK;
+    }
+    case LSQR_OPT_KTILE:
+        if (!(value == 0.0 || value == 1.0 || value == 2.0 || value == 4.0 || value == 8.0))
+            return fail(LSQR_E_INVALID, "k-tile must be 0 (autotune), 1, 2, 4 or 8");
+        h->ktile = (int)value;
+        return LSQR_OK;
     case LSQR_OPT_OUTER_TOL:
         if (!(value >= 0.0)) return fail(LSQR_E_INVALID, "outer tolerance must be >= 0");
         h->outer_tol = value;
@@ -610,19 +1029,16 @@ lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y)
 {
     LSQR_TRY(check_handle(h));
     if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
+    LSQR_TRY(ensure_att(h));
     const int64_t bytes = h->sv.n_instr_cols * 8;
     const int lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
     const size_t lds = lds_instr ? (size_t)bytes : 0;
     if (h->value_type == LSQR_F64)
-        hipLaunchKernelGGL((k_aprod2<double, double, double, false>), dim3(h->nb2), dim3(kBlock),
-                           lds, h->user_stream, h->sv, y, x, h->wb, h->gpart_raw, lds_instr,
-                           (const Scalars*)nullptr);
+        launch_aprod2<double, double>(h, y, x, h->gpart_raw, h->S_raw, lds, lds_instr, nullptr,
+                                      h->user_stream);
     else
-        hipLaunchKernelGGL((k_aprod2<float, double, double, false>), dim3(h->nb2), dim3(kBlock), lds,
-                           h->user_stream, h->sv, y, x, h->wb, h->gpart_raw, lds_instr,
-                           (const Scalars*)nullptr);
-    hipLaunchKernelGGL((k_glob_sum<double>), dim3(1), dim3(kBlock), 0, h->user_stream,
-                       h->gpart_raw, h->nb2, x + h->sv.glob_base, (const Scalars*)nullptr);
+        launch_aprod2<float, double>(h, y, x, h->gpart_raw, h->S_raw, lds, lds_instr, nullptr,
+                                     h->user_stream);
     HIP_TRY(hipGetLastError());
     return LSQR_OK;
 }
@@ -669,6 +1085,7 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
         return fail(LSQR_E_INVALID, "itn_limit >= 0 and outer_limit >= 1 required");
     if (!(atol >= 0.0) || !(btol >= 0.0)) return fail(LSQR_E_INVALID, "atol, btol must be >= 0");
     HIP_TRY(hipStreamSynchronize(h->user_stream));
+    LSQR_TRY(ensure_att(h));
     LSQR_TRY((prepare_path<float, float>(h, h->p32)));
     Path<float>& P = h->p32;
     const int64_t n = h->sv.n;
@@ -710,6 +1127,33 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
     if (outer > outer_limit) outer = outer_limit;
     *h->sc_host = last;
     fill_info(h, info, total_itn, outer, bnorm);
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32_t k,
+                               int32_t itn_limit, double atol, double btol, lsqr_info* infos)
+{
+    LSQR_TRY(check_handle(h));
+    if (!B || !X) return fail(LSQR_E_INVALID, "null matrix");
+    if (k < 1 || k > 4096) return fail(LSQR_E_INVALID, "k must be in [1, 4096]");
+    if (itn_limit < 0) return fail(LSQR_E_INVALID, "itn_limit must be >= 0");
+    if (!(atol >= 0.0) || !(btol >= 0.0)) return fail(LSQR_E_INVALID, "atol, btol must be >= 0");
+    if (h->att_mode != 0)
+        return fail(LSQR_E_UNSUPPORTED, "batched solves use the atomic attitude scatter");
+    HIP_TRY(hipStreamSynchronize(h->user_stream));
+    if (h->value_type == LSQR_F64)
+        LSQR_TRY(solve_batched<double>(h, B, X, k, itn_limit, atol, btol, infos));
+    else
+        LSQR_TRY(solve_batched<float>(h, B, X, k, itn_limit, atol, btol, infos));
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_batch_tuning(lsqr_handle* h, int32_t* k_tile, double* ms_per_rhs_iter)
+{
+    if (!h) return fail(LSQR_E_INVALID, "null handle");
+    if (k_tile) *k_tile = h->batch.tuned_k;
+    if (ms_per_rhs_iter)
+        for (int K = 1, i = 0; K <= 8; K *= 2, ++i) ms_per_rhs_iter[i] = h->batch.tuned_ms[K];
     return LSQR_OK;
 }
 

@@ -22,11 +22,12 @@ LSQR_E_UNSUPPORTED = -5
 LSQR_F64 = 0
 LSQR_F32 = 1
 
-OPTIONS = {"conlim": 1, "tests": 2, "chunk": 3, "graph": 4, "profile": 5, "outer_tol": 6}
+OPTIONS = {"conlim": 1, "tests": 2, "chunk": 3, "graph": 4, "profile": 5, "outer_tol": 6,
+           "att_mode": 7, "astro_scan": 8, "ktile": 9}
 
 SYMBOLS = ("lsqr_create", "lsqr_destroy", "lsqr_set_option", "lsqr_aprod1", "lsqr_aprod2",
            "lsqr_get_precond", "lsqr_num_cols", "lsqr_solve", "lsqr_solve_refined",
-           "lsqr_kernel_times", "lsqr_last_error")
+           "lsqr_solve_batched", "lsqr_batch_tuning", "lsqr_kernel_times", "lsqr_last_error")
 
 
 class LsqrError(RuntimeError):
@@ -91,6 +92,8 @@ def load_library(path: str = LIB_PATH):
         "lsqr_num_cols": ([H, ctypes.POINTER(I64)], I32),
         "lsqr_solve": ([H, P, P, I32, F64, F64, ctypes.POINTER(_Info)], I32),
         "lsqr_solve_refined": ([H, P, P, I32, F64, F64, I32, ctypes.POINTER(_Info)], I32),
+        "lsqr_solve_batched": ([H, P, P, I32, I32, F64, F64, ctypes.POINTER(_Info)], I32),
+        "lsqr_batch_tuning": ([H, ctypes.POINTER(I32), ctypes.POINTER(F64)], I32),
         "lsqr_kernel_times": ([H, ctypes.POINTER(F64), ctypes.POINTER(I64),
                                ctypes.POINTER(F64), ctypes.POINTER(I64)], I32),
         "lsqr_last_error": ([], ctypes.c_char_p),
@@ -240,6 +243,26 @@ class LsqrSystem:
                                        int(itn_limit), float(atol), float(btol),
                                        int(outer_limit), ctypes.byref(ci)))
         return x, self._info(ci)
+
+    def solve_batched(self, B, itn_limit: int, atol: float = 1e-12, btol: float = 1e-12, X=None):
+        """B: [m, k] float64 (row-interleaved); returns X [n, k] and k Info."""
+        import torch
+
+        if B.dim() != 2 or B.shape[0] != self.m:
+            raise ValueError(f"B must be [m, k] with m={self.m}")
+        k = int(B.shape[1])
+        X = torch.empty((self.n, k), dtype=torch.float64, device=self.device) if X is None else X
+        infos = (_Info * k)()
+        _check(_lib.lsqr_solve_batched(self._h, _dev_ptr(B, torch.float64, (self.m, k), "B"),
+                                       _dev_ptr(X, torch.float64, (self.n, k), "X"), k,
+                                       int(itn_limit), float(atol), float(btol), infos))
+        return X, [self._info(ci) for ci in infos]
+
+    def batch_tuning(self):
+        k = ctypes.c_int32()
+        ms = (ctypes.c_double * 4)()
+        _check(_lib.lsqr_batch_tuning(self._h, ctypes.byref(k), ms))
+        return {"k_tile": k.value, "ms_per_rhs_iter": {1 << i: ms[i] for i in range(4)}}
 
     def kernel_times(self):
         a, b = ctypes.c_double(), ctypes.c_double()

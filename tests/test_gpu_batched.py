@@ -1,0 +1,108 @@
+"""Batched right-hand sides against the oracle's single-RHS solves."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def c0():
+    S = synth.make_system(synth.CONFIGS[0])
+    o = oracle.OracleSystem.from_synth(S)
+    xt = synth.x_true(S.spec)
+    B = np.stack([o.aprod1(xt, synth.noise(S.spec, S.m, rhs=j)) for j in range(5)], axis=1)
+    return S, o, B
+
+
+def rel_inf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("ktile", [1, 2, 4, 8])
+def test_batched_fixed_iterations(torch_cuda, c0, ktile):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LsqrSystem
+
+    S, o, B = c0
+    itn = 40
+    say(f"batched parity: c0 k=5 ktile={ktile} itn={itn}")
+    g = LsqrSystem.from_host(S, "cuda:0")
+    g.set_option("tests", 0)
+    g.set_option("ktile", ktile)
+    X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(B)).cuda(), itn, 0.0, 0.0)
+    Xh = X.cpu().numpy()
+    g.close()
+    for j in range(B.shape[1]):
+        x_ref, i_ref = o.lsqr(B[:, j], itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+        assert infos[j].itn == itn and infos[j].istop == 7
+        assert rel_inf(Xh[:, j], x_ref) <= 1e-10, j
+        assert abs(infos[j].rnorm - i_ref.rnorm) <= 1e-8 * i_ref.rnorm
+
+
+def test_batched_masks_freeze_converged_rhs(torch_cuda, c0):
+    # RHS 0 is consistent (b = one column of A) and stops early by S1; the
+    # others stop later by S2. Each must equal its own single solve.
+    torch = torch_cuda
+    from paper_2308_00778_amd import LsqrSystem
+
+    S, o, B = c0
+    B = B.copy()
+    e = np.zeros(o.n)
+    e[-1] = 1.0
+    B[:, 0] = o.aprod1(e)
+    B[:, 3] = 0.0  # b = 0: stops before the first iteration
+    say("batched masks: c0 k=5, consistent + zero + noisy RHS")
+    g = LsqrSystem.from_host(S, "cuda:0")
+    g.set_option("ktile", 8)
+    X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(B)).cuda(), 300,
+                               1e-12, 1e-12)
+    Xh = X.cpu().numpy()
+    singles = []
+    for j in range(B.shape[1]):
+        xs, inf = g.solve(torch.from_numpy(np.ascontiguousarray(B[:, j])).cuda(), 300,
+                          1e-12, 1e-12)
+        singles.append((xs.cpu().numpy(), inf))
+    g.close()
+    assert infos[3].istop == 0 and infos[3].itn == 0 and not np.any(Xh[:, 3])
+    assert infos[0].istop == 1 and infos[0].itn < infos[1].itn
+    for j in (0, 1, 2, 4):
+        x_ref, i_ref = o.lsqr(B[:, j], 300, atol=1e-12, btol=1e-12, conlim=1e8)
+        xs, inf = singles[j]
+        assert infos[j].istop == i_ref.istop and abs(infos[j].itn - i_ref.itn) <= 1, j
+        assert (infos[j].istop, infos[j].itn) == (inf.istop, inf.itn), j
+        assert rel_inf(Xh[:, j], x_ref) <= 1e-10, j
+        assert rel_inf(Xh[:, j], xs) <= 1e-10, j
+
+
+def test_batched_autotune_picks_a_tile(torch_cuda, c0):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LsqrSystem
+
+    S, o, B = c0
+    say("batched autotune: c0 k=5")
+    g = LsqrSystem.from_host(S, "cuda:0")
+    g.set_option("tests", 0)
+    X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(B)).cuda(), 30, 0.0, 0.0)
+    t = g.batch_tuning()
+    Xh = X.cpu().numpy()
+    g.close()
+    assert t["k_tile"] in (1, 2, 4)
+    assert all(t["ms_per_rhs_iter"][k] > 0 for k in (1, 2, 4))
+    x_ref, _ = o.lsqr(B[:, 2], 30, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+    assert rel_inf(Xh[:, 2], x_ref) <= 1e-10

@@ -93,17 +93,23 @@ def test_aprod1_parity(torch_cuda, name):
     assert np.all(np.abs(got - want) <= 32 * EPS * bound + 1e-300)
 
 
+VARIANTS = [(0, 1), (1, 0), (0, 0), (1, 1)]  # (att_mode, astro_scan)
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=[f"att{a}_scan{b}" for a, b in VARIANTS])
 @pytest.mark.parametrize("name", list(SPECS))
-def test_aprod2_parity(torch_cuda, name):
+def test_aprod2_parity(torch_cuda, name, variant):
     torch = torch_cuda
     S, o = system(name)
-    say(f"aprod2 parity: {name} m={S.m} n={o.n} seed={S.spec.seed}")
+    say(f"aprod2 parity: {name} m={S.m} n={o.n} seed={S.spec.seed} variant={variant}")
     rng = np.random.default_rng(6)
     y = rng.standard_normal(o.m)
     x0 = rng.standard_normal(o.n)
     want = o.aprod2(y, x0)
     bound = abs_system(S).aprod2(np.abs(y), np.abs(x0))
     g = gpu_system(torch, S)
+    g.set_option("att_mode", variant[0])
+    g.set_option("astro_scan", variant[1])
     xd = torch.from_numpy(x0).cuda()
     g.aprod2(xd, torch.from_numpy(y).cuda())
     torch.cuda.synchronize()
@@ -138,12 +144,24 @@ def _b(S, o, rhs=0):
                                        ("one_star", 15), ("few_rows", 15), ("wide_instr", 60)])
 @pytest.mark.parametrize("graph", [1, 0])
 def test_solve_fixed_iterations(torch_cuda, name, itn, graph):
+    _solve_fixed(torch_cuda, name, itn, graph, (0, 1))
+
+
+@pytest.mark.parametrize("variant", VARIANTS[1:], ids=[f"att{a}_scan{b}" for a, b in VARIANTS[1:]])
+@pytest.mark.parametrize("name,itn", [("c0", 50), ("ragged", 60)])
+def test_solve_variants(torch_cuda, name, itn, variant):
+    _solve_fixed(torch_cuda, name, itn, 1, variant)
+
+
+def _solve_fixed(torch_cuda, name, itn, graph, variant):
     torch = torch_cuda
     S, o = system(name)
     b = _b(S, o)
     x_ref, i_ref = o.lsqr(b, itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)
-    say(f"solve parity: {name} itn={itn} graph={graph}")
+    say(f"solve parity: {name} itn={itn} graph={graph} variant={variant}")
     g = gpu_system(torch, S)
+    g.set_option("att_mode", variant[0])
+    g.set_option("astro_scan", variant[1])
     g.set_option("tests", 0)
     g.set_option("graph", graph)
     g.set_option("chunk", 7)
