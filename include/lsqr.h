@@ -112,14 +112,15 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         read back with lsqr_kernel_times
  *   LSQR_OPT_OUTER_TOL    refinement: stop when ||d||_inf <= tol ||x||_inf
  *                         (default 1e-10)
- *   LSQR_OPT_ATT_MODE     attitude part of aprod2: 0 (default) scatter-add with
- *                         device atomics; 1 a second pass over the rows sorted
- *                         by attitude start (segmented sums, no atomics; costs
- *                         a sorted copy of the 12 attitude coefficients and two
- *                         int32 per row, built on first use, n_rows < 2^31)
- *   LSQR_OPT_ASTRO_SCAN   astrometric part of aprod2: 1 (default) segmented scan
- *                         per 64-row chunk; 0 running per-lane partials reduced
- *                         only where a star ends
+ *   LSQR_OPT_ATT_MODE     attitude part of aprod2: 1 (default) a second pass over
+ *                         the rows sorted by attitude start (segmented sums, no
+ *                         atomics; costs a sorted copy of the 12 attitude
+ *                         coefficients and two int32 per row, built on first
+ *                         use, needs n_rows < 2^31); 0 scatter-add with device
+ *                         atomics (no extra memory, about 8x slower on MI355X)
+ *   LSQR_OPT_ASTRO_SCAN   astrometric part of aprod2: 0 (default) running
+ *                         per-lane partials reduced only where a star ends;
+ *                         1 a segmented scan over every 64-row chunk
  *   LSQR_OPT_KTILE        batched solves: right-hand sides advanced together per
  *                         pass over A (1, 2, 4, 8), 0 (default) = autotune once
  *                         per handle
@@ -158,9 +159,12 @@ lsqr_status lsqr_solve(lsqr_handle* h, const double* b, double* x, int32_t itn_l
 /* FP32-stored system: FP64 iterative refinement around an FP32 LSQR.
  * Outer step k: r = b - A x in FP64 (values widened, FP64 accumulation),
  * then an inner LSQR on min ||A d - r|| with FP32 products and FP32
- * accumulation (FP64 norms, Givens scalars and x/w updates), stopped by its
- * own tests with tolerances atol, btol or after itn_limit iterations; then
- * x += d in FP64. The outer loop ends when ||d||_inf <= OUTER_TOL ||x||_inf,
+ * accumulation (FP64 norms, Givens scalars and x/w updates), stopped once
+ * its normal-equation residual estimate ||Abar^T (r - A d)|| has fallen below
+ * atol times its initial value ||Abar^T r|| (btol is unused: the residual of
+ * a correction problem is dominated by the irreducible least-squares
+ * residual, so the absolute tests S1/S2 cannot measure its progress), or
+ * after itn_limit iterations; then x += d in FP64. The outer loop ends when ||d||_inf <= OUTER_TOL ||x||_inf,
  * when r is zero or orthogonal to the range of A, or after outer_limit steps.
  * b: FP64 [m]; x: FP64 [n] output (x_0 = 0). info->itn counts the inner
  * iterations of all steps, info->outer_steps the outer steps, info->istop and
@@ -177,8 +181,7 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
  * RHS that has stopped is frozen (its x, w, v, u and estimates no longer
  * change) while the others continue. Each x[:, j] is the result lsqr_solve
  * would give for b[:, j] up to rounding order. infos: host array of k
- * results (may be NULL); outer_steps is 0. Needs LSQR_OPT_ATT_MODE 0.
- * Synchronous. */
+ * results (may be NULL); outer_steps is 0. Synchronous. */
 lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32_t k,
                                int32_t itn_limit, double atol, double btol, lsqr_info* infos);
 

@@ -71,6 +71,8 @@ struct Scalars {
     double t1, t2, inv_alpha, coef_u;
     double atol, btol, ctol;
     double dmax, xmax;  // refinement: ||d||_inf, ||x||_inf of the last outer step
+    double arnorm0;     // alpha_1 beta_1 = ||Abar^T b||, the initial normal-equation residual
+    double rel_ar;      // > 0: also stop (istop 2) once arnorm <= rel_ar * arnorm0
     int32_t itn, itn_limit, istop, done;
     int32_t tests, beta_zero, pad0, pad1;
 };
@@ -111,6 +113,21 @@ __device__ __forceinline__ double block_max(double v, double* lds)
     return r;
 }
 
+template <int NT>
+__device__ __forceinline__ double block_sum_n(double v, double* lds /* >= NT / kWave */)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    __syncthreads();
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / kWave; ++k) r += lds[k];
+    return r;
+}
+
 // Sum of n partials by one block, fixed order (deterministic). Thread 0.
 __device__ __forceinline__ double sum_partials(const double* part, int n, double* lds)
 {
@@ -128,8 +145,10 @@ __device__ __forceinline__ double max_partials(const double* part, int n, double
 
 // ------------------------------------------------------------------- aprod 1
 // Eq. (2) for one row: sum over the 24 coefficients in section order.
+// xi: the instrumental slice of x (x + instr_base, or its copy in LDS).
 template <typename T, typename Acc, typename VX>
-__device__ __forceinline__ Acc row_dot(const SysView& s, const VX* __restrict__ x, int64_t i)
+__device__ __forceinline__ Acc row_dot(const SysView& s, const VX* __restrict__ x,
+                                       const VX* __restrict__ xi, int64_t i)
 {
     const T* __restrict__ val = static_cast<const T*>(s.val);
     const int64_t m = s.m;
@@ -152,7 +171,6 @@ __device__ __forceinline__ Acc row_dot(const SysView& s, const VX* __restrict__ 
 #pragma unroll
         for (int q = 0; q < kParAxis; ++q) sum += (Acc)a[kOffAtt + ax * kParAxis + q] * (Acc)xt[q];
     }
-    const VX* xi = x + s.instr_base;
 #pragma unroll
     for (int j = 0; j < kInstr; ++j) sum += (Acc)a[kOffInstr + j] * (Acc)xi[ic[j]];
     sum += (Acc)a[kOffGlob] * (Acc)x[s.glob_base];
@@ -166,25 +184,35 @@ enum Aprod1Mode : int {
 };
 
 // part[blockIdx.x] receives the FP64 sum of squares of the stored y (LSQR,
-// RESID modes).
-template <typename T, typename Acc, typename VX, typename VY, int MODE>
-__global__ __launch_bounds__(kBlock) void k_aprod1(SysView s, const VX* __restrict__ x,
-                                                    VY* __restrict__ y,
-                                                    const double* __restrict__ b,
-                                                    const Scalars* __restrict__ sc,
-                                                    double* __restrict__ part)
+// RESID modes). NT threads per block. LDSX: the instrumental slice of x
+// (n_instr_cols values) is first copied into LDS, so that the six random
+// instrumental gathers per row hit LDS instead of L2.
+template <typename T, typename Acc, typename VX, typename VY, int MODE, int NT = kBlock,
+          bool LDSX = false>
+__global__ __launch_bounds__(NT) void k_aprod1(SysView s, const VX* __restrict__ x,
+                                                VY* __restrict__ y, const double* __restrict__ b,
+                                                const Scalars* __restrict__ sc,
+                                                double* __restrict__ part)
 {
-    __shared__ double red[kWavesPerBlock];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[NT / kWave];
     if (MODE == A1_LSQR && sc->done) return;
+    const VX* xi = x + s.instr_base;
+    if (LDSX) {
+        VX* xl = reinterpret_cast<VX*>(smem_raw);
+        for (int64_t j = threadIdx.x; j < s.n_instr_cols; j += NT) xl[j] = xi[j];
+        __syncthreads();
+        xi = xl;
+    }
     const Acc coef = (MODE == A1_LSQR) ? (Acc)sc->coef_u : (Acc)0;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t stride = (int64_t)gridDim.x * NT;
     double ssq = 0.0;
-    for (int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x; i0 < s.m; i0 += 2 * stride) {
+    for (int64_t i0 = (int64_t)blockIdx.x * NT + threadIdx.x; i0 < s.m; i0 += 2 * stride) {
         const int64_t i1 = i0 + stride;
         const bool has1 = i1 < s.m;
         const int64_t i1c = has1 ? i1 : i0;
-        const Acc d0 = row_dot<T, Acc, VX>(s, x, i0);
-        const Acc d1 = row_dot<T, Acc, VX>(s, x, i1c);
+        const Acc d0 = row_dot<T, Acc, VX>(s, x, xi, i0);
+        const Acc d1 = row_dot<T, Acc, VX>(s, x, xi, i1c);
         if (MODE == A1_ACCUM) {
             y[i0] = (VY)((Acc)y[i0] + d0);
             if (has1) y[i1] = (VY)((Acc)y[i1] + d1);
@@ -209,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_aprod1(SysView s, const VX* __restri
         }
     }
     if (MODE != A1_ACCUM) {
-        const double r = block_sum(ssq, red);
+        const double r = block_sum_n<NT>(ssq, red);
         if (threadIdx.x == 0) part[blockIdx.x] = r;
     }
 }
@@ -657,6 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_scalar_init_alpha(const double* __re
     sc->rhobar = alpha;
     sc->phibar = sc->beta;
     sc->arnorm = alpha * sc->beta;
+    sc->arnorm0 = sc->arnorm;
     sc->inv_alpha = alpha > 0.0 ? 1.0 / alpha : 1.0;
     sc->coef_u = alpha / sc->beta;
     if (sc->arnorm == 0.0) sc->done = 1;  // A^T b = 0: x = 0 (istop 0)
@@ -750,6 +779,9 @@ __global__ __launch_bounds__(kBlock) void k_scalar_stop(const double* __restrict
         if (test2 <= sc->atol) istop = 2;
         if (test1 <= rtol) istop = 1;
     }
+    // Relative form of the normal-equation test, for correction problems whose
+    // residual is dominated by the irreducible least-squares residual.
+    if (sc->rel_ar > 0.0 && arnorm <= sc->rel_ar * sc->arnorm0) istop = 2;
     sc->istop = istop;
     if (istop != 0) sc->done = 1;
 }
@@ -1033,7 +1065,7 @@ __global__ __launch_bounds__(kBlock) void k_aprod1(SysView s, const Acc* __restr
 // flush segments, attitude: device atomics, instrumental: LDS histogram
 // [n_instr_cols][K] when lds_instr, else device atomics, global: partials
 // gpart[blk][K]). Frozen RHS contribute nothing.
-template <typename T, typename Acc, int K>
+template <typename T, typename Acc, int K, bool ATT = true>
 __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const Acc* __restrict__ U,
                                                     Acc* __restrict__ Q,
                                                     const int64_t* __restrict__ wb,
@@ -1073,10 +1105,11 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const Acc* __restr
         const bool ok = i < re;
         const int64_t ic = ok ? i : re - 1;
         const int64_t st = ok ? ldnt(&s.star[ic]) : kNoStar;
-        const int64_t t = ldnt(&s.att[ic]);
+        const int64_t t = ATT ? ldnt(&s.att[ic]) : 0;
         T a[kPar];
 #pragma unroll
-        for (int c = 0; c < kPar; ++c) a[c] = ldnt(&val[c * m + ic]);
+        for (int c = 0; c < kPar; ++c)
+            a[c] = (ATT || c < kOffAtt || c >= kOffInstr) ? ldnt(&val[c * m + ic]) : (T)0;
         int32_t ix[kInstr];
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
@@ -1086,7 +1119,7 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const Acc* __restr
 
         if (ok) {
 #pragma unroll
-            for (int ax = 0; ax < kAxes; ++ax)
+            for (int ax = 0; ax < (ATT ? kAxes : 0); ++ax)
 #pragma unroll
                 for (int qq = 0; qq < kParAxis; ++qq) {
                     Acc* dst = qatt + (ax * s.n_dfa + t + qq) * K;
@@ -1425,6 +1458,77 @@ __global__ __launch_bounds__(kBlock) void k_scalar_stop(const double* __restrict
             s.istop = istop;
             if (istop != 0) s.done = 1;
         }
+    }
+}
+
+// Row-reordered attitude pass for K right-hand sides: S[t][12][K].
+template <typename T, typename Acc, int K>
+__global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
+    int64_t m, const T* __restrict__ att_sorted, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ tkey, const Acc* __restrict__ U, Acc* __restrict__ S,
+    const int64_t* __restrict__ wb, const Scalars* __restrict__ sc)
+{
+    constexpr int kAtt = kAxes * kParAxis;
+    uint32_t live = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) live |= ((sc[r].done || sc[r].beta_zero) ? 0u : 1u) << r;
+    if (live == 0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t rb = wb[wave], re = wb[wave + 1];
+    SegAcc<Acc, kAtt * K> seg;
+    auto emit = [S](int64_t t, const Acc (&tot)[kAtt * K]) {
+#pragma unroll
+        for (int j = 0; j < kAtt * K; ++j) S[t * kAtt * K + j] = tot[j];
+    };
+    for (int64_t r0 = rb; r0 < re; r0 += kWave) {
+        const int64_t k = r0 + lane;
+        const bool ok = k < re;
+        const int64_t kc = ok ? k : re - 1;
+        const int64_t t = ok ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
+        const int64_t i = ldnt(&perm[kc]);
+        Acc u[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) u[r] = (ok && ((live >> r) & 1u)) ? U[i * K + r] : (Acc)0;
+        Acc v[kAtt * K];
+#pragma unroll
+        for (int c = 0; c < kAtt; ++c) {
+            const Acc a = (Acc)ldnt(&att_sorted[c * m + kc]);
+#pragma unroll
+            for (int r = 0; r < K; ++r) v[c * K + r] = a * u[r];
+        }
+        seg_chunk(seg, t, v, lane, emit);
+    }
+    seg_finish(seg, lane, emit);
+}
+
+template <typename Acc, int K>
+__global__ __launch_bounds__(kBlock) void k_att_combine(const Acc* __restrict__ S, int64_t n_dfa,
+                                                         Acc* __restrict__ qatt,
+                                                         const Scalars* __restrict__ sc)
+{
+    constexpr int kAtt = kAxes * kParAxis;
+    uint32_t live = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) live |= ((sc[r].done || sc[r].beta_zero) ? 0u : 1u) << r;
+    if (live == 0) return;
+    const int64_t nt = n_dfa - kParAxis + 1;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < kAxes * n_dfa;
+         j += (int64_t)gridDim.x * kBlock) {
+        const int64_t ax = j / n_dfa, c = j - ax * n_dfa;
+        Acc sum[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) sum[r] = (Acc)0;
+#pragma unroll
+        for (int qq = 0; qq < kParAxis; ++qq) {
+            const int64_t t = c - qq;
+            if (t >= 0 && t < nt)
+#pragma unroll
+                for (int r = 0; r < K; ++r) sum[r] += S[(t * kAtt + ax * kParAxis + qq) * K + r];
+        }
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+            if ((live >> r) & 1u) qatt[j * K + r] += sum[r];
     }
 }
 

@@ -89,6 +89,8 @@ void dfree(V*& p)
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 constexpr int64_t kLdsInstrBudget = 64 * 1024;  // bytes of LDS for the instrumental histogram
+constexpr int64_t kLdsXBudget = 64 * 1024;      // bytes of LDS for aprod1's instrumental slice
+constexpr int kBlock1 = 512;                    // aprod1 workgroup size
 
 // Working vectors of one arithmetic precision of the LSQR loop.
 template <typename Acc>
@@ -150,7 +152,7 @@ struct lsqr_handle {
         int kmax = 0;
         double *U = nullptr, *V = nullptr, *W = nullptr, *Y = nullptr, *VP = nullptr, *Q = nullptr;
         double *gpart = nullptr, *part1 = nullptr, *partc = nullptr, *partdd = nullptr,
-               *partxx = nullptr;
+               *partxx = nullptr, *S = nullptr;
         Scalars* sc = nullptr;
         int32_t* flag = nullptr;
         hipGraphExec_t graph[9] = {};  // by K
@@ -165,8 +167,8 @@ struct lsqr_handle {
     int chunk = 16;
     int use_graph = 1;
     int profile = 0;
-    int att_mode = 0;    // 0: attitude scatter with device atomics, 1: row-reordered pass
-    int astro_scan = 1;  // 1: segmented scan per chunk, 0: accumulate-and-flush segments
+    int att_mode = 1;    // 0: attitude scatter with device atomics, 1: row-reordered pass
+    int astro_scan = 0;  // 1: segmented scan per chunk, 0: accumulate-and-flush segments
     double outer_tol = 1e-10;
     int ktile = 0;       // batched k-tile: 0 autotune, else 1, 2, 4 or 8
 
@@ -179,6 +181,20 @@ struct lsqr_handle {
 namespace {
 
 // ------------------------------------------------------------ launch helpers
+// aprod1 with the instrumental slice of x staged in LDS when it fits.
+template <typename T, typename Acc, typename VX, typename VY, int MODE>
+void launch_aprod1(const lsqr_handle* h, const VX* x, VY* y, const double* b, const Scalars* sc,
+                   double* part, hipStream_t st)
+{
+    const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(VX);
+    if (bytes <= kLdsXBudget)
+        hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, true>), dim3(h->nb1),
+                           dim3(kBlock1), (size_t)bytes, st, h->sv, x, y, b, sc, part);
+    else
+        hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, false>), dim3(h->nb1),
+                           dim3(kBlock1), 0, st, h->sv, x, y, b, sc, part);
+}
+
 // q += A^T u for the LSQR loop (and lsqr_aprod2): the main pass over the rows
 // in star order, the global-column second stage and, in the row-reordered
 // attitude mode, the attitude pass over the t-sorted rows.
@@ -218,8 +234,8 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
 {
     const int64_t n = h->sv.n;
     if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL((k_aprod1<T, Acc, Acc, Acc, A1_LSQR>), dim3(h->nb1), dim3(kBlock), 0, st,
-                       h->sv, (const Acc*)P.vp, P.u, (const double*)nullptr, h->sc, h->part1);
+    launch_aprod1<T, Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u, nullptr, h->sc, h->part1,
+                                            st);
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
     if (ev) (void)hipEventRecord(ev[2], st);
@@ -343,7 +359,8 @@ void release_path(Path<Acc>& P)
     P.ready = false;
 }
 
-lsqr_status upload_controls(lsqr_handle* h, int32_t itn_limit, double atol, double btol)
+lsqr_status upload_controls(lsqr_handle* h, int32_t itn_limit, double atol, double btol,
+                            double rel_ar = 0.0)
 {
     // The controls are written into the pinned mirror and copied as one block
     // with the rest of the (reset) state; the kernels then own the state.
@@ -353,7 +370,8 @@ lsqr_status upload_controls(lsqr_handle* h, int32_t itn_limit, double atol, doub
     s->btol = btol;
     s->ctol = h->conlim > 0.0 ? 1.0 / h->conlim : 0.0;
     s->itn_limit = itn_limit;
-    s->tests = h->tests;
+    s->tests = rel_ar > 0.0 ? 0 : h->tests;
+    s->rel_ar = rel_ar;
     s->inv_alpha = 1.0;
     HIP_TRY(hipMemcpyAsync(h->sc, s, sizeof(Scalars), hipMemcpyHostToDevice, h->stream));
     return LSQR_OK;
@@ -480,8 +498,9 @@ lsqr_status batch_alloc(lsqr_handle* h, int kmax)
         if (g) (void)hipGraphExecDestroy(g), g = nullptr;
     dfree(B.U); dfree(B.V); dfree(B.W); dfree(B.Y); dfree(B.VP); dfree(B.Q);
     dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
-    dfree(B.sc); dfree(B.flag);
+    dfree(B.sc); dfree(B.flag); dfree(B.S);
     B.kmax = 0;
+    LSQR_TRY(dalloc(&B.S, (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis * kmax));
     LSQR_TRY(dalloc(&B.U, m * kmax));
     LSQR_TRY(dalloc(&B.V, n * kmax));
     LSQR_TRY(dalloc(&B.W, n * kmax));
@@ -509,7 +528,7 @@ void batch_free(lsqr_handle* h)
         if (g) (void)hipGraphExecDestroy(g), g = nullptr;
     dfree(B.U); dfree(B.V); dfree(B.W); dfree(B.Y); dfree(B.VP); dfree(B.Q);
     dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
-    dfree(B.sc); dfree(B.flag);
+    dfree(B.sc); dfree(B.flag); dfree(B.S);
     B.kmax = 0;
 }
 
@@ -527,10 +546,23 @@ void batch_aprod2(lsqr_handle* h, hipStream_t st)
     auto& B = h->batch;
     int li = 0;
     const size_t lds = batch_lds<K>(h, &li);
-    hipLaunchKernelGGL((batched::k_aprod2<T, double, K>), dim3(h->nb2), dim3(kBlock), lds, st,
-                       h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
+    if (h->att_mode == 0)
+        hipLaunchKernelGGL((batched::k_aprod2<T, double, K, true>), dim3(h->nb2), dim3(kBlock), lds,
+                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
+    else
+        hipLaunchKernelGGL((batched::k_aprod2<T, double, K, false>), dim3(h->nb2), dim3(kBlock),
+                           lds, st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
     hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
                        (const double*)B.gpart, h->nb2, B.Q + h->sv.glob_base * K, B.sc);
+    if (h->att_mode != 0) {
+        const int64_t ns = (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis * K;
+        hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, ns, B.S, 0.0);
+        hipLaunchKernelGGL((batched::k_aprod2_att_sorted<T, double, K>), dim3(h->nb2), dim3(kBlock),
+                           0, st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->perm,
+                           (const int32_t*)h->tkey, (const double*)B.U, B.S, h->wb_att, B.sc);
+        hipLaunchKernelGGL((batched::k_att_combine<double, K>), dim3(h->nbc), dim3(kBlock), 0, st,
+                           (const double*)B.S, h->sv.n_dfa, B.Q + h->sv.att_base * K, B.sc);
+    }
 }
 
 template <typename T, int K>
@@ -831,16 +863,19 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     // grids
     const int64_t m = s.m, n = s.n;
     {
+        // aprod1 grid: resident workgroups of the LDS-staged kernel
+        const int64_t bytes = s.n_instr_cols * 8;
         int occ = 0;
-        if (h->value_type == LSQR_F64)
+        if (bytes <= kLdsXBudget)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ, k_aprod1<double, double, double, double, A1_LSQR>, kBlock, 0);
+                &occ, k_aprod1<double, double, double, double, A1_LSQR, kBlock1, true>, kBlock1,
+                (size_t)bytes);
         else
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ, k_aprod1<float, float, float, float, A1_LSQR>, kBlock, 0);
-        if (e != hipSuccess || occ <= 0) occ = 4;
+                &occ, k_aprod1<double, double, double, double, A1_LSQR, kBlock1, false>, kBlock1, 0);
+        if (e != hipSuccess || occ <= 0) occ = 2;
         h->nb1 = (int)std::max<int64_t>(
-            1, std::min<int64_t>((int64_t)h->num_cu * occ, cdiv(m, 2 * kBlock)));
+            1, std::min<int64_t>((int64_t)h->num_cu * occ, cdiv(m, 2 * kBlock1)));
     }
     {
         // aprod2 grid: as many resident workgroups as the LDS histogram allows
@@ -1014,13 +1049,11 @@ lsqr_status lsqr_aprod1(lsqr_handle* h, const double* x, double* y)
     LSQR_TRY(check_handle(h));
     if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
     if (h->value_type == LSQR_F64)
-        hipLaunchKernelGGL((k_aprod1<double, double, double, double, A1_ACCUM>), dim3(h->nb1),
-                           dim3(kBlock), 0, h->user_stream, h->sv, x, y, (const double*)nullptr,
-                           (const Scalars*)nullptr, (double*)nullptr);
+        launch_aprod1<double, double, double, double, A1_ACCUM>(h, x, y, nullptr, nullptr, nullptr,
+                                                                h->user_stream);
     else
-        hipLaunchKernelGGL((k_aprod1<float, double, double, double, A1_ACCUM>), dim3(h->nb1),
-                           dim3(kBlock), 0, h->user_stream, h->sv, x, y, (const double*)nullptr,
-                           (const Scalars*)nullptr, (double*)nullptr);
+        launch_aprod1<float, double, double, double, A1_ACCUM>(h, x, y, nullptr, nullptr, nullptr,
+                                                               h->user_stream);
     HIP_TRY(hipGetLastError());
     return LSQR_OK;
 }
@@ -1100,11 +1133,13 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
     double bnorm = 0.0;
     Scalars last{};
     for (outer = 1; outer <= outer_limit; ++outer) {
-        LSQR_TRY(upload_controls(h, itn_limit, atol, btol));
+        // Each correction problem min ||A d - r|| has a residual dominated by the
+        // irreducible least-squares residual, so its inner solve stops on the
+        // relative decrease of ||Abar^T r|| (tolerance atol) or the itn limit.
+        LSQR_TRY(upload_controls(h, itn_limit, 0.0, 0.0, std::max(atol, 1e-300)));
         // FP64 residual of the full problem, stored as the FP32 start vector
-        hipLaunchKernelGGL((k_aprod1<float, double, double, float, A1_RESID>), dim3(h->nb1),
-                           dim3(kBlock), 0, h->stream, h->sv, (const double*)x, P.u, b,
-                           (const Scalars*)nullptr, h->part1);
+        launch_aprod1<float, double, double, float, A1_RESID>(h, (const double*)x, P.u, b, nullptr,
+                                                              h->part1, h->stream);
         launch_init<float, float>(h, P, h->stream);
         HIP_TRY(hipGetLastError());
         LSQR_TRY(read_scalars(h));
@@ -1138,9 +1173,8 @@ lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32
     if (k < 1 || k > 4096) return fail(LSQR_E_INVALID, "k must be in [1, 4096]");
     if (itn_limit < 0) return fail(LSQR_E_INVALID, "itn_limit must be >= 0");
     if (!(atol >= 0.0) || !(btol >= 0.0)) return fail(LSQR_E_INVALID, "atol, btol must be >= 0");
-    if (h->att_mode != 0)
-        return fail(LSQR_E_UNSUPPORTED, "batched solves use the atomic attitude scatter");
     HIP_TRY(hipStreamSynchronize(h->user_stream));
+    LSQR_TRY(ensure_att(h));
     if (h->value_type == LSQR_F64)
         LSQR_TRY(solve_batched<double>(h, B, X, k, itn_limit, atol, btol, infos));
     else

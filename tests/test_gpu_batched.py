@@ -34,15 +34,17 @@ def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
+@pytest.mark.parametrize("att_mode", [1, 0])
 @pytest.mark.parametrize("ktile", [1, 2, 4, 8])
-def test_batched_fixed_iterations(torch_cuda, c0, ktile):
+def test_batched_fixed_iterations(torch_cuda, c0, ktile, att_mode):
     torch = torch_cuda
     from paper_2308_00778_amd import LsqrSystem
 
     S, o, B = c0
     itn = 40
-    say(f"batched parity: c0 k=5 ktile={ktile} itn={itn}")
+    say(f"batched parity: c0 k=5 ktile={ktile} att_mode={att_mode} itn={itn}")
     g = LsqrSystem.from_host(S, "cuda:0")
+    g.set_option("att_mode", att_mode)
     g.set_option("tests", 0)
     g.set_option("ktile", ktile)
     X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(B)).cuda(), itn, 0.0, 0.0)

@@ -93,7 +93,7 @@ def test_aprod1_parity(torch_cuda, name):
     assert np.all(np.abs(got - want) <= 32 * EPS * bound + 1e-300)
 
 
-VARIANTS = [(0, 1), (1, 0), (0, 0), (1, 1)]  # (att_mode, astro_scan)
+VARIANTS = [(1, 0), (0, 1), (0, 0), (1, 1)]  # (att_mode, astro_scan); first = default
 
 
 @pytest.mark.parametrize("variant", VARIANTS, ids=[f"att{a}_scan{b}" for a, b in VARIANTS])
@@ -144,7 +144,7 @@ def _b(S, o, rhs=0):
                                        ("one_star", 15), ("few_rows", 15), ("wide_instr", 60)])
 @pytest.mark.parametrize("graph", [1, 0])
 def test_solve_fixed_iterations(torch_cuda, name, itn, graph):
-    _solve_fixed(torch_cuda, name, itn, graph, (0, 1))
+    _solve_fixed(torch_cuda, name, itn, graph, VARIANTS[0])
 
 
 @pytest.mark.parametrize("variant", VARIANTS[1:], ids=[f"att{a}_scan{b}" for a, b in VARIANTS[1:]])
@@ -194,10 +194,13 @@ def test_solve_stopping_rules(torch_cuda):
     g.close()
     assert info.istop == i_ref.istop and abs(info.itn - i_ref.itn) <= 1, (info, i_ref)
     assert rel_inf(xg, x_ref) <= 1e-10
-    # converged: normal-equation residual of the scaled problem
+    # converged: normal-equation residual of the scaled problem, recomputed
+    # explicitly. Forming r = b - A x in FP64 (||b|| ~ 1.5e3, ||r|| ~ 3e-4)
+    # leaves a floor of about eps ||A|| ||x|| / ||r|| ~ 1e-9 on this ratio; an
+    # unconverged iterate (10 iterations) sits near 1e-5.
     p = o.precond()
     r = b - o.aprod1(xg)
-    assert np.linalg.norm(p * o.aprod2(r)) <= 1e-11 * info.anorm * np.linalg.norm(r)
+    assert np.linalg.norm(p * o.aprod2(r)) <= 1e-9 * info.anorm * np.linalg.norm(r)
 
 
 def test_zero_rhs_and_zero_iterations(torch_cuda):
@@ -214,16 +217,20 @@ def test_zero_rhs_and_zero_iterations(torch_cuda):
 
 
 def test_no_preconditioning(torch_cuda):
+    # Without column scaling the iterates of any two FP64 LSQR codes part early
+    # on this system (oracle vs SciPy: 4.5e-3 apart at k = 20), so the check is
+    # on the converged least-squares solution, which is unique (kappa = 45).
     torch = torch_cuda
     S, o = system("ragged")
     b = _b(S, o)
-    x_ref, _ = o.lsqr(b, 80, atol=0.0, btol=0.0, conlim=0.0, tests=False, precondition=False)
-    say("solve without preconditioning: ragged itn=80")
+    x_ref, i_ref = o.lsqr(b, 3000, atol=1e-14, btol=1e-14, conlim=0.0, precondition=False)
+    say(f"solve without preconditioning: ragged, to convergence (oracle itn={i_ref.itn})")
     g = gpu_system(torch, S, precondition=False)
-    g.set_option("tests", 0)
-    x, info = g.solve(torch.from_numpy(b).cuda(), 80, atol=0.0, btol=0.0)
+    g.set_option("conlim", 0)
+    x, info = g.solve(torch.from_numpy(b).cuda(), 3000, atol=1e-14, btol=1e-14)
     xg = x.cpu().numpy()
     g.close()
+    assert info.istop in (1, 2, 4, 5) and info.itn < 3000
     assert rel_inf(xg, x_ref) <= 1e-10
 
 
