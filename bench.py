@@ -119,6 +119,40 @@ def refine_leg(cfg: int, dev):
     return out
 
 
+def attitude_ab(dev, cfg: int = 1, itn: int = 20):
+    """aprod1 / aprod2 times of the attitude variants on one system: device
+    atomics scatter vs the row-reordered pass, each astrometric reduction."""
+    import torch
+
+    import synth
+    from paper_2308_00778_amd import LsqrSystem
+
+    spec = synth.CONFIGS[cfg]
+    arrays, first = synth.device_system(spec, dev)
+    m = int(first[-1])
+    g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
+                   n_instr_cols=spec.n_instr_cols)
+    b = synth.device_noise(spec, m, 0, dev)
+    g.aprod1(synth.device_x_true(spec, dev), b)
+    out = {}
+    for att, scan in ((1, 0), (1, 1), (0, 0), (0, 1)):
+        g.set_option("att_mode", att)
+        g.set_option("astro_scan", scan)
+        g.set_option("tests", 0)
+        g.set_option("profile", 1)
+        g.solve(b, 2, atol=0.0, btol=0.0)
+        x, info = g.solve(b, itn, atol=0.0, btol=0.0)
+        kt = g.kernel_times()
+        a1, a2 = kt["aprod1_ms"] / kt["aprod1_n"], kt["aprod2_ms"] / kt["aprod2_n"]
+        key = ("reordered" if att else "atomics") + ("_scan" if scan else "_flush")
+        out[key] = {"aprod1_ms": a1, "aprod2_ms": a2,
+                    "aprod2_GBps": BYTES_PER_ROW["aprod2"] * m / (a2 * 1e-3) / 1e9,
+                    "rnorm": info.rnorm}
+        log(f"{key}: aprod1 {a1:.3f} ms, aprod2 {a2:.3f} ms")
+    g.close()
+    print(json.dumps({"attitude_ab": out, "rows": m, "iterations": itn}))
+
+
 def copy_calibration(dev, gib: float = 4.0, reps: int = 5):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -142,6 +176,8 @@ def main():
     ap.add_argument("--forms", default="refine",
                     help="comma list of extra legs: refine (FP32 + FP64 refinement), none")
     ap.add_argument("--copy", action="store_true", help="only run the copy calibration")
+    ap.add_argument("--attitude-ab", action="store_true",
+                    help="only time the attitude variants of aprod2")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding "
@@ -156,6 +192,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.copy:
         copy_calibration(dev)
+        return
+    if args.attitude_ab:
+        attitude_ab(dev, args.config)
         return
     spec = synth.CONFIGS[args.config]
     assert spec.value_dtype == "f64", "the FP64 bench runs on an FP64 workload"

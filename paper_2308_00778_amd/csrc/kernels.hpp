@@ -187,12 +187,17 @@ enum Aprod1Mode : int {
 // RESID modes). NT threads per block. LDSX: the instrumental slice of x
 // (n_instr_cols values) is first copied into LDS, so that the six random
 // instrumental gathers per row hit LDS instead of L2.
+// ys (optional): y is also written in the attitude-sorted row order,
+// ys[invperm[i]] = y[i], so that the reordered attitude pass of aprod2 reads
+// it sequentially instead of gathering it.
 template <typename T, typename Acc, typename VX, typename VY, int MODE, int NT = kBlock,
           bool LDSX = false>
 __global__ __launch_bounds__(NT) void k_aprod1(SysView s, const VX* __restrict__ x,
                                                 VY* __restrict__ y, const double* __restrict__ b,
                                                 const Scalars* __restrict__ sc,
-                                                double* __restrict__ part)
+                                                double* __restrict__ part,
+                                                const int32_t* __restrict__ invperm = nullptr,
+                                                VY* __restrict__ ys = nullptr)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[NT / kWave];
@@ -216,23 +221,17 @@ __global__ __launch_bounds__(NT) void k_aprod1(SysView s, const VX* __restrict__
         if (MODE == A1_ACCUM) {
             y[i0] = (VY)((Acc)y[i0] + d0);
             if (has1) y[i1] = (VY)((Acc)y[i1] + d1);
-        } else if (MODE == A1_LSQR) {
-            const VY n0 = (VY)(d0 - coef * (Acc)y[i0]);
-            y[i0] = n0;
-            ssq += (double)n0 * (double)n0;
-            if (has1) {
-                const VY n1 = (VY)(d1 - coef * (Acc)y[i1]);
-                y[i1] = n1;
-                ssq += (double)n1 * (double)n1;
-            }
         } else {
-            const VY n0 = (VY)((Acc)b[i0] - d0);
+            const VY n0 = MODE == A1_LSQR ? (VY)(d0 - coef * (Acc)y[i0]) : (VY)((Acc)b[i0] - d0);
             y[i0] = n0;
             ssq += (double)n0 * (double)n0;
+            if (ys) ys[ldnt(&invperm[i0])] = n0;
             if (has1) {
-                const VY n1 = (VY)((Acc)b[i1] - d1);
+                const VY n1 =
+                    MODE == A1_LSQR ? (VY)(d1 - coef * (Acc)y[i1]) : (VY)((Acc)b[i1] - d1);
                 y[i1] = n1;
                 ssq += (double)n1 * (double)n1;
+                if (ys) ys[ldnt(&invperm[i1])] = n1;
             }
         }
     }
@@ -385,11 +384,14 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const VU* __restri
         for (int j = 0; j < kAstro; ++j) q[kAstro * star + j] += tot[j];
     };
 
-    for (int64_t r0 = rb; r0 < re; r0 += kWave) {
+    // Chunks start on 64-row boundaries so that every coefficient stream is
+    // read in whole cache lines; lanes before rb (owned by the previous wave)
+    // take the first row's star with zero contributions.
+    for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
         const int64_t i = r0 + lane;
-        const bool ok = i < re;
-        const int64_t ic = ok ? i : re - 1;
-        const int64_t st = ok ? ldnt(&s.star[ic]) : kNoStar;
+        const bool ok = i >= rb && i < re;
+        const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
+        const int64_t st = i < re ? ldnt(&s.star[ic]) : kNoStar;
         const int64_t t = ATT ? ldnt(&s.att[ic]) : 0;
         T a[kPar];
 #pragma unroll
@@ -854,6 +856,25 @@ __global__ __launch_bounds__(kBlock) void k_att_keys(const int64_t* __restrict__
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_invert_perm(const int32_t* __restrict__ perm, int64_t m,
+                                                         int32_t* __restrict__ invperm)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * kBlock)
+        invperm[perm[k]] = (int32_t)k;
+}
+
+// us[k] = u[perm[k]]
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_gather_perm(const V* __restrict__ u,
+                                                         const int32_t* __restrict__ perm,
+                                                         int64_t m, V* __restrict__ us)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m;
+         k += (int64_t)gridDim.x * kBlock)
+        us[k] = u[perm[k]];
+}
+
 // att_sorted[c][k] = values[kOffAtt + c][perm[k]], c < 12
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val, int64_t m,
@@ -871,7 +892,9 @@ __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val
 
 // S[t][12] = sum over rows with attitude start t of a_att * u, over t-aligned
 // per-wave ranges of the sorted rows (each t owned by one wave: plain stores).
-template <typename T, typename Acc, typename VU>
+// SEQ: u is already in sorted order (written by aprod1), else gathered as
+// u[perm[k]].
+template <typename T, typename Acc, typename VU, bool SEQ = false>
 __global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
     int64_t m, const T* __restrict__ att_sorted, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ tkey, const VU* __restrict__ u, Acc* __restrict__ S,
@@ -887,13 +910,14 @@ __global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
 #pragma unroll
         for (int j = 0; j < kAtt; ++j) S[t * kAtt + j] = tot[j];
     };
-    for (int64_t r0 = rb; r0 < re; r0 += kWave) {
+    for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
         const int64_t k = r0 + lane;
-        const bool ok = k < re;
-        const int64_t kc = ok ? k : re - 1;
-        const int64_t t = ok ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
-        const int32_t i = ldnt(&perm[kc]);
-        const Acc ui = ok ? (Acc)u[i] : (Acc)0;
+        const bool ok = k >= rb && k < re;
+        const int64_t kc = k < rb ? rb : (k < re ? k : re - 1);
+        const int64_t t = k < re ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
+        Acc ui = (Acc)0;
+        if (SEQ) ui = ok ? (Acc)ldnt(&u[kc]) : (Acc)0;
+        else ui = ok ? (Acc)u[ldnt(&perm[kc])] : (Acc)0;
         Acc v[kAtt];
 #pragma unroll
         for (int c = 0; c < kAtt; ++c) v[c] = (Acc)ldnt(&att_sorted[c * m + kc]) * ui;
@@ -1100,11 +1124,14 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const Acc* __restr
 #pragma unroll
         for (int j = 0; j < kAstro * K; ++j) dst[j] += tot[j];
     };
-    for (int64_t r0 = rb; r0 < re; r0 += kWave) {
+    // Chunks start on 64-row boundaries so that every coefficient stream is
+    // read in whole cache lines; lanes before rb (owned by the previous wave)
+    // take the first row's star with zero contributions.
+    for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
         const int64_t i = r0 + lane;
-        const bool ok = i < re;
-        const int64_t ic = ok ? i : re - 1;
-        const int64_t st = ok ? ldnt(&s.star[ic]) : kNoStar;
+        const bool ok = i >= rb && i < re;
+        const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
+        const int64_t st = i < re ? ldnt(&s.star[ic]) : kNoStar;
         const int64_t t = ATT ? ldnt(&s.att[ic]) : 0;
         T a[kPar];
 #pragma unroll
@@ -1481,11 +1508,11 @@ __global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
 #pragma unroll
         for (int j = 0; j < kAtt * K; ++j) S[t * kAtt * K + j] = tot[j];
     };
-    for (int64_t r0 = rb; r0 < re; r0 += kWave) {
+    for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
         const int64_t k = r0 + lane;
-        const bool ok = k < re;
-        const int64_t kc = ok ? k : re - 1;
-        const int64_t t = ok ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
+        const bool ok = k >= rb && k < re;
+        const int64_t kc = k < rb ? rb : (k < re ? k : re - 1);
+        const int64_t t = k < re ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
         const int64_t i = ldnt(&perm[kc]);
         Acc u[K];
 #pragma unroll

@@ -100,6 +100,7 @@ struct Path {
     Acc* q = nullptr;      // [n] aprod2 accumulator (zero between uses)
     Acc* gpart = nullptr;  // [nb2] global-column partials
     Acc* S = nullptr;      // [(n_dfa-3)*12] attitude partials of the reordered pass
+    Acc* us = nullptr;     // [m] u~ in attitude-sorted row order (reordered pass)
     size_t lds = 0;        // dynamic LDS bytes of aprod2
     int lds_instr = 0;
     hipGraphExec_t graph = nullptr;
@@ -142,6 +143,7 @@ struct lsqr_handle {
     // row-reordered attitude pass (built on first use)
     int32_t* perm = nullptr;      // [m] rows sorted by attitude start
     int32_t* tkey = nullptr;      // [m] attitude start of each sorted row
+    int32_t* invperm = nullptr;   // [m] sorted position of each row
     void* att_sorted = nullptr;   // [12][m] attitude coefficients in sorted order
     int64_t* wb_att = nullptr;    // [nb2*4 + 1] t-aligned ranges of the sorted rows
     double* S_raw = nullptr;      // [(n_dfa-3)*12] partials of lsqr_aprod2
@@ -184,23 +186,26 @@ namespace {
 // aprod1 with the instrumental slice of x staged in LDS when it fits.
 template <typename T, typename Acc, typename VX, typename VY, int MODE>
 void launch_aprod1(const lsqr_handle* h, const VX* x, VY* y, const double* b, const Scalars* sc,
-                   double* part, hipStream_t st)
+                   double* part, hipStream_t st, VY* ys = nullptr)
 {
     const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(VX);
+    const int32_t* ip = ys ? h->invperm : nullptr;
     if (bytes <= kLdsXBudget)
         hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, true>), dim3(h->nb1),
-                           dim3(kBlock1), (size_t)bytes, st, h->sv, x, y, b, sc, part);
+                           dim3(kBlock1), (size_t)bytes, st, h->sv, x, y, b, sc, part, ip, ys);
     else
         hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, false>), dim3(h->nb1),
-                           dim3(kBlock1), 0, st, h->sv, x, y, b, sc, part);
+                           dim3(kBlock1), 0, st, h->sv, x, y, b, sc, part, ip, ys);
 }
 
 // q += A^T u for the LSQR loop (and lsqr_aprod2): the main pass over the rows
 // in star order, the global-column second stage and, in the row-reordered
 // attitude mode, the attitude pass over the t-sorted rows.
+// us: u in attitude-sorted order (read sequentially by the attitude pass), or
+// nullptr to gather u through the permutation.
 template <typename T, typename Acc>
 void launch_aprod2(lsqr_handle* h, const Acc* u, Acc* q, Acc* gpart, Acc* S, size_t lds,
-                   int lds_instr, const Scalars* sc, hipStream_t st)
+                   int lds_instr, const Scalars* sc, hipStream_t st, const Acc* us = nullptr)
 {
     const dim3 g(h->nb2), b(kBlock);
     const bool att = h->att_mode == 0;
@@ -220,9 +225,14 @@ void launch_aprod2(lsqr_handle* h, const Acc* u, Acc* q, Acc* gpart, Acc* S, siz
     if (!att) {
         const int64_t ns = (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis;
         hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), b, 0, st, ns, S, (Acc)0);
-        hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc>), g, b, 0, st, h->sv.m,
-                           (const T*)h->att_sorted, (const int32_t*)h->perm,
-                           (const int32_t*)h->tkey, u, S, h->wb_att, sc);
+        if (us)
+            hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, true>), g, b, 0, st, h->sv.m,
+                               (const T*)h->att_sorted, (const int32_t*)h->perm,
+                               (const int32_t*)h->tkey, us, S, h->wb_att, sc);
+        else
+            hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, false>), g, b, 0, st, h->sv.m,
+                               (const T*)h->att_sorted, (const int32_t*)h->perm,
+                               (const int32_t*)h->tkey, u, S, h->wb_att, sc);
         hipLaunchKernelGGL((k_att_combine<Acc>), dim3(h->nbc), b, 0, st, (const Acc*)S,
                            h->sv.n_dfa, q + h->sv.att_base, sc);
     }
@@ -234,12 +244,13 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
 {
     const int64_t n = h->sv.n;
     if (ev) (void)hipEventRecord(ev[0], st);
+    Acc* us = h->att_mode ? P.us : nullptr;
     launch_aprod1<T, Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u, nullptr, h->sc, h->part1,
-                                            st);
+                                            st, us);
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
     if (ev) (void)hipEventRecord(ev[2], st);
-    launch_aprod2<T, Acc>(h, P.u, P.q, P.gpart, P.S, P.lds, P.lds_instr, h->sc, st);
+    launch_aprod2<T, Acc>(h, P.u, P.q, P.gpart, P.S, P.lds, P.lds_instr, h->sc, st, us);
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
                        h->sc, h->partc);
@@ -251,14 +262,20 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
 }
 
 // Initialisation given u~ (already written) and ||u~||^2 partials in part1.
+// u_sorted_ready: u~ was also written in sorted order (residual kernel).
 template <typename T, typename Acc>
-void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st)
+void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st, bool u_sorted_ready = false)
 {
     const int64_t n = h->sv.n;
     hipLaunchKernelGGL(k_scalar_init_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, P.q, (Acc)0);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->v, 0.0);
-    launch_aprod2<T, Acc>(h, P.u, P.q, P.gpart, P.S, P.lds, P.lds_instr, h->sc, st);
+    Acc* us = h->att_mode ? P.us : nullptr;
+    if (us && !u_sorted_ready)
+        hipLaunchKernelGGL((k_gather_perm<Acc>), dim3(std::min<int64_t>(cdiv(h->sv.m, kBlock), 65536)),
+                           dim3(kBlock), 0, st, (const Acc*)P.u, (const int32_t*)h->perm, h->sv.m,
+                           us);
+    launch_aprod2<T, Acc>(h, P.u, P.q, P.gpart, P.S, P.lds, P.lds_instr, h->sc, st, us);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
                        h->sc, h->partc);
     hipLaunchKernelGGL(k_scalar_init_alpha, dim3(1), dim3(kBlock), 0, st, h->partc, h->nbc, h->sc);
@@ -276,6 +293,7 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     LSQR_TRY(dalloc(&P.q, n));
     LSQR_TRY(dalloc(&P.gpart, h->nb2));
     LSQR_TRY(dalloc(&P.S, (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis));
+    LSQR_TRY(dalloc(&P.us, m));
     const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(Acc);
     P.lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
     P.lds = P.lds_instr ? (size_t)bytes : 0;
@@ -303,6 +321,7 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
     while (bits < 31 && ((int64_t)1 << bits) < h->sv.n_dfa) ++bits;
     LSQR_TRY(dalloc(&h->perm, m));
     LSQR_TRY(dalloc(&h->tkey, m));
+    LSQR_TRY(dalloc(&h->invperm, m));
     LSQR_TRY(dalloc(&h->wb_att, (int64_t)h->nb2 * kWavesPerBlock + 1));
     LSQR_TRY(dalloc(&h->S_raw, (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis));
     T* att_sorted = nullptr;
@@ -325,6 +344,8 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
         hipLaunchKernelGGL((k_att_gather<T>), dim3(std::min<int64_t>(cdiv(m, kBlock), 65536)),
                            dim3(kBlock), 0, st, (const T*)h->sv.val, m, (const int32_t*)h->perm,
                            att_sorted);
+        hipLaunchKernelGGL(k_invert_perm, dim3(std::min<int64_t>(cdiv(m, kBlock), 65536)),
+                           dim3(kBlock), 0, st, (const int32_t*)h->perm, m, h->invperm);
         const int64_t nw = (int64_t)h->nb2 * kWavesPerBlock;
         hipLaunchKernelGGL((k_wave_bounds<int32_t>), dim3(cdiv(nw + 1, kBlock)), dim3(kBlock), 0, st,
                            (const int32_t*)h->tkey, m, nw, h->wb_att);
@@ -356,6 +377,7 @@ void release_path(Path<Acc>& P)
     dfree(P.q);
     dfree(P.gpart);
     dfree(P.S);
+    dfree(P.us);
     P.ready = false;
 }
 
@@ -974,6 +996,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h)
     dfree(h->wb);
     dfree(h->perm);
     dfree(h->tkey);
+    dfree(h->invperm);
     dfree(h->wb_att);
     dfree(h->S_raw);
     if (h->att_sorted) (void)hipFree(h->att_sorted);
@@ -1139,8 +1162,9 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
         LSQR_TRY(upload_controls(h, itn_limit, 0.0, 0.0, std::max(atol, 1e-300)));
         // FP64 residual of the full problem, stored as the FP32 start vector
         launch_aprod1<float, double, double, float, A1_RESID>(h, (const double*)x, P.u, b, nullptr,
-                                                              h->part1, h->stream);
-        launch_init<float, float>(h, P, h->stream);
+                                                              h->part1, h->stream,
+                                                              h->att_mode ? P.us : nullptr);
+        launch_init<float, float>(h, P, h->stream, true);
         HIP_TRY(hipGetLastError());
         LSQR_TRY(read_scalars(h));
         if (outer == 1) bnorm = h->sc_host->bnorm;
