@@ -135,7 +135,7 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
     b = synth.device_noise(spec, m, 0, dev)
     g.aprod1(synth.device_x_true(spec, dev), b)
     out = {}
-    for att, scan in ((1, 0), (1, 1), (0, 0), (0, 1)):
+    for att, scan in ((1, 0), (2, 0), (1, 1), (0, 0)):
         g.set_option("att_mode", att)
         g.set_option("astro_scan", scan)
         g.set_option("tests", 0)
@@ -144,13 +144,81 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
         x, info = g.solve(b, itn, atol=0.0, btol=0.0)
         kt = g.kernel_times()
         a1, a2 = kt["aprod1_ms"] / kt["aprod1_n"], kt["aprod2_ms"] / kt["aprod2_n"]
-        key = ("reordered" if att else "atomics") + ("_scan" if scan else "_flush")
+        key = ("atomics", "reordered_gather", "reordered_u_written_sorted")[att] + \
+            ("_scan" if scan else "_flush")
         out[key] = {"aprod1_ms": a1, "aprod2_ms": a2,
                     "aprod2_GBps": BYTES_PER_ROW["aprod2"] * m / (a2 * 1e-3) / 1e9,
                     "rnorm": info.rnorm}
         log(f"{key}: aprod1 {a1:.3f} ms, aprod2 {a2:.3f} ms")
     g.close()
     print(json.dumps({"attitude_ab": out, "rows": m, "iterations": itn}))
+
+
+def batched_leg(cfg: int, dev, singles: int = 2):
+    """k noise realisations of b solved together (to convergence, atol = btol =
+    1e-12) against single-RHS solves of the same right-hand sides."""
+    import torch
+
+    import synth
+    from paper_2308_00778_amd import LsqrSystem
+
+    spec = synth.CONFIGS[cfg]
+    k = spec.n_rhs
+    t0 = time.perf_counter()
+    arrays, first = synth.device_system(spec, dev)
+    m = int(first[-1])
+    g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
+                   n_instr_cols=spec.n_instr_cols)
+    xt = synth.device_x_true(spec, dev)
+    B = torch.empty((m, k), dtype=torch.float64, device=dev)
+    for j in range(k):
+        bj = synth.device_noise(spec, m, j, dev)
+        g.aprod1(xt, bj)
+        B[:, j] = bj
+        del bj
+    torch.cuda.synchronize()
+    log(f"batched leg: m={m} n={g.n} k={k} ready in {time.perf_counter() - t0:.1f} s")
+    # autotune (first call) outside the timed region
+    g.set_option("tests", 0)
+    g.solve_batched(B[:, :8].contiguous(), 2, 0.0, 0.0)
+    g.set_option("tests", 1)
+    tune = g.batch_tuning()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X, infos = g.solve_batched(B, 500, 1e-12, 1e-12)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t1
+    rhs_itn = sum(i.itn for i in infos)
+    # single-RHS solves of the first right-hand sides, same tolerances
+    t_single, single_itn, err = 0.0, 0, 0.0
+    for j in range(singles):
+        bj = B[:, j].contiguous()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        xj, ij = g.solve(bj, 500, 1e-12, 1e-12)
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t2
+        single_itn += ij.itn
+        err = max(err, rel_inf(X[:, j], xj))
+    per_rhs_iter_single = t_single / single_itn
+    out = {
+        "workload": f"{spec.n_stars} stars x {spec.obs_lo} obs = {m} rows x {g.n} unknowns, "
+                    f"FP64, k = {k} noise realisations of b",
+        "k": k, "k_tile": tune["k_tile"], "autotune_ms_per_rhs_iter": tune["ms_per_rhs_iter"],
+        "batched_seconds": t_batch, "rhs_iterations": rhs_itn,
+        "rhs_iter_per_s": rhs_itn / t_batch,
+        "itn_per_rhs": [i.itn for i in infos], "istop": sorted({i.istop for i in infos}),
+        "single_rhs_iter_per_s": 1.0 / per_rhs_iter_single,
+        "speedup_vs_single": (rhs_itn / t_batch) * per_rhs_iter_single,
+        "max_rel_inf_err_vs_single": err,
+    }
+    log(f"batched leg: {rhs_itn} RHS-iterations in {t_batch:.2f} s "
+        f"({out['rhs_iter_per_s']:.1f}/s, single {out['single_rhs_iter_per_s']:.1f}/s, "
+        f"k_tile {tune['k_tile']}), err vs single {err:.2e}")
+    g.close()
+    del arrays, B, X
+    torch.cuda.empty_cache()
+    return out
 
 
 def copy_calibration(dev, gib: float = 4.0, reps: int = 5):
@@ -173,8 +241,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="refine",
-                    help="comma list of extra legs: refine (FP32 + FP64 refinement), none")
+    ap.add_argument("--forms", default="refine,batched",
+                    help="comma list of extra legs: refine (FP32 + FP64 refinement), "
+                         "batched (k right-hand sides), none")
     ap.add_argument("--copy", action="store_true", help="only run the copy calibration")
     ap.add_argument("--attitude-ab", action="store_true",
                     help="only time the attitude variants of aprod2")
@@ -268,6 +337,8 @@ def main():
     forms = [f for f in args.forms.split(",") if f and f != "none"]
     if "refine" in forms:
         result["fp32_refine"] = refine_leg(2, dev)
+    if "batched" in forms:
+        result["batched"] = batched_leg(3, dev)
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample ...")
         result["cpu_baseline"] = cpu_baseline(spec)

@@ -113,14 +113,19 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *   LSQR_OPT_OUTER_TOL    refinement: stop when ||d||_inf <= tol ||x||_inf
  *                         (default 1e-10)
  *   LSQR_OPT_ATT_MODE     attitude part of aprod2: 1 (default) a second pass over
- *                         the rows sorted by attitude start (segmented sums, no
- *                         atomics; costs a sorted copy of the 12 attitude
- *                         coefficients and two int32 per row, built on first
- *                         use, needs n_rows < 2^31); 0 scatter-add with device
- *                         atomics (no extra memory, about 8x slower on MI355X)
+ *                         the rows in (row block, attitude start) order (segmented
+ *                         sums, no atomics; costs a reordered copy of the 12
+ *                         attitude coefficients and three int32 per row, built
+ *                         on first use, needs n_rows < 2^31), u gathered through
+ *                         the permutation; 2 the same pass, with aprod1 also
+ *                         writing u in the reordered order; 0 scatter-add with
+ *                         device atomics (no extra memory, about 8x slower)
  *   LSQR_OPT_ASTRO_SCAN   astrometric part of aprod2: 0 (default) running
  *                         per-lane partials reduced only where a star ends;
  *                         1 a segmented scan over every 64-row chunk
+ *   LSQR_OPT_ATT_GROUP_ROWS  rows per block of the (row block, attitude start)
+ *                         order (default 12,582,912: an FP64 row vector slice of
+ *                         96 MB); settable only before the first solve or aprod2
  *   LSQR_OPT_KTILE        batched solves: right-hand sides advanced together per
  *                         pass over A (1, 2, 4, 8), 0 (default) = autotune once
  *                         per handle
@@ -134,6 +139,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_ATT_MODE 7
 #define LSQR_OPT_ASTRO_SCAN 8
 #define LSQR_OPT_KTILE 9
+#define LSQR_OPT_ATT_GROUP_ROWS 10
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
 
 /* aprod mode 1, Eq. (2): y[m] += A x[n] with the raw (unscaled) A.

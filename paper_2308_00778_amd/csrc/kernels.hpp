@@ -845,13 +845,18 @@ __global__ __launch_bounds__(kBlock) void k_make_p(int64_t n, double* __restrict
 // Rows sorted by their attitude start t (a stable radix sort at set-up) turn
 // the attitude scatter into a segmented reduction: every row with the same t
 // contributes to the same 3 x 4 columns.
+// Sort key of row i: (row block, attitude start). Rows are grouped into
+// contiguous blocks of group_rows rows and sorted by t inside each block, so
+// that the u values one stretch of the sorted order touches lie in one block
+// (a slice small enough to stay in the GPU's last-level cache).
 __global__ __launch_bounds__(kBlock) void k_att_keys(const int64_t* __restrict__ att, int64_t m,
+                                                      int64_t group_rows, int64_t nt,
                                                       int32_t* __restrict__ keys,
                                                       int32_t* __restrict__ rows)
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * kBlock) {
-        keys[i] = (int32_t)att[i];
+        keys[i] = (int32_t)((i / group_rows) * nt + att[i]);
         rows[i] = (int32_t)i;
     }
 }
@@ -926,10 +931,11 @@ __global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
     seg_finish(seg, lane, emit);
 }
 
-// q[att_base + a n_dfa + c] += sum_q S[c - q][a][q] over valid starts.
+// q[att_base + a n_dfa + c] += sum over row blocks g and parameters q of
+// S[g][c - q][a][q] (valid starts only). S holds ngroups * nt segments.
 template <typename Acc>
 __global__ __launch_bounds__(kBlock) void k_att_combine(const Acc* __restrict__ S, int64_t n_dfa,
-                                                         Acc* __restrict__ qatt,
+                                                         int64_t ngroups, Acc* __restrict__ qatt,
                                                          const Scalars* __restrict__ sc)
 {
     constexpr int kAtt = kAxes * kParAxis;
@@ -939,10 +945,12 @@ __global__ __launch_bounds__(kBlock) void k_att_combine(const Acc* __restrict__ 
          j += (int64_t)gridDim.x * kBlock) {
         const int64_t ax = j / n_dfa, c = j - ax * n_dfa;
         Acc sum = (Acc)0;
+        for (int64_t g = 0; g < ngroups; ++g) {
 #pragma unroll
-        for (int qq = 0; qq < kParAxis; ++qq) {
-            const int64_t t = c - qq;
-            if (t >= 0 && t < nt) sum += S[t * kAtt + ax * kParAxis + qq];
+            for (int qq = 0; qq < kParAxis; ++qq) {
+                const int64_t t = c - qq;
+                if (t >= 0 && t < nt) sum += S[(g * nt + t) * kAtt + ax * kParAxis + qq];
+            }
         }
         qatt[j] += sum;
     }
@@ -1531,7 +1539,7 @@ __global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
 
 template <typename Acc, int K>
 __global__ __launch_bounds__(kBlock) void k_att_combine(const Acc* __restrict__ S, int64_t n_dfa,
-                                                         Acc* __restrict__ qatt,
+                                                         int64_t ngroups, Acc* __restrict__ qatt,
                                                          const Scalars* __restrict__ sc)
 {
     constexpr int kAtt = kAxes * kParAxis;
@@ -1546,12 +1554,15 @@ __global__ __launch_bounds__(kBlock) void k_att_combine(const Acc* __restrict__ 
         Acc sum[K];
 #pragma unroll
         for (int r = 0; r < K; ++r) sum[r] = (Acc)0;
+        for (int64_t g = 0; g < ngroups; ++g) {
 #pragma unroll
-        for (int qq = 0; qq < kParAxis; ++qq) {
-            const int64_t t = c - qq;
-            if (t >= 0 && t < nt)
+            for (int qq = 0; qq < kParAxis; ++qq) {
+                const int64_t t = c - qq;
+                if (t >= 0 && t < nt)
 #pragma unroll
-                for (int r = 0; r < K; ++r) sum[r] += S[(t * kAtt + ax * kParAxis + qq) * K + r];
+                    for (int r = 0; r < K; ++r)
+                        sum[r] += S[((g * nt + t) * kAtt + ax * kParAxis + qq) * K + r];
+            }
         }
 #pragma unroll
         for (int r = 0; r < K; ++r)

@@ -91,6 +91,9 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 constexpr int64_t kLdsInstrBudget = 64 * 1024;  // bytes of LDS for the instrumental histogram
 constexpr int64_t kLdsXBudget = 64 * 1024;      // bytes of LDS for aprod1's instrumental slice
 constexpr int kBlock1 = 512;                    // aprod1 workgroup size
+// Rows per block of the two-level attitude sort: the block's slice of an FP64
+// row vector (8 B/row) stays well inside the 256 MB last-level cache.
+constexpr int64_t kAttGroupBytes = 96ll << 20;
 
 // Working vectors of one arithmetic precision of the LSQR loop.
 template <typename Acc>
@@ -146,6 +149,8 @@ struct lsqr_handle {
     int32_t* invperm = nullptr;   // [m] sorted position of each row
     void* att_sorted = nullptr;   // [12][m] attitude coefficients in sorted order
     int64_t* wb_att = nullptr;    // [nb2*4 + 1] t-aligned ranges of the sorted rows
+    int64_t att_group_rows = 0;   // rows per block of the two-level sort
+    int64_t att_groups = 1;       // row blocks: S has att_groups * (n_dfa - 3) segments
     double* S_raw = nullptr;      // [(n_dfa-3)*12] partials of lsqr_aprod2
     bool att_ready = false;
 
@@ -181,6 +186,11 @@ struct lsqr_handle {
 };
 
 namespace {
+
+inline int64_t att_segments(const lsqr_handle* h)
+{
+    return h->att_groups * (h->sv.n_dfa - kParAxis + 1);
+}
 
 // ------------------------------------------------------------ launch helpers
 // aprod1 with the instrumental slice of x staged in LDS when it fits.
@@ -223,7 +233,7 @@ void launch_aprod2(lsqr_handle* h, const Acc* u, Acc* q, Acc* gpart, Acc* S, siz
                            q, h->wb, gpart, lds_instr, sc);
     hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), b, 0, st, gpart, h->nb2, q + h->sv.glob_base, sc);
     if (!att) {
-        const int64_t ns = (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis;
+        const int64_t ns = att_segments(h) * kAxes * kParAxis;
         hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), b, 0, st, ns, S, (Acc)0);
         if (us)
             hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, true>), g, b, 0, st, h->sv.m,
@@ -234,7 +244,7 @@ void launch_aprod2(lsqr_handle* h, const Acc* u, Acc* q, Acc* gpart, Acc* S, siz
                                (const T*)h->att_sorted, (const int32_t*)h->perm,
                                (const int32_t*)h->tkey, u, S, h->wb_att, sc);
         hipLaunchKernelGGL((k_att_combine<Acc>), dim3(h->nbc), b, 0, st, (const Acc*)S,
-                           h->sv.n_dfa, q + h->sv.att_base, sc);
+                           h->sv.n_dfa, h->att_groups, q + h->sv.att_base, sc);
     }
 }
 
@@ -244,7 +254,7 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
 {
     const int64_t n = h->sv.n;
     if (ev) (void)hipEventRecord(ev[0], st);
-    Acc* us = h->att_mode ? P.us : nullptr;
+    Acc* us = h->att_mode == 2 ? P.us : nullptr;
     launch_aprod1<T, Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u, nullptr, h->sc, h->part1,
                                             st, us);
     if (ev) (void)hipEventRecord(ev[1], st);
@@ -270,7 +280,7 @@ void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st, bool u_sorted_rea
     hipLaunchKernelGGL(k_scalar_init_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, P.q, (Acc)0);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->v, 0.0);
-    Acc* us = h->att_mode ? P.us : nullptr;
+    Acc* us = h->att_mode == 2 ? P.us : nullptr;
     if (us && !u_sorted_ready)
         hipLaunchKernelGGL((k_gather_perm<Acc>), dim3(std::min<int64_t>(cdiv(h->sv.m, kBlock), 65536)),
                            dim3(kBlock), 0, st, (const Acc*)P.u, (const int32_t*)h->perm, h->sv.m,
@@ -292,7 +302,7 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     LSQR_TRY(dalloc(&P.vp, n));
     LSQR_TRY(dalloc(&P.q, n));
     LSQR_TRY(dalloc(&P.gpart, h->nb2));
-    LSQR_TRY(dalloc(&P.S, (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis));
+    LSQR_TRY(dalloc(&P.S, att_segments(h) * kAxes * kParAxis));
     LSQR_TRY(dalloc(&P.us, m));
     const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(Acc);
     P.lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
@@ -317,13 +327,16 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
     int32_t *keys = nullptr, *rows = nullptr;
     void* temp = nullptr;
     size_t temp_bytes = 0;
+    const int64_t nt = h->sv.n_dfa - kParAxis + 1;
+    if (h->att_groups * nt >= ((int64_t)1 << 31))
+        return fail(LSQR_E_UNSUPPORTED, "too many attitude sort segments");
     int bits = 1;
-    while (bits < 31 && ((int64_t)1 << bits) < h->sv.n_dfa) ++bits;
+    while (bits < 31 && ((int64_t)1 << bits) < h->att_groups * nt) ++bits;
     LSQR_TRY(dalloc(&h->perm, m));
     LSQR_TRY(dalloc(&h->tkey, m));
     LSQR_TRY(dalloc(&h->invperm, m));
     LSQR_TRY(dalloc(&h->wb_att, (int64_t)h->nb2 * kWavesPerBlock + 1));
-    LSQR_TRY(dalloc(&h->S_raw, (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis));
+    LSQR_TRY(dalloc(&h->S_raw, att_segments(h) * kAxes * kParAxis));
     T* att_sorted = nullptr;
     LSQR_TRY(dalloc(&att_sorted, (int64_t)kAxes * kParAxis * m));
     h->att_sorted = att_sorted;
@@ -332,7 +345,7 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
     hipError_t e = hipSuccess;
     if (rc == LSQR_OK) {
         hipLaunchKernelGGL(k_att_keys, dim3(std::min<int64_t>(cdiv(m, kBlock), 65536)), dim3(kBlock),
-                           0, st, h->sv.att, m, keys, rows);
+                           0, st, h->sv.att, m, h->att_group_rows, nt, keys, rows);
         e = rocprim::radix_sort_pairs(nullptr, temp_bytes, keys, h->tkey, rows, h->perm,
                                       (size_t)m, 0, bits, st);
         if (e == hipSuccess) rc = dalloc(reinterpret_cast<char**>(&temp), (int64_t)temp_bytes);
@@ -522,7 +535,7 @@ lsqr_status batch_alloc(lsqr_handle* h, int kmax)
     dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
     dfree(B.sc); dfree(B.flag); dfree(B.S);
     B.kmax = 0;
-    LSQR_TRY(dalloc(&B.S, (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis * kmax));
+    LSQR_TRY(dalloc(&B.S, att_segments(h) * kAxes * kParAxis * kmax));
     LSQR_TRY(dalloc(&B.U, m * kmax));
     LSQR_TRY(dalloc(&B.V, n * kmax));
     LSQR_TRY(dalloc(&B.W, n * kmax));
@@ -577,13 +590,14 @@ void batch_aprod2(lsqr_handle* h, hipStream_t st)
     hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
                        (const double*)B.gpart, h->nb2, B.Q + h->sv.glob_base * K, B.sc);
     if (h->att_mode != 0) {
-        const int64_t ns = (h->sv.n_dfa - kParAxis + 1) * kAxes * kParAxis * K;
+        const int64_t ns = att_segments(h) * kAxes * kParAxis * K;
         hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, ns, B.S, 0.0);
         hipLaunchKernelGGL((batched::k_aprod2_att_sorted<T, double, K>), dim3(h->nb2), dim3(kBlock),
                            0, st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->perm,
                            (const int32_t*)h->tkey, (const double*)B.U, B.S, h->wb_att, B.sc);
         hipLaunchKernelGGL((batched::k_att_combine<double, K>), dim3(h->nbc), dim3(kBlock), 0, st,
-                           (const double*)B.S, h->sv.n_dfa, B.Q + h->sv.att_base * K, B.sc);
+                           (const double*)B.S, h->sv.n_dfa, h->att_groups, B.Q + h->sv.att_base * K,
+                           B.sc);
     }
 }
 
@@ -911,6 +925,8 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
             1, std::min<int64_t>((int64_t)h->num_cu * occ, cdiv(m, (int64_t)kWave * kWavesPerBlock)));
     }
     h->nbc = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)h->num_cu * 4, cdiv(n, kBlock)));
+    h->att_group_rows = std::max<int64_t>(kWave, kAttGroupBytes / 8);
+    h->att_groups = cdiv(m, h->att_group_rows);
 
     lsqr_status st;
     const int64_t nw = (int64_t)h->nb2 * kWavesPerBlock;
@@ -1042,7 +1058,9 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         return LSQR_OK;
     case LSQR_OPT_ATT_MODE:
     case LSQR_OPT_ASTRO_SCAN: {
-        const int v = value != 0.0 ? 1 : 0;
+        if (option == LSQR_OPT_ATT_MODE && !(value == 0.0 || value == 1.0 || value == 2.0))
+            return fail(LSQR_E_INVALID, "attitude mode must be 0, 1 or 2");
+        const int v = option == LSQR_OPT_ATT_MODE ? (int)value : (value != 0.0 ? 1 : 0);
         int& slot = option == LSQR_OPT_ATT_MODE ? h->att_mode : h->astro_scan;
         if (slot != v) {  // captured graphs bake in the kernel choice
             if (h->p64.graph) (void)hipGraphExecDestroy(h->p64.graph);
@@ -1058,6 +1076,15 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
             return fail(LSQR_E_INVALID, "k-tile must be 0 (autotune), 1, 2, 4 or 8");
         h->ktile = (int)value;
         return LSQR_OK;
+    case LSQR_OPT_ATT_GROUP_ROWS: {
+        if (h->att_ready || h->p64.ready || h->p32.ready || h->batch.kmax > 0 || h->S_raw)
+            return fail(LSQR_E_STATE, "attitude row blocks must be set before the first solve");
+        if (!(value >= (double)kWave && value <= 2147483647.0))
+            return fail(LSQR_E_INVALID, "rows per attitude block must be in [64, 2^31)");
+        h->att_group_rows = (int64_t)value;
+        h->att_groups = cdiv(h->sv.m, h->att_group_rows);
+        return LSQR_OK;
+    }
     case LSQR_OPT_OUTER_TOL:
         if (!(value >= 0.0)) return fail(LSQR_E_INVALID, "outer tolerance must be >= 0");
         h->outer_tol = value;
@@ -1163,7 +1190,7 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
         // FP64 residual of the full problem, stored as the FP32 start vector
         launch_aprod1<float, double, double, float, A1_RESID>(h, (const double*)x, P.u, b, nullptr,
                                                               h->part1, h->stream,
-                                                              h->att_mode ? P.us : nullptr);
+                                                              h->att_mode == 2 ? P.us : nullptr);
         launch_init<float, float>(h, P, h->stream, true);
         HIP_TRY(hipGetLastError());
         LSQR_TRY(read_scalars(h));

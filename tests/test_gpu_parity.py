@@ -93,7 +93,7 @@ def test_aprod1_parity(torch_cuda, name):
     assert np.all(np.abs(got - want) <= 32 * EPS * bound + 1e-300)
 
 
-VARIANTS = [(1, 0), (0, 1), (0, 0), (1, 1)]  # (att_mode, astro_scan); first = default
+VARIANTS = [(1, 0), (2, 0), (0, 1), (0, 0), (1, 1)]  # (att_mode, astro_scan); first = default
 
 
 @pytest.mark.parametrize("variant", VARIANTS, ids=[f"att{a}_scan{b}" for a, b in VARIANTS])
@@ -110,6 +110,7 @@ def test_aprod2_parity(torch_cuda, name, variant):
     g = gpu_system(torch, S)
     g.set_option("att_mode", variant[0])
     g.set_option("astro_scan", variant[1])
+    g.set_option("att_group_rows", 1000)  # several row blocks even on small systems
     xd = torch.from_numpy(x0).cuda()
     g.aprod2(xd, torch.from_numpy(y).cuda())
     torch.cuda.synchronize()
@@ -162,6 +163,8 @@ def _solve_fixed(torch_cuda, name, itn, graph, variant):
     g = gpu_system(torch, S)
     g.set_option("att_mode", variant[0])
     g.set_option("astro_scan", variant[1])
+    if graph:
+        g.set_option("att_group_rows", 4096)
     g.set_option("tests", 0)
     g.set_option("graph", graph)
     g.set_option("chunk", 7)
