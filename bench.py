@@ -135,9 +135,10 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
     b = synth.device_noise(spec, m, 0, dev)
     g.aprod1(synth.device_x_true(spec, dev), b)
     out = {}
-    for att, scan in ((1, 0), (2, 0), (1, 1), (0, 0)):
+    for att, scan, att4 in ((1, 0, 1), (1, 0, 0), (2, 0, 1), (1, 1, 1), (0, 0, 1)):
         g.set_option("att_mode", att)
         g.set_option("astro_scan", scan)
+        g.set_option("att4", att4)
         g.set_option("tests", 0)
         g.set_option("profile", 1)
         g.solve(b, 2, atol=0.0, btol=0.0)
@@ -145,7 +146,7 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
         kt = g.kernel_times()
         a1, a2 = kt["aprod1_ms"] / kt["aprod1_n"], kt["aprod2_ms"] / kt["aprod2_n"]
         key = ("atomics", "reordered_gather", "reordered_u_written_sorted")[att] + \
-            ("_scan" if scan else "_flush")
+            ("_scan" if scan else "_flush") + ("" if att4 else "_aprod1_plain_att_gathers")
         out[key] = {"aprod1_ms": a1, "aprod2_ms": a2,
                     "aprod2_GBps": BYTES_PER_ROW["aprod2"] * m / (a2 * 1e-3) / 1e9,
                     "rnorm": info.rnorm}

@@ -126,6 +126,10 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *   LSQR_OPT_ATT_GROUP_ROWS  rows per block of the (row block, attitude start)
  *                         order (default 12,582,912: an FP64 row vector slice of
  *                         96 MB); settable only before the first solve or aprod2
+ *   LSQR_OPT_ATT4         aprod1 reads the attitude values of a row from an
+ *                         expanded copy of the attitude section (4 aligned values
+ *                         per axis and start, rebuilt before every aprod1): 1
+ *                         (default) or 0 (gathers straight from the vector)
  *   LSQR_OPT_KTILE        batched solves: right-hand sides advanced together per
  *                         pass over A (1, 2, 4, 8), 0 (default) = autotune once
  *                         per handle
@@ -140,6 +144,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_ASTRO_SCAN 8
 #define LSQR_OPT_KTILE 9
 #define LSQR_OPT_ATT_GROUP_ROWS 10
+#define LSQR_OPT_ATT4 11
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
 
 /* aprod mode 1, Eq. (2): y[m] += A x[n] with the raw (unscaled) A.

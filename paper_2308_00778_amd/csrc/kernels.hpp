@@ -145,10 +145,26 @@ __device__ __forceinline__ double max_partials(const double* part, int n, double
 
 // ------------------------------------------------------------------- aprod 1
 // Eq. (2) for one row: sum over the 24 coefficients in section order.
+// Four consecutive values of a column vector as one aligned vector load.
+template <typename V>
+__device__ __forceinline__ void load4(const V* __restrict__ p, V (&o)[4])
+{
+    typedef V V4 __attribute__((ext_vector_type(4)));
+    const V4 v = *reinterpret_cast<const V4*>(p);
+    o[0] = v[0];
+    o[1] = v[1];
+    o[2] = v[2];
+    o[3] = v[3];
+}
+
 // xi: the instrumental slice of x (x + instr_base, or its copy in LDS).
-template <typename T, typename Acc, typename VX>
+// x4 (ATT4): expanded attitude section, x4[(axis * nt + t) * 4 + q] =
+// x[att_base + axis * n_dfa + t + q], so that the 4 attitude values a row
+// needs per axis are one aligned 4-vector.
+template <typename T, typename Acc, typename VX, bool ATT4 = false>
 __device__ __forceinline__ Acc row_dot(const SysView& s, const VX* __restrict__ x,
-                                       const VX* __restrict__ xi, int64_t i)
+                                       const VX* __restrict__ xi, int64_t i,
+                                       const VX* __restrict__ x4 = nullptr)
 {
     const T* __restrict__ val = static_cast<const T*>(s.val);
     const int64_t m = s.m;
@@ -167,9 +183,16 @@ __device__ __forceinline__ Acc row_dot(const SysView& s, const VX* __restrict__ 
     for (int j = 0; j < kAstro; ++j) sum += (Acc)a[j] * (Acc)xa[j];
 #pragma unroll
     for (int ax = 0; ax < kAxes; ++ax) {
-        const VX* xt = x + s.att_base + ax * s.n_dfa + t;
+        VX xv[kParAxis];
+        if (ATT4) {
+            load4(x4 + (ax * (s.n_dfa - kParAxis + 1) + t) * kParAxis, xv);
+        } else {
+            const VX* xt = x + s.att_base + ax * s.n_dfa + t;
 #pragma unroll
-        for (int q = 0; q < kParAxis; ++q) sum += (Acc)a[kOffAtt + ax * kParAxis + q] * (Acc)xt[q];
+            for (int q = 0; q < kParAxis; ++q) xv[q] = xt[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kParAxis; ++q) sum += (Acc)a[kOffAtt + ax * kParAxis + q] * (Acc)xv[q];
     }
 #pragma unroll
     for (int j = 0; j < kInstr; ++j) sum += (Acc)a[kOffInstr + j] * (Acc)xi[ic[j]];
@@ -191,13 +214,14 @@ enum Aprod1Mode : int {
 // ys[invperm[i]] = y[i], so that the reordered attitude pass of aprod2 reads
 // it sequentially instead of gathering it.
 template <typename T, typename Acc, typename VX, typename VY, int MODE, int NT = kBlock,
-          bool LDSX = false>
+          bool LDSX = false, bool ATT4 = false>
 __global__ __launch_bounds__(NT) void k_aprod1(SysView s, const VX* __restrict__ x,
                                                 VY* __restrict__ y, const double* __restrict__ b,
                                                 const Scalars* __restrict__ sc,
                                                 double* __restrict__ part,
                                                 const int32_t* __restrict__ invperm = nullptr,
-                                                VY* __restrict__ ys = nullptr)
+                                                VY* __restrict__ ys = nullptr,
+                                                const VX* __restrict__ x4 = nullptr)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[NT / kWave];
@@ -216,8 +240,8 @@ __global__ __launch_bounds__(NT) void k_aprod1(SysView s, const VX* __restrict__
         const int64_t i1 = i0 + stride;
         const bool has1 = i1 < s.m;
         const int64_t i1c = has1 ? i1 : i0;
-        const Acc d0 = row_dot<T, Acc, VX>(s, x, xi, i0);
-        const Acc d1 = row_dot<T, Acc, VX>(s, x, xi, i1c);
+        const Acc d0 = row_dot<T, Acc, VX, ATT4>(s, x, xi, i0, x4);
+        const Acc d1 = row_dot<T, Acc, VX, ATT4>(s, x, xi, i1c, x4);
         if (MODE == A1_ACCUM) {
             y[i0] = (VY)((Acc)y[i0] + d0);
             if (has1) y[i1] = (VY)((Acc)y[i1] + d1);
@@ -238,6 +262,24 @@ __global__ __launch_bounds__(NT) void k_aprod1(SysView s, const VX* __restrict__
     if (MODE != A1_ACCUM) {
         const double r = block_sum_n<NT>(ssq, red);
         if (threadIdx.x == 0) part[blockIdx.x] = r;
+    }
+}
+
+// x4[(axis * nt + t) * 4 + q] = x[att_base + axis * n_dfa + t + q]
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_expand_att(const V* __restrict__ x, int64_t att_base,
+                                                        int64_t n_dfa, V* __restrict__ x4,
+                                                        const Scalars* __restrict__ sc)
+{
+    if (sc != nullptr && sc->done) return;
+    const int64_t nt = n_dfa - kParAxis + 1;
+    const int64_t total = (int64_t)kAxes * nt * kParAxis;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * kBlock) {
+        const int64_t q = j & (kParAxis - 1);
+        const int64_t at = j / kParAxis;
+        const int64_t ax = at / nt, t = at - ax * nt;
+        x4[j] = x[att_base + ax * n_dfa + t + q];
     }
 }
 

@@ -88,7 +88,9 @@ void dfree(V*& p)
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-constexpr int64_t kLdsInstrBudget = 64 * 1024;  // bytes of LDS for the instrumental histogram
+// bytes of LDS for the instrumental histogram of aprod2 (gfx950 allows 160 KB
+// per workgroup; a little is kept for the static arrays)
+constexpr int64_t kLdsInstrBudget = 152 * 1024;
 constexpr int64_t kLdsXBudget = 64 * 1024;      // bytes of LDS for aprod1's instrumental slice
 constexpr int kBlock1 = 512;                    // aprod1 workgroup size
 // Rows per block of the two-level attitude sort: the block's slice of an FP64
@@ -104,6 +106,7 @@ struct Path {
     Acc* gpart = nullptr;  // [nb2] global-column partials
     Acc* S = nullptr;      // [(n_dfa-3)*12] attitude partials of the reordered pass
     Acc* us = nullptr;     // [m] u~ in attitude-sorted row order (reordered pass)
+    Acc* vp4 = nullptr;    // [3 (n_dfa-3) 4] expanded attitude section of vp
     size_t lds = 0;        // dynamic LDS bytes of aprod2
     int lds_instr = 0;
     hipGraphExec_t graph = nullptr;
@@ -152,6 +155,7 @@ struct lsqr_handle {
     int64_t att_group_rows = 0;   // rows per block of the two-level sort
     int64_t att_groups = 1;       // row blocks: S has att_groups * (n_dfa - 3) segments
     double* S_raw = nullptr;      // [(n_dfa-3)*12] partials of lsqr_aprod2
+    double* x4_raw = nullptr;     // expanded attitude section of lsqr_aprod1's x
     bool att_ready = false;
 
     // batched right-hand sides (tile buffers for the largest K, reused per tile)
@@ -176,6 +180,7 @@ struct lsqr_handle {
     int profile = 0;
     int att_mode = 1;    // 0: attitude scatter with device atomics, 1: row-reordered pass
     int astro_scan = 0;  // 1: segmented scan per chunk, 0: accumulate-and-flush segments
+    int att4 = 1;        // aprod1 gathers attitude values from the expanded copy
     double outer_tol = 1e-10;
     int ktile = 0;       // batched k-tile: 0 autotune, else 1, 2, 4 or 8
 
@@ -194,18 +199,33 @@ inline int64_t att_segments(const lsqr_handle* h)
 
 // ------------------------------------------------------------ launch helpers
 // aprod1 with the instrumental slice of x staged in LDS when it fits.
+// x4 (optional): expanded attitude section of x, already written (k_expand_att).
 template <typename T, typename Acc, typename VX, typename VY, int MODE>
 void launch_aprod1(const lsqr_handle* h, const VX* x, VY* y, const double* b, const Scalars* sc,
-                   double* part, hipStream_t st, VY* ys = nullptr)
+                   double* part, hipStream_t st, VY* ys = nullptr, const VX* x4 = nullptr)
 {
     const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(VX);
     const int32_t* ip = ys ? h->invperm : nullptr;
-    if (bytes <= kLdsXBudget)
-        hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, true>), dim3(h->nb1),
-                           dim3(kBlock1), (size_t)bytes, st, h->sv, x, y, b, sc, part, ip, ys);
+    const dim3 g(h->nb1), b1(kBlock1);
+    if (bytes <= kLdsXBudget && x4)
+        hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, true, true>), g, b1,
+                           (size_t)bytes, st, h->sv, x, y, b, sc, part, ip, ys, x4);
+    else if (bytes <= kLdsXBudget)
+        hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, true, false>), g, b1,
+                           (size_t)bytes, st, h->sv, x, y, b, sc, part, ip, ys, x4);
+    else if (x4)
+        hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, false, true>), g, b1, 0, st,
+                           h->sv, x, y, b, sc, part, ip, ys, x4);
     else
-        hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, false>), dim3(h->nb1),
-                           dim3(kBlock1), 0, st, h->sv, x, y, b, sc, part, ip, ys);
+        hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, false, false>), g, b1, 0, st,
+                           h->sv, x, y, b, sc, part, ip, ys, x4);
+}
+
+template <typename V>
+void launch_expand_att(const lsqr_handle* h, const V* x, V* x4, const Scalars* sc, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_expand_att<V>), dim3(h->nbc), dim3(kBlock), 0, st, x, h->sv.att_base,
+                       h->sv.n_dfa, x4, sc);
 }
 
 // q += A^T u for the LSQR loop (and lsqr_aprod2): the main pass over the rows
@@ -255,8 +275,9 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
     const int64_t n = h->sv.n;
     if (ev) (void)hipEventRecord(ev[0], st);
     Acc* us = h->att_mode == 2 ? P.us : nullptr;
+    if (h->att4) launch_expand_att<Acc>(h, P.vp, P.vp4, h->sc, st);
     launch_aprod1<T, Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u, nullptr, h->sc, h->part1,
-                                            st, us);
+                                            st, us, h->att4 ? (const Acc*)P.vp4 : nullptr);
     if (ev) (void)hipEventRecord(ev[1], st);
     hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
     if (ev) (void)hipEventRecord(ev[2], st);
@@ -304,6 +325,7 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     LSQR_TRY(dalloc(&P.gpart, h->nb2));
     LSQR_TRY(dalloc(&P.S, att_segments(h) * kAxes * kParAxis));
     LSQR_TRY(dalloc(&P.us, m));
+    LSQR_TRY(dalloc(&P.vp4, (int64_t)kAxes * (h->sv.n_dfa - kParAxis + 1) * kParAxis));
     const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(Acc);
     P.lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
     P.lds = P.lds_instr ? (size_t)bytes : 0;
@@ -391,6 +413,7 @@ void release_path(Path<Acc>& P)
     dfree(P.gpart);
     dfree(P.S);
     dfree(P.us);
+    dfree(P.vp4);
     P.ready = false;
 }
 
@@ -1013,6 +1036,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h)
     dfree(h->perm);
     dfree(h->tkey);
     dfree(h->invperm);
+    dfree(h->x4_raw);
     dfree(h->wb_att);
     dfree(h->S_raw);
     if (h->att_sorted) (void)hipFree(h->att_sorted);
@@ -1071,6 +1095,15 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         slot = v;
         return LSQR_OK;
     }
+    case LSQR_OPT_ATT4:
+        if (h->att4 != (value != 0.0 ? 1 : 0)) {
+            if (h->p64.graph) (void)hipGraphExecDestroy(h->p64.graph);
+            if (h->p32.graph) (void)hipGraphExecDestroy(h->p32.graph);
+            h->p64.graph = nullptr;
+            h->p32.graph = nullptr;
+        }
+        h->att4 = value != 0.0 ? 1 : 0;
+        return LSQR_OK;
     case LSQR_OPT_KTILE:
         if (!(value == 0.0 || value == 1.0 || value == 2.0 || value == 4.0 || value == 8.0))
             return fail(LSQR_E_INVALID, "k-tile must be 0 (autotune), 1, 2, 4 or 8");
@@ -1098,12 +1131,19 @@ lsqr_status lsqr_aprod1(lsqr_handle* h, const double* x, double* y)
 {
     LSQR_TRY(check_handle(h));
     if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
+    const double* x4 = nullptr;
+    if (h->att4) {
+        if (!h->x4_raw)
+            LSQR_TRY(dalloc(&h->x4_raw, (int64_t)kAxes * (h->sv.n_dfa - kParAxis + 1) * kParAxis));
+        launch_expand_att<double>(h, x, h->x4_raw, nullptr, h->user_stream);
+        x4 = h->x4_raw;
+    }
     if (h->value_type == LSQR_F64)
         launch_aprod1<double, double, double, double, A1_ACCUM>(h, x, y, nullptr, nullptr, nullptr,
-                                                                h->user_stream);
+                                                                h->user_stream, nullptr, x4);
     else
         launch_aprod1<float, double, double, double, A1_ACCUM>(h, x, y, nullptr, nullptr, nullptr,
-                                                               h->user_stream);
+                                                               h->user_stream, nullptr, x4);
     HIP_TRY(hipGetLastError());
     return LSQR_OK;
 }
@@ -1188,9 +1228,17 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
         // relative decrease of ||Abar^T r|| (tolerance atol) or the itn limit.
         LSQR_TRY(upload_controls(h, itn_limit, 0.0, 0.0, std::max(atol, 1e-300)));
         // FP64 residual of the full problem, stored as the FP32 start vector
+        const double* x4 = nullptr;
+        if (h->att4) {
+            if (!h->x4_raw)
+                LSQR_TRY(dalloc(&h->x4_raw,
+                                (int64_t)kAxes * (h->sv.n_dfa - kParAxis + 1) * kParAxis));
+            launch_expand_att<double>(h, x, h->x4_raw, nullptr, h->stream);
+            x4 = h->x4_raw;
+        }
         launch_aprod1<float, double, double, float, A1_RESID>(h, (const double*)x, P.u, b, nullptr,
                                                               h->part1, h->stream,
-                                                              h->att_mode == 2 ? P.us : nullptr);
+                                                              h->att_mode == 2 ? P.us : nullptr, x4);
         launch_init<float, float>(h, P, h->stream, true);
         HIP_TRY(hipGetLastError());
         LSQR_TRY(read_scalars(h));

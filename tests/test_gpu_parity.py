@@ -74,17 +74,19 @@ def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
+@pytest.mark.parametrize("att4", [1, 0])
 @pytest.mark.parametrize("name", list(SPECS))
-def test_aprod1_parity(torch_cuda, name):
+def test_aprod1_parity(torch_cuda, name, att4):
     torch = torch_cuda
     S, o = system(name)
-    say(f"aprod1 parity: {name} m={S.m} n={o.n} seed={S.spec.seed}")
+    say(f"aprod1 parity: {name} m={S.m} n={o.n} seed={S.spec.seed} att4={att4}")
     rng = np.random.default_rng(5)
     x = rng.standard_normal(o.n)
     y0 = rng.standard_normal(o.m)
     want = o.aprod1(x, y0)
     bound = abs_system(S).aprod1(np.abs(x), np.abs(y0))
     g = gpu_system(torch, S)
+    g.set_option("att4", att4)
     yd = torch.from_numpy(y0).cuda()
     g.aprod1(torch.from_numpy(x).cuda(), yd)
     torch.cuda.synchronize()
@@ -154,7 +156,12 @@ def test_solve_variants(torch_cuda, name, itn, variant):
     _solve_fixed(torch_cuda, name, itn, 1, variant)
 
 
-def _solve_fixed(torch_cuda, name, itn, graph, variant):
+@pytest.mark.parametrize("name,itn", [("c0", 50), ("wide_instr", 40)])
+def test_solve_without_expanded_attitude(torch_cuda, name, itn):
+    _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], att4=0)
+
+
+def _solve_fixed(torch_cuda, name, itn, graph, variant, att4=1):
     torch = torch_cuda
     S, o = system(name)
     b = _b(S, o)
@@ -163,6 +170,7 @@ def _solve_fixed(torch_cuda, name, itn, graph, variant):
     g = gpu_system(torch, S)
     g.set_option("att_mode", variant[0])
     g.set_option("astro_scan", variant[1])
+    g.set_option("att4", att4)
     if graph:
         g.set_option("att_group_rows", 4096)
     g.set_option("tests", 0)
