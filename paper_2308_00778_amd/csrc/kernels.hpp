@@ -389,8 +389,9 @@ __device__ __forceinline__ void seg_finish(SegAcc<Acc, NV>& S, int lane, Emit&& 
 // (k_aprod2_att_sorted) and skips loading them. SCAN selects the astrometric
 // reduction: a segmented scan every chunk (true) or the accumulate-and-flush
 // segments of seg_chunk (false).
-template <typename T, typename Acc, typename VU, bool SQUARE, bool ATT = true, bool SCAN = true>
-__global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const VU* __restrict__ u,
+template <typename T, typename Acc, typename VU, bool SQUARE, bool ATT = true, bool SCAN = true,
+          int NT = kBlock>
+__global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__ u,
                                                     Acc* __restrict__ q,
                                                     const int64_t* __restrict__ wb,
                                                     Acc* __restrict__ gpart, int lds_instr,
@@ -398,19 +399,19 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const VU* __restri
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Acc* lds = reinterpret_cast<Acc*>(smem_raw);
-    __shared__ Acc gred[kWavesPerBlock];
+    __shared__ Acc gred[NT / kWave];
     if (sc != nullptr && (sc->done || sc->beta_zero)) return;
 
     const T* __restrict__ val = static_cast<const T*>(s.val);
     const int64_t m = s.m;
     const int64_t ninst = s.n_instr_cols;
     if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst; j += kBlock) lds[j] = (Acc)0;
+        for (int64_t j = threadIdx.x; j < ninst; j += NT) lds[j] = (Acc)0;
         __syncthreads();
     }
 
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t wave = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave;
     const int64_t rb = wb[wave], re = wb[wave + 1];
     Acc* __restrict__ qatt = q + s.att_base;
     Acc* __restrict__ qins = q + s.instr_base;
@@ -514,12 +515,12 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const VU* __restri
     __syncthreads();
     if (threadIdx.x == 0) {
         Acc g = (Acc)0;
-        for (int k = 0; k < kWavesPerBlock; ++k) g += gred[k];
+        for (int k = 0; k < NT / kWave; ++k) g += gred[k];
         gpart[blockIdx.x] = g;
     }
     // instrumental flush: one device atomic per column per workgroup
     if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst; j += kBlock) {
+        for (int64_t j = threadIdx.x; j < ninst; j += NT) {
             const Acc v = lds[j];
             if (v != (Acc)0) atomicAdd(&qins[j], v);
         }
@@ -1139,8 +1140,8 @@ __global__ __launch_bounds__(kBlock) void k_aprod1(SysView s, const Acc* __restr
 // flush segments, attitude: device atomics, instrumental: LDS histogram
 // [n_instr_cols][K] when lds_instr, else device atomics, global: partials
 // gpart[blk][K]). Frozen RHS contribute nothing.
-template <typename T, typename Acc, int K, bool ATT = true>
-__global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const Acc* __restrict__ U,
+template <typename T, typename Acc, int K, bool ATT = true, int NT = kBlock>
+__global__ __launch_bounds__(NT) void k_aprod2(SysView s, const Acc* __restrict__ U,
                                                     Acc* __restrict__ Q,
                                                     const int64_t* __restrict__ wb,
                                                     Acc* __restrict__ gpart, int lds_instr,
@@ -1148,7 +1149,7 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const Acc* __restr
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Acc* lds = reinterpret_cast<Acc*>(smem_raw);
-    __shared__ Acc gred[K * kWavesPerBlock];
+    __shared__ Acc gred[K * (NT / kWave)];
     uint32_t live = 0;
 #pragma unroll
     for (int r = 0; r < K; ++r) live |= ((sc[r].done || sc[r].beta_zero) ? 0u : 1u) << r;
@@ -1157,11 +1158,11 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const Acc* __restr
     const int64_t m = s.m;
     const int64_t ninst = s.n_instr_cols;
     if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst * K; j += kBlock) lds[j] = (Acc)0;
+        for (int64_t j = threadIdx.x; j < ninst * K; j += NT) lds[j] = (Acc)0;
         __syncthreads();
     }
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t wave = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave;
     const int64_t rb = wb[wave], re = wb[wave + 1];
     Acc* __restrict__ qatt = Q + s.att_base * K;
     Acc* __restrict__ qins = Q + s.instr_base * K;
@@ -1233,15 +1234,15 @@ __global__ __launch_bounds__(kBlock) void k_aprod2(SysView s, const Acc* __restr
     }
     if (lane == 0)
 #pragma unroll
-        for (int r = 0; r < K; ++r) gred[r * kWavesPerBlock + threadIdx.x / kWave] = gsum[r];
+        for (int r = 0; r < K; ++r) gred[r * (NT / kWave) + threadIdx.x / kWave] = gsum[r];
     __syncthreads();
     if (threadIdx.x < K) {
         Acc g = (Acc)0;
-        for (int k = 0; k < kWavesPerBlock; ++k) g += gred[threadIdx.x * kWavesPerBlock + k];
+        for (int k = 0; k < NT / kWave; ++k) g += gred[threadIdx.x * (NT / kWave) + k];
         gpart[(int64_t)blockIdx.x * K + threadIdx.x] = g;
     }
     if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst * K; j += kBlock) {
+        for (int64_t j = threadIdx.x; j < ninst * K; j += NT) {
             const Acc v = lds[j];
             if (v != (Acc)0) atomicAdd(&qins[j], v);
         }

@@ -93,6 +93,8 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 constexpr int64_t kLdsInstrBudget = 152 * 1024;
 constexpr int64_t kLdsXBudget = 64 * 1024;      // bytes of LDS for aprod1's instrumental slice
 constexpr int kBlock1 = 512;                    // aprod1 workgroup size
+constexpr int kBlock2 = 1024;                   // aprod2 main-pass workgroup size
+constexpr int kWavesPerCU = 16;                 // row ranges per compute unit in aprod2
 // Rows per block of the two-level attitude sort: the block's slice of an FP64
 // row vector (8 B/row) stays well inside the 256 MB last-level cache.
 constexpr int64_t kAttGroupBytes = 96ll << 20;
@@ -126,10 +128,12 @@ struct lsqr_handle {
     hipStream_t stream = nullptr;       // solves (capturable, owned)
 
     int nb1 = 0;  // aprod1 grid
-    int nb2 = 0;  // aprod2 grid (4 star-aligned row ranges per block)
+    int64_t nw = 0;  // star-aligned row ranges of aprod2, one per wave (multiple of 16)
+    int nb2 = 0;     // aprod2 main-pass grid: nw / 16 workgroups of 1024 threads
+    int nba = 0;     // reordered attitude pass grid: nw / 4 workgroups of 256 threads
     int nbc = 0;  // column-kernel grid
 
-    int64_t* wb = nullptr;  // [nb2*4 + 1] row boundaries
+    int64_t* wb = nullptr;  // [nw + 1] row boundaries
     double* p = nullptr;    // [n] column scaling
     double* v = nullptr;    // [n]
     double* w = nullptr;    // [n]
@@ -151,7 +155,7 @@ struct lsqr_handle {
     int32_t* tkey = nullptr;      // [m] attitude start of each sorted row
     int32_t* invperm = nullptr;   // [m] sorted position of each row
     void* att_sorted = nullptr;   // [12][m] attitude coefficients in sorted order
-    int64_t* wb_att = nullptr;    // [nb2*4 + 1] t-aligned ranges of the sorted rows
+    int64_t* wb_att = nullptr;    // [nw + 1] t-aligned ranges of the sorted rows
     int64_t att_group_rows = 0;   // rows per block of the two-level sort
     int64_t att_groups = 1;       // row blocks: S has att_groups * (n_dfa - 3) segments
     double* S_raw = nullptr;      // [(n_dfa-3)*12] partials of lsqr_aprod2
@@ -237,30 +241,30 @@ template <typename T, typename Acc>
 void launch_aprod2(lsqr_handle* h, const Acc* u, Acc* q, Acc* gpart, Acc* S, size_t lds,
                    int lds_instr, const Scalars* sc, hipStream_t st, const Acc* us = nullptr)
 {
-    const dim3 g(h->nb2), b(kBlock);
+    const dim3 g(h->nb2), bm(kBlock2), ga(h->nba), b(kBlock);
     const bool att = h->att_mode == 0;
     if (att && h->astro_scan)
-        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, true>), g, b, lds, st, h->sv, u, q,
-                           h->wb, gpart, lds_instr, sc);
+        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, true, kBlock2>), g, bm, lds, st, h->sv,
+                           u, q, h->wb, gpart, lds_instr, sc);
     else if (att)
-        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, false>), g, b, lds, st, h->sv, u, q,
-                           h->wb, gpart, lds_instr, sc);
+        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, false, kBlock2>), g, bm, lds, st,
+                           h->sv, u, q, h->wb, gpart, lds_instr, sc);
     else if (h->astro_scan)
-        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, true>), g, b, lds, st, h->sv, u, q,
-                           h->wb, gpart, lds_instr, sc);
+        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, true, kBlock2>), g, bm, lds, st,
+                           h->sv, u, q, h->wb, gpart, lds_instr, sc);
     else
-        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, false>), g, b, lds, st, h->sv, u,
-                           q, h->wb, gpart, lds_instr, sc);
+        hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, false, kBlock2>), g, bm, lds, st,
+                           h->sv, u, q, h->wb, gpart, lds_instr, sc);
     hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), b, 0, st, gpart, h->nb2, q + h->sv.glob_base, sc);
     if (!att) {
         const int64_t ns = att_segments(h) * kAxes * kParAxis;
         hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), b, 0, st, ns, S, (Acc)0);
         if (us)
-            hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, true>), g, b, 0, st, h->sv.m,
+            hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, true>), ga, b, 0, st, h->sv.m,
                                (const T*)h->att_sorted, (const int32_t*)h->perm,
                                (const int32_t*)h->tkey, us, S, h->wb_att, sc);
         else
-            hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, false>), g, b, 0, st, h->sv.m,
+            hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, false>), ga, b, 0, st, h->sv.m,
                                (const T*)h->att_sorted, (const int32_t*)h->perm,
                                (const int32_t*)h->tkey, u, S, h->wb_att, sc);
         hipLaunchKernelGGL((k_att_combine<Acc>), dim3(h->nbc), b, 0, st, (const Acc*)S,
@@ -357,7 +361,7 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
     LSQR_TRY(dalloc(&h->perm, m));
     LSQR_TRY(dalloc(&h->tkey, m));
     LSQR_TRY(dalloc(&h->invperm, m));
-    LSQR_TRY(dalloc(&h->wb_att, (int64_t)h->nb2 * kWavesPerBlock + 1));
+    LSQR_TRY(dalloc(&h->wb_att, h->nw + 1));
     LSQR_TRY(dalloc(&h->S_raw, att_segments(h) * kAxes * kParAxis));
     T* att_sorted = nullptr;
     LSQR_TRY(dalloc(&att_sorted, (int64_t)kAxes * kParAxis * m));
@@ -381,7 +385,7 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
                            att_sorted);
         hipLaunchKernelGGL(k_invert_perm, dim3(std::min<int64_t>(cdiv(m, kBlock), 65536)),
                            dim3(kBlock), 0, st, (const int32_t*)h->perm, m, h->invperm);
-        const int64_t nw = (int64_t)h->nb2 * kWavesPerBlock;
+        const int64_t nw = h->nw;
         hipLaunchKernelGGL((k_wave_bounds<int32_t>), dim3(cdiv(nw + 1, kBlock)), dim3(kBlock), 0, st,
                            (const int32_t*)h->tkey, m, nw, h->wb_att);
         e = hipGetLastError();
@@ -565,7 +569,7 @@ lsqr_status batch_alloc(lsqr_handle* h, int kmax)
     LSQR_TRY(dalloc(&B.Y, n * kmax));
     LSQR_TRY(dalloc(&B.VP, n * kmax));
     LSQR_TRY(dalloc(&B.Q, n * kmax));
-    LSQR_TRY(dalloc(&B.gpart, (int64_t)h->nb2 * kmax));
+    LSQR_TRY(dalloc(&B.gpart, (int64_t)h->nba * kmax));
     LSQR_TRY(dalloc(&B.part1, (int64_t)h->nb1 * kmax));
     LSQR_TRY(dalloc(&B.partc, (int64_t)h->nbc * kmax));
     LSQR_TRY(dalloc(&B.partdd, (int64_t)h->nbc * kmax));
@@ -604,18 +608,22 @@ void batch_aprod2(lsqr_handle* h, hipStream_t st)
     auto& B = h->batch;
     int li = 0;
     const size_t lds = batch_lds<K>(h, &li);
+    // K <= 2 fits the 128 registers a lane has in a 1024-thread workgroup;
+    // wider tiles keep 256-thread workgroups over the same row ranges.
+    constexpr int NT = K <= 2 ? kBlock2 : kBlock;
+    const int grid = K <= 2 ? h->nb2 : h->nba;
     if (h->att_mode == 0)
-        hipLaunchKernelGGL((batched::k_aprod2<T, double, K, true>), dim3(h->nb2), dim3(kBlock), lds,
+        hipLaunchKernelGGL((batched::k_aprod2<T, double, K, true, NT>), dim3(grid), dim3(NT), lds,
                            st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
     else
-        hipLaunchKernelGGL((batched::k_aprod2<T, double, K, false>), dim3(h->nb2), dim3(kBlock),
-                           lds, st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
+        hipLaunchKernelGGL((batched::k_aprod2<T, double, K, false, NT>), dim3(grid), dim3(NT), lds,
+                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
     hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
-                       (const double*)B.gpart, h->nb2, B.Q + h->sv.glob_base * K, B.sc);
+                       (const double*)B.gpart, grid, B.Q + h->sv.glob_base * K, B.sc);
     if (h->att_mode != 0) {
         const int64_t ns = att_segments(h) * kAxes * kParAxis * K;
         hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, ns, B.S, 0.0);
-        hipLaunchKernelGGL((batched::k_aprod2_att_sorted<T, double, K>), dim3(h->nb2), dim3(kBlock),
+        hipLaunchKernelGGL((batched::k_aprod2_att_sorted<T, double, K>), dim3(h->nba), dim3(kBlock),
                            0, st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->perm,
                            (const int32_t*)h->tkey, (const double*)B.U, B.S, h->wb_att, B.sc);
         hipLaunchKernelGGL((batched::k_att_combine<double, K>), dim3(h->nbc), dim3(kBlock), 0, st,
@@ -937,22 +945,23 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
             1, std::min<int64_t>((int64_t)h->num_cu * occ, cdiv(m, 2 * kBlock1)));
     }
     {
-        // aprod2 grid: as many resident workgroups as the LDS histogram allows
-        const size_t lds = (size_t)std::min<int64_t>(s.n_instr_cols * 8, kLdsInstrBudget);
-        int occ = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, k_aprod2<double, double, double, false>, kBlock, lds);
-        if (e != hipSuccess || occ <= 0) occ = 2;
-        occ = std::min(occ, 4);
-        h->nb2 = (int)std::max<int64_t>(
-            1, std::min<int64_t>((int64_t)h->num_cu * occ, cdiv(m, (int64_t)kWave * kWavesPerBlock)));
+        // aprod2: a fixed number of row ranges (16 waves per compute unit),
+        // run by 1024-thread workgroups in the main pass (one per compute
+        // unit whatever the LDS histogram size) and by 256-thread workgroups
+        // in the attitude pass.
+        const int64_t per = kBlock2 / kWave;
+        int64_t nw = std::min<int64_t>((int64_t)h->num_cu * kWavesPerCU, cdiv(m, kWave));
+        nw = std::max<int64_t>(per, cdiv(nw, per) * per);
+        h->nw = nw;
+        h->nb2 = (int)(nw / per);
+        h->nba = (int)(nw / kWavesPerBlock);
     }
     h->nbc = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)h->num_cu * 4, cdiv(n, kBlock)));
     h->att_group_rows = std::max<int64_t>(kWave, kAttGroupBytes / 8);
     h->att_groups = cdiv(m, h->att_group_rows);
 
     lsqr_status st;
-    const int64_t nw = (int64_t)h->nb2 * kWavesPerBlock;
+    const int64_t nw = h->nw;
     if ((st = dalloc(&h->wb, nw + 1)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->p, n)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->v, n)) != LSQR_OK) return bail(st);
@@ -1005,13 +1014,13 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     const size_t lds = lds_instr ? (size_t)bytes64 : 0;
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st0, n, ssq, 0.0);
     if (h->value_type == LSQR_F64)
-        hipLaunchKernelGGL((k_aprod2<double, double, double, true>), dim3(h->nb2), dim3(kBlock), lds,
-                           st0, s, (const double*)nullptr, ssq, h->wb, h->gpart_raw, lds_instr,
-                           (const Scalars*)nullptr);
+        hipLaunchKernelGGL((k_aprod2<double, double, double, true, true, true, kBlock2>),
+                           dim3(h->nb2), dim3(kBlock2), lds, st0, s, (const double*)nullptr, ssq,
+                           h->wb, h->gpart_raw, lds_instr, (const Scalars*)nullptr);
     else
-        hipLaunchKernelGGL((k_aprod2<float, double, double, true>), dim3(h->nb2), dim3(kBlock), lds,
-                           st0, s, (const double*)nullptr, ssq, h->wb, h->gpart_raw, lds_instr,
-                           (const Scalars*)nullptr);
+        hipLaunchKernelGGL((k_aprod2<float, double, double, true, true, true, kBlock2>),
+                           dim3(h->nb2), dim3(kBlock2), lds, st0, s, (const double*)nullptr, ssq,
+                           h->wb, h->gpart_raw, lds_instr, (const Scalars*)nullptr);
     hipLaunchKernelGGL((k_glob_sum<double>), dim3(1), dim3(kBlock), 0, st0, h->gpart_raw, h->nb2,
                        ssq + s.glob_base, (const Scalars*)nullptr);
     hipLaunchKernelGGL(k_make_p, dim3(h->nbc), dim3(kBlock), 0, st0, n, ssq, h->p, h->precondition);
