@@ -6,7 +6,10 @@ values (19.2 GB), 3 x 100,000 attitude columns, 6,000 instrumental columns,
 paper's system. A step is one LSQR iteration (aprod1, beta, aprod2, alpha,
 Givens rotation, x/w update, stopping tests); the timed region is one
 lsqr_solve of exactly `steps` iterations (stopping tests off) with HIP events
-around every aprod1 / aprod2 launch on the stream they run on.
+around every launch of the two row passes on the stream they run on: the
+fused pass (aprod1 with the astrometric, instrumental and global part of
+aprod2) and the row-reordered attitude pass. The same iterations with
+separate aprod1 / aprod2 launches are timed for comparison.
 
 Prints one JSON line.
 """
@@ -22,10 +25,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
-# algorithmic bytes per row and launch (FP64 values, configured index layout)
-BYTES_PER_ROW = {"aprod1": 24 * 8 + 40 + 16, "aprod2": 24 * 8 + 40 + 8}
+# Algorithmic bytes per row and launch (FP64 values, configured index layout:
+# int64 star, int64 attitude start, 6 int32 instrumental indices = 40 B).
+#   aprod1: 24 values + indices + u read and written
+#   aprod2: 24 values + indices + u read
+#   fused pass: as aprod1 (A is read once for both products)
+#   attitude pass: 12 reordered attitude values + int32 t and row + u gathered
+BYTES_PER_ROW = {"aprod1": 24 * 8 + 40 + 16, "aprod2": 24 * 8 + 40 + 8,
+                 "fused": 24 * 8 + 40 + 16, "attitude": 12 * 8 + 8 + 8}
 # FP32 values with FP32 work vectors (the inner solve of the refinement)
-BYTES_PER_ROW_F32 = {"aprod1": 24 * 4 + 40 + 8, "aprod2": 24 * 4 + 40 + 4}
+BYTES_PER_ROW_F32 = {"aprod1": 24 * 4 + 40 + 8, "aprod2": 24 * 4 + 40 + 4,
+                     "fused": 24 * 4 + 40 + 8, "attitude": 12 * 4 + 8 + 4}
+
+
+def pass_names(fused: bool):
+    """Names of the two timed row passes of an iteration."""
+    return ("fused", "attitude") if fused else ("aprod1", "aprod2")
+
+
+def pass_times(kt, fused: bool):
+    a, b = pass_names(fused)
+    return {a: kt["aprod1_ms"] / max(1, kt["aprod1_n"]),
+            b: kt["aprod2_ms"] / max(1, kt["aprod2_n"])}
 
 
 def log(*a):
@@ -101,8 +122,7 @@ def refine_leg(cfg: int, dev):
     g.solve_refined(b, 20, atol=0.0, btol=0.0, outer_limit=1)
     kt = g.kernel_times()
     g.set_option("profile", 0)
-    ms = {"aprod1": kt["aprod1_ms"] / max(1, kt["aprod1_n"]),
-          "aprod2": kt["aprod2_ms"] / max(1, kt["aprod2_n"])}
+    ms = pass_times(kt, True)
     out.update({
         "fp64_seconds": t_fp64, "fp64_itn": i64.itn, "fp64_istop": i64.istop,
         "refined_seconds": t_ref, "refined_inner_itn": i32.itn,
@@ -120,8 +140,11 @@ def refine_leg(cfg: int, dev):
 
 
 def attitude_ab(dev, cfg: int = 1, itn: int = 20):
-    """aprod1 / aprod2 times of the attitude variants on one system: device
-    atomics scatter vs the row-reordered pass, each astrometric reduction."""
+    """Row-pass times of the iteration variants on one system: fused pass vs
+    separate aprod1 / aprod2, attitude values interleaved or gathered from the
+    three axis windows, and for aprod2 the device-atomics attitude scatter vs
+    the row-reordered pass (u gathered or written in sorted order by aprod1),
+    each astrometric reduction."""
     import torch
 
     import synth
@@ -135,22 +158,23 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
     b = synth.device_noise(spec, m, 0, dev)
     g.aprod1(synth.device_x_true(spec, dev), b)
     out = {}
-    for att, scan, att4 in ((1, 0, 1), (1, 0, 0), (2, 0, 1), (1, 1, 1), (0, 0, 1)):
+    for fused, att, scan, il in ((1, 1, 0, 1), (1, 1, 0, 0), (0, 1, 0, 1), (0, 1, 0, 0),
+                                 (0, 2, 0, 1), (0, 1, 1, 1), (0, 0, 0, 1)):
+        g.set_option("fused", fused)
         g.set_option("att_mode", att)
         g.set_option("astro_scan", scan)
-        g.set_option("att4", att4)
+        g.set_option("att_interleave", il)
         g.set_option("tests", 0)
         g.set_option("profile", 1)
         g.solve(b, 2, atol=0.0, btol=0.0)
         x, info = g.solve(b, itn, atol=0.0, btol=0.0)
-        kt = g.kernel_times()
-        a1, a2 = kt["aprod1_ms"] / kt["aprod1_n"], kt["aprod2_ms"] / kt["aprod2_n"]
-        key = ("atomics", "reordered_gather", "reordered_u_written_sorted")[att] + \
-            ("_scan" if scan else "_flush") + ("" if att4 else "_aprod1_plain_att_gathers")
-        out[key] = {"aprod1_ms": a1, "aprod2_ms": a2,
-                    "aprod2_GBps": BYTES_PER_ROW["aprod2"] * m / (a2 * 1e-3) / 1e9,
-                    "rnorm": info.rnorm}
-        log(f"{key}: aprod1 {a1:.3f} ms, aprod2 {a2:.3f} ms")
+        ms = pass_times(g.kernel_times(), bool(fused and att == 1))
+        key = ("fused_" if fused else "") + \
+            ("atomics", "reordered_gather", "reordered_u_written_sorted")[att] + \
+            ("_scan" if scan else "_flush") + ("" if il else "_plain_att_gathers")
+        out[key] = {**{f"{k}_ms": v for k, v in ms.items()},
+                    "iteration_rows_ms": sum(ms.values()), "rnorm": info.rnorm}
+        log(f"{key}: " + ", ".join(f"{k} {v:.3f} ms" for k, v in ms.items()))
     g.close()
     print(json.dumps({"attitude_ab": out, "rows": m, "iterations": itn}))
 
@@ -294,11 +318,11 @@ def main():
     wall = time.perf_counter() - t1
     kt = g.kernel_times()
     assert info.itn == args.steps and kt["aprod1_n"] == args.steps == kt["aprod2_n"]
-    ms = {"aprod1": kt["aprod1_ms"] / kt["aprod1_n"], "aprod2": kt["aprod2_ms"] / kt["aprod2_n"]}
+    ms = pass_times(kt, True)
     gbps = {k: BYTES_PER_ROW[k] * m / (ms[k] * 1e-3) / 1e9 for k in ms}
     dom = max(ms, key=ms.get)
-    log(f"timed {args.steps} iterations in {wall:.3f} s; aprod1 {ms['aprod1']:.3f} ms "
-        f"({gbps['aprod1']:.0f} GB/s), aprod2 {ms['aprod2']:.3f} ms ({gbps['aprod2']:.0f} GB/s)")
+    log(f"timed {args.steps} iterations in {wall:.3f} s; " +
+        ", ".join(f"{k} {ms[k]:.3f} ms ({gbps[k]:.0f} GB/s)" for k in ms))
 
     # graph-replayed iterations (no events) for comparison
     g.set_option("profile", 0)
@@ -307,6 +331,20 @@ def main():
     g.solve(b, args.steps, atol=0.0, btol=0.0)
     torch.cuda.synchronize()
     wall_graph = time.perf_counter() - t2
+
+    # the same iterations with separate aprod1 / aprod2 launches
+    g.set_option("fused", 0)
+    g.set_option("profile", 1)
+    g.solve(b, 2, atol=0.0, btol=0.0)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    g.solve(b, args.steps, atol=0.0, btol=0.0)
+    torch.cuda.synchronize()
+    wall_unfused = time.perf_counter() - t3
+    ms_u = pass_times(g.kernel_times(), False)
+    g.set_option("fused", 1)
+    log(f"unfused: {args.steps / wall_unfused:.1f} iter/s; " +
+        ", ".join(f"{k} {v:.3f} ms" for k, v in ms_u.items()))
 
     result = {
         "metric": "LSQR iter/s + aprod HBM GB/s, FP64 vs FP32+refine & batched RHS at 1e-10 err",
@@ -330,6 +368,10 @@ def main():
         "kernels": {k: {"ms": ms[k], "GBps": gbps[k], "bytes_per_row": BYTES_PER_ROW[k],
                         "frac_of_peak": gbps[k] / HBM_PEAK_GBPS} for k in ms},
         "graph_iter_per_s": args.steps / wall_graph,
+        "unfused": {"iter_per_s": args.steps / wall_unfused,
+                    "kernels": {k: {"ms": v, "GBps": BYTES_PER_ROW[k] * m / (v * 1e-3) / 1e9,
+                                    "bytes_per_row": BYTES_PER_ROW[k]}
+                                for k, v in ms_u.items()}},
         "solve_info": {"itn": info.itn, "istop": info.istop, "rnorm": info.rnorm},
     }
     g.close()

@@ -126,10 +126,17 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *   LSQR_OPT_ATT_GROUP_ROWS  rows per block of the (row block, attitude start)
  *                         order (default 12,582,912: an FP64 row vector slice of
  *                         96 MB); settable only before the first solve or aprod2
- *   LSQR_OPT_ATT4         aprod1 reads the attitude values of a row from an
- *                         expanded copy of the attitude section (4 aligned values
- *                         per axis and start, rebuilt before every aprod1): 1
- *                         (default) or 0 (gathers straight from the vector)
+ *   LSQR_OPT_ATT_INTERLEAVE  aprod1 reads the 12 attitude values of a row from
+ *                         a copy of the attitude section interleaved by axis
+ *                         (x3[3 c + axis], rebuilt before every aprod1; the
+ *                         values are then consecutive): 1 (default) or 0
+ *                         (three 4-value windows straight from the vector)
+ *   LSQR_OPT_FUSED        1 (default): with LSQR_OPT_ATT_MODE 1, each LSQR
+ *                         iteration reads A once for aprod1 and the
+ *                         astrometric, instrumental and global part of aprod2
+ *                         (u~ = Abar v - alpha u is row-local, so every row's new
+ *                         value is scattered as soon as it is computed), then
+ *                         runs the attitude pass; 0: separate aprod1 and aprod2
  *   LSQR_OPT_KTILE        batched solves: right-hand sides advanced together per
  *                         pass over A (1, 2, 4, 8), 0 (default) = autotune once
  *                         per handle
@@ -144,7 +151,8 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_ASTRO_SCAN 8
 #define LSQR_OPT_KTILE 9
 #define LSQR_OPT_ATT_GROUP_ROWS 10
-#define LSQR_OPT_ATT4 11
+#define LSQR_OPT_ATT_INTERLEAVE 11
+#define LSQR_OPT_FUSED 12
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
 
 /* aprod mode 1, Eq. (2): y[m] += A x[n] with the raw (unscaled) A.
@@ -202,8 +210,10 @@ lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32
 lsqr_status lsqr_batch_tuning(lsqr_handle* h, int32_t* k_tile, double* ms_per_rhs_iter);
 
 /* Per-kernel timing of the last solve run with LSQR_OPT_PROFILE = 1:
- * total milliseconds and launch counts of the aprod1 and aprod2 kernels.
- * Host pointers; any may be NULL. */
+ * total milliseconds and launch counts of the aprod1 and aprod2 kernels of
+ * the iterations (with LSQR_OPT_FUSED: of the fused pass, which includes the
+ * attitude-interleave copy, and of the attitude pass). Host pointers; any may
+ * be NULL. */
 lsqr_status lsqr_kernel_times(lsqr_handle* h, double* ms_aprod1, int64_t* n_aprod1,
                               double* ms_aprod2, int64_t* n_aprod2);
 

@@ -108,9 +108,12 @@ struct Path {
     Acc* gpart = nullptr;  // [nb2] global-column partials
     Acc* S = nullptr;      // [(n_dfa-3)*12] attitude partials of the reordered pass
     Acc* us = nullptr;     // [m] u~ in attitude-sorted row order (reordered pass)
-    Acc* vp4 = nullptr;    // [3 (n_dfa-3) 4] expanded attitude section of vp
+    Acc* vp3 = nullptr;    // [3 n_dfa] attitude section of vp interleaved by axis
     size_t lds = 0;        // dynamic LDS bytes of aprod2
     int lds_instr = 0;
+    size_t lds_f = 0;      // dynamic LDS bytes of the fused pass
+    int f_instr = 0;       // fused pass: instrumental histogram in LDS
+    int f_ldsx = 0;        // fused pass: instrumental slice of vp in LDS
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
     bool ready = false;
@@ -138,7 +141,7 @@ struct lsqr_handle {
     double* v = nullptr;    // [n]
     double* w = nullptr;    // [n]
     double* y = nullptr;    // [n] iterate in the scaled space
-    double* part1 = nullptr;                    // [nb1]
+    double* part1 = nullptr;                    // [max(nb1, nb2)]
     double* partc = nullptr;                    // [nbc]
     double* partdd = nullptr;                   // [nbc]
     double* partxx = nullptr;                   // [nbc]
@@ -159,7 +162,7 @@ struct lsqr_handle {
     int64_t att_group_rows = 0;   // rows per block of the two-level sort
     int64_t att_groups = 1;       // row blocks: S has att_groups * (n_dfa - 3) segments
     double* S_raw = nullptr;      // [(n_dfa-3)*12] partials of lsqr_aprod2
-    double* x4_raw = nullptr;     // expanded attitude section of lsqr_aprod1's x
+    double* x3_raw = nullptr;     // interleaved attitude section of lsqr_aprod1's x
     bool att_ready = false;
 
     // batched right-hand sides (tile buffers for the largest K, reused per tile)
@@ -184,7 +187,8 @@ struct lsqr_handle {
     int profile = 0;
     int att_mode = 1;    // 0: attitude scatter with device atomics, 1: row-reordered pass
     int astro_scan = 0;  // 1: segmented scan per chunk, 0: accumulate-and-flush segments
-    int att4 = 1;        // aprod1 gathers attitude values from the expanded copy
+    int att_il = 1;      // aprod1 gathers attitude values from the interleaved copy
+    int fused = 1;       // one pass for aprod1 and the non-attitude part of aprod2
     double outer_tol = 1e-10;
     int ktile = 0;       // batched k-tile: 0 autotune, else 1, 2, 4 or 8
 
@@ -203,33 +207,81 @@ inline int64_t att_segments(const lsqr_handle* h)
 
 // ------------------------------------------------------------ launch helpers
 // aprod1 with the instrumental slice of x staged in LDS when it fits.
-// x4 (optional): expanded attitude section of x, already written (k_expand_att).
+// x3 (optional): interleaved attitude section of x, already written
+// (k_interleave_att).
 template <typename T, typename Acc, typename VX, typename VY, int MODE>
 void launch_aprod1(const lsqr_handle* h, const VX* x, VY* y, const double* b, const Scalars* sc,
-                   double* part, hipStream_t st, VY* ys = nullptr, const VX* x4 = nullptr)
+                   double* part, hipStream_t st, VY* ys = nullptr, const VX* x3 = nullptr)
 {
     const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(VX);
     const int32_t* ip = ys ? h->invperm : nullptr;
     const dim3 g(h->nb1), b1(kBlock1);
-    if (bytes <= kLdsXBudget && x4)
+    if (bytes <= kLdsXBudget && x3)
         hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, true, true>), g, b1,
-                           (size_t)bytes, st, h->sv, x, y, b, sc, part, ip, ys, x4);
+                           (size_t)bytes, st, h->sv, x, y, b, sc, part, ip, ys, x3);
     else if (bytes <= kLdsXBudget)
         hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, true, false>), g, b1,
-                           (size_t)bytes, st, h->sv, x, y, b, sc, part, ip, ys, x4);
-    else if (x4)
+                           (size_t)bytes, st, h->sv, x, y, b, sc, part, ip, ys, x3);
+    else if (x3)
         hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, false, true>), g, b1, 0, st,
-                           h->sv, x, y, b, sc, part, ip, ys, x4);
+                           h->sv, x, y, b, sc, part, ip, ys, x3);
     else
         hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, false, false>), g, b1, 0, st,
-                           h->sv, x, y, b, sc, part, ip, ys, x4);
+                           h->sv, x, y, b, sc, part, ip, ys, x3);
 }
 
 template <typename V>
-void launch_expand_att(const lsqr_handle* h, const V* x, V* x4, const Scalars* sc, hipStream_t st)
+void launch_interleave_att(const lsqr_handle* h, const V* x, V* x3, const Scalars* sc,
+                           hipStream_t st)
 {
-    hipLaunchKernelGGL((k_expand_att<V>), dim3(h->nbc), dim3(kBlock), 0, st, x, h->sv.att_base,
-                       h->sv.n_dfa, x4, sc);
+    hipLaunchKernelGGL((k_interleave_att<V>), dim3(h->nbc), dim3(kBlock), 0, st, x,
+                       h->sv.att_base, h->sv.n_dfa, x3, sc);
+}
+
+// The fused pass (aprod1 and the astrometric, instrumental and global part of
+// aprod2 in one sweep) over the main-pass grid.
+template <typename T, typename Acc>
+void launch_fused(const lsqr_handle* h, Path<Acc>& P, hipStream_t st)
+{
+    const dim3 g(h->nb2), bm(kBlock2);
+    const Acc* x3 = h->att_il ? (const Acc*)P.vp3 : nullptr;
+    if (P.f_ldsx && x3)
+        hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, true, true>), g, bm, P.lds_f, st, h->sv,
+                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
+                           h->sc);
+    else if (P.f_ldsx)
+        hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, true, false>), g, bm, P.lds_f, st, h->sv,
+                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
+                           h->sc);
+    else if (x3)
+        hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, false, true>), g, bm, P.lds_f, st, h->sv,
+                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
+                           h->sc);
+    else
+        hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, false, false>), g, bm, P.lds_f, st, h->sv,
+                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
+                           h->sc);
+}
+
+// Attitude part of aprod2 by the row-reordered pass: S = segment sums over the
+// sorted rows, then q_att += their combination.
+template <typename T, typename Acc>
+void launch_att_pass(lsqr_handle* h, const Acc* u, Acc* q, Acc* S, const Scalars* sc,
+                     hipStream_t st, const Acc* us = nullptr)
+{
+    const dim3 ga(h->nba), b(kBlock);
+    const int64_t ns = att_segments(h) * kAxes * kParAxis;
+    hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), b, 0, st, ns, S, (Acc)0);
+    if (us)
+        hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, true>), ga, b, 0, st, h->sv.m,
+                           (const T*)h->att_sorted, (const int32_t*)h->perm,
+                           (const int32_t*)h->tkey, us, S, h->wb_att, sc);
+    else
+        hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, false>), ga, b, 0, st, h->sv.m,
+                           (const T*)h->att_sorted, (const int32_t*)h->perm,
+                           (const int32_t*)h->tkey, u, S, h->wb_att, sc);
+    hipLaunchKernelGGL((k_att_combine<Acc>), dim3(h->nbc), b, 0, st, (const Acc*)S, h->sv.n_dfa,
+                       h->att_groups, q + h->sv.att_base, sc);
 }
 
 // q += A^T u for the LSQR loop (and lsqr_aprod2): the main pass over the rows
@@ -241,7 +293,7 @@ template <typename T, typename Acc>
 void launch_aprod2(lsqr_handle* h, const Acc* u, Acc* q, Acc* gpart, Acc* S, size_t lds,
                    int lds_instr, const Scalars* sc, hipStream_t st, const Acc* us = nullptr)
 {
-    const dim3 g(h->nb2), bm(kBlock2), ga(h->nba), b(kBlock);
+    const dim3 g(h->nb2), bm(kBlock2), b(kBlock);
     const bool att = h->att_mode == 0;
     if (att && h->astro_scan)
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, true, kBlock2>), g, bm, lds, st, h->sv,
@@ -256,36 +308,39 @@ void launch_aprod2(lsqr_handle* h, const Acc* u, Acc* q, Acc* gpart, Acc* S, siz
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, false, kBlock2>), g, bm, lds, st,
                            h->sv, u, q, h->wb, gpart, lds_instr, sc);
     hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), b, 0, st, gpart, h->nb2, q + h->sv.glob_base, sc);
-    if (!att) {
-        const int64_t ns = att_segments(h) * kAxes * kParAxis;
-        hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), b, 0, st, ns, S, (Acc)0);
-        if (us)
-            hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, true>), ga, b, 0, st, h->sv.m,
-                               (const T*)h->att_sorted, (const int32_t*)h->perm,
-                               (const int32_t*)h->tkey, us, S, h->wb_att, sc);
-        else
-            hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, false>), ga, b, 0, st, h->sv.m,
-                               (const T*)h->att_sorted, (const int32_t*)h->perm,
-                               (const int32_t*)h->tkey, u, S, h->wb_att, sc);
-        hipLaunchKernelGGL((k_att_combine<Acc>), dim3(h->nbc), b, 0, st, (const Acc*)S,
-                           h->sv.n_dfa, h->att_groups, q + h->sv.att_base, sc);
-    }
+    if (!att) launch_att_pass<T, Acc>(h, u, q, S, sc, st, us);
 }
 
-// One LSQR iteration; ev (optional) = 4 events bracketing aprod1 and aprod2.
+// The fused pass serves the default attitude mode (row-reordered pass with u
+// gathered through the permutation).
+inline bool use_fused(const lsqr_handle* h) { return h->fused && h->att_mode == 1; }
+
+// One LSQR iteration; ev (optional) = 4 events bracketing aprod1 and aprod2
+// (with the fused pass: that pass, and the attitude pass).
 template <typename T, typename Acc>
 void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* ev)
 {
     const int64_t n = h->sv.n;
     if (ev) (void)hipEventRecord(ev[0], st);
-    Acc* us = h->att_mode == 2 ? P.us : nullptr;
-    if (h->att4) launch_expand_att<Acc>(h, P.vp, P.vp4, h->sc, st);
-    launch_aprod1<T, Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u, nullptr, h->sc, h->part1,
-                                            st, us, h->att4 ? (const Acc*)P.vp4 : nullptr);
-    if (ev) (void)hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
-    if (ev) (void)hipEventRecord(ev[2], st);
-    launch_aprod2<T, Acc>(h, P.u, P.q, P.gpart, P.S, P.lds, P.lds_instr, h->sc, st, us);
+    if (h->att_il) launch_interleave_att<Acc>(h, P.vp, P.vp3, h->sc, st);
+    if (use_fused(h)) {
+        launch_fused<T, Acc>(h, P, st);
+        if (ev) (void)hipEventRecord(ev[1], st);
+        hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb2, h->sc);
+        if (ev) (void)hipEventRecord(ev[2], st);
+        hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), dim3(kBlock), 0, st, P.gpart, h->nb2,
+                           P.q + h->sv.glob_base, h->sc);
+        launch_att_pass<T, Acc>(h, P.u, P.q, P.S, h->sc, st);
+    } else {
+        Acc* us = h->att_mode == 2 ? P.us : nullptr;
+        launch_aprod1<T, Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u, nullptr, h->sc,
+                                                h->part1, st, us,
+                                                h->att_il ? (const Acc*)P.vp3 : nullptr);
+        if (ev) (void)hipEventRecord(ev[1], st);
+        hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
+        if (ev) (void)hipEventRecord(ev[2], st);
+        launch_aprod2<T, Acc>(h, P.u, P.q, P.gpart, P.S, P.lds, P.lds_instr, h->sc, st, us);
+    }
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
                        h->sc, h->partc);
@@ -329,10 +384,16 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     LSQR_TRY(dalloc(&P.gpart, h->nb2));
     LSQR_TRY(dalloc(&P.S, att_segments(h) * kAxes * kParAxis));
     LSQR_TRY(dalloc(&P.us, m));
-    LSQR_TRY(dalloc(&P.vp4, (int64_t)kAxes * (h->sv.n_dfa - kParAxis + 1) * kParAxis));
+    LSQR_TRY(dalloc(&P.vp3, (int64_t)kAxes * h->sv.n_dfa));
     const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(Acc);
     P.lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
     P.lds = P.lds_instr ? (size_t)bytes : 0;
+    // fused pass: the histogram first (device atomics otherwise cost far
+    // more), then the slice of vp if both fit
+    P.f_instr = P.lds_instr;
+    const int64_t hist = P.f_instr ? (bytes + 15) & ~(int64_t)15 : 0;
+    P.f_ldsx = hist + bytes <= kLdsInstrBudget ? 1 : 0;
+    P.lds_f = (size_t)(P.f_ldsx ? hist + bytes : hist);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n, P.q, (Acc)0);
     HIP_TRY(hipGetLastError());
     P.ready = true;
@@ -417,7 +478,7 @@ void release_path(Path<Acc>& P)
     dfree(P.gpart);
     dfree(P.S);
     dfree(P.us);
-    dfree(P.vp4);
+    dfree(P.vp3);
     P.ready = false;
 }
 
@@ -967,7 +1028,7 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     if ((st = dalloc(&h->v, n)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->w, n)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->y, n)) != LSQR_OK) return bail(st);
-    if ((st = dalloc(&h->part1, h->nb1)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->part1, std::max(h->nb1, h->nb2))) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->partc, h->nbc)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->partdd, h->nbc)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->partxx, h->nbc)) != LSQR_OK) return bail(st);
@@ -1045,7 +1106,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h)
     dfree(h->perm);
     dfree(h->tkey);
     dfree(h->invperm);
-    dfree(h->x4_raw);
+    dfree(h->x3_raw);
     dfree(h->wb_att);
     dfree(h->S_raw);
     if (h->att_sorted) (void)hipFree(h->att_sorted);
@@ -1104,15 +1165,19 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         slot = v;
         return LSQR_OK;
     }
-    case LSQR_OPT_ATT4:
-        if (h->att4 != (value != 0.0 ? 1 : 0)) {
+    case LSQR_OPT_ATT_INTERLEAVE:
+    case LSQR_OPT_FUSED: {
+        const int v = value != 0.0 ? 1 : 0;
+        int& slot = option == LSQR_OPT_FUSED ? h->fused : h->att_il;
+        if (slot != v) {
             if (h->p64.graph) (void)hipGraphExecDestroy(h->p64.graph);
             if (h->p32.graph) (void)hipGraphExecDestroy(h->p32.graph);
             h->p64.graph = nullptr;
             h->p32.graph = nullptr;
         }
-        h->att4 = value != 0.0 ? 1 : 0;
+        slot = v;
         return LSQR_OK;
+    }
     case LSQR_OPT_KTILE:
         if (!(value == 0.0 || value == 1.0 || value == 2.0 || value == 4.0 || value == 8.0))
             return fail(LSQR_E_INVALID, "k-tile must be 0 (autotune), 1, 2, 4 or 8");
@@ -1140,19 +1205,18 @@ lsqr_status lsqr_aprod1(lsqr_handle* h, const double* x, double* y)
 {
     LSQR_TRY(check_handle(h));
     if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
-    const double* x4 = nullptr;
-    if (h->att4) {
-        if (!h->x4_raw)
-            LSQR_TRY(dalloc(&h->x4_raw, (int64_t)kAxes * (h->sv.n_dfa - kParAxis + 1) * kParAxis));
-        launch_expand_att<double>(h, x, h->x4_raw, nullptr, h->user_stream);
-        x4 = h->x4_raw;
+    const double* x3 = nullptr;
+    if (h->att_il) {
+        if (!h->x3_raw) LSQR_TRY(dalloc(&h->x3_raw, (int64_t)kAxes * h->sv.n_dfa));
+        launch_interleave_att<double>(h, x, h->x3_raw, nullptr, h->user_stream);
+        x3 = h->x3_raw;
     }
     if (h->value_type == LSQR_F64)
         launch_aprod1<double, double, double, double, A1_ACCUM>(h, x, y, nullptr, nullptr, nullptr,
-                                                                h->user_stream, nullptr, x4);
+                                                                h->user_stream, nullptr, x3);
     else
         launch_aprod1<float, double, double, double, A1_ACCUM>(h, x, y, nullptr, nullptr, nullptr,
-                                                               h->user_stream, nullptr, x4);
+                                                               h->user_stream, nullptr, x3);
     HIP_TRY(hipGetLastError());
     return LSQR_OK;
 }
@@ -1237,17 +1301,15 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
         // relative decrease of ||Abar^T r|| (tolerance atol) or the itn limit.
         LSQR_TRY(upload_controls(h, itn_limit, 0.0, 0.0, std::max(atol, 1e-300)));
         // FP64 residual of the full problem, stored as the FP32 start vector
-        const double* x4 = nullptr;
-        if (h->att4) {
-            if (!h->x4_raw)
-                LSQR_TRY(dalloc(&h->x4_raw,
-                                (int64_t)kAxes * (h->sv.n_dfa - kParAxis + 1) * kParAxis));
-            launch_expand_att<double>(h, x, h->x4_raw, nullptr, h->stream);
-            x4 = h->x4_raw;
+        const double* x3 = nullptr;
+        if (h->att_il) {
+            if (!h->x3_raw) LSQR_TRY(dalloc(&h->x3_raw, (int64_t)kAxes * h->sv.n_dfa));
+            launch_interleave_att<double>(h, x, h->x3_raw, nullptr, h->stream);
+            x3 = h->x3_raw;
         }
         launch_aprod1<float, double, double, float, A1_RESID>(h, (const double*)x, P.u, b, nullptr,
                                                               h->part1, h->stream,
-                                                              h->att_mode == 2 ? P.us : nullptr, x4);
+                                                              h->att_mode == 2 ? P.us : nullptr, x3);
         launch_init<float, float>(h, P, h->stream, true);
         HIP_TRY(hipGetLastError());
         LSQR_TRY(read_scalars(h));

@@ -74,19 +74,19 @@ def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("att4", [1, 0])
+@pytest.mark.parametrize("interleave", [1, 0])
 @pytest.mark.parametrize("name", list(SPECS))
-def test_aprod1_parity(torch_cuda, name, att4):
+def test_aprod1_parity(torch_cuda, name, interleave):
     torch = torch_cuda
     S, o = system(name)
-    say(f"aprod1 parity: {name} m={S.m} n={o.n} seed={S.spec.seed} att4={att4}")
+    say(f"aprod1 parity: {name} m={S.m} n={o.n} seed={S.spec.seed} interleave={interleave}")
     rng = np.random.default_rng(5)
     x = rng.standard_normal(o.n)
     y0 = rng.standard_normal(o.m)
     want = o.aprod1(x, y0)
     bound = abs_system(S).aprod1(np.abs(x), np.abs(y0))
     g = gpu_system(torch, S)
-    g.set_option("att4", att4)
+    g.set_option("att_interleave", interleave)
     yd = torch.from_numpy(y0).cuda()
     g.aprod1(torch.from_numpy(x).cuda(), yd)
     torch.cuda.synchronize()
@@ -157,20 +157,30 @@ def test_solve_variants(torch_cuda, name, itn, variant):
 
 
 @pytest.mark.parametrize("name,itn", [("c0", 50), ("wide_instr", 40)])
-def test_solve_without_expanded_attitude(torch_cuda, name, itn):
-    _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], att4=0)
+def test_solve_without_interleaved_attitude(torch_cuda, name, itn):
+    _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], interleave=0)
 
 
-def _solve_fixed(torch_cuda, name, itn, graph, variant, att4=1):
+# The fused pass (default) against separate aprod1/aprod2 launches of the same
+# attitude mode: both must match the oracle.
+@pytest.mark.parametrize("name,itn", [("c0", 60), ("ragged", 60), ("one_star", 15),
+                                       ("few_rows", 15), ("wide_instr", 40)])
+def test_solve_unfused(torch_cuda, name, itn):
+    _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], fused=0)
+
+
+def _solve_fixed(torch_cuda, name, itn, graph, variant, interleave=1, fused=1):
     torch = torch_cuda
     S, o = system(name)
     b = _b(S, o)
     x_ref, i_ref = o.lsqr(b, itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)
-    say(f"solve parity: {name} itn={itn} graph={graph} variant={variant}")
+    say(f"solve parity: {name} itn={itn} graph={graph} variant={variant} "
+        f"interleave={interleave} fused={fused}")
     g = gpu_system(torch, S)
     g.set_option("att_mode", variant[0])
     g.set_option("astro_scan", variant[1])
-    g.set_option("att4", att4)
+    g.set_option("att_interleave", interleave)
+    g.set_option("fused", fused)
     if graph:
         g.set_option("att_group_rows", 4096)
     g.set_option("tests", 0)
