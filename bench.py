@@ -176,6 +176,22 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
                     "iteration_rows_ms": sum(ms.values()), "rnorm": info.rnorm}
         log(f"{key}: " + ", ".join(f"{k} {v:.3f} ms" for k, v in ms.items()))
     g.close()
+    # row-block size of the attitude order (fused default path; a fresh handle
+    # per size, the option is fixed once the reordering exists)
+    for rows in (1 << 20, 1 << 22, 1 << 24, 1 << 26):
+        g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
+                       n_instr_cols=spec.n_instr_cols)
+        g.set_option("att_group_rows", rows)
+        g.set_option("tests", 0)
+        g.set_option("profile", 1)
+        g.solve(b, 2, atol=0.0, btol=0.0)
+        x, info = g.solve(b, itn, atol=0.0, btol=0.0)
+        ms = pass_times(g.kernel_times(), True)
+        key = f"fused_att_group_rows_{rows}"
+        out[key] = {**{f"{k}_ms": v for k, v in ms.items()},
+                    "iteration_rows_ms": sum(ms.values()), "rnorm": info.rnorm}
+        log(f"{key}: " + ", ".join(f"{k} {v:.3f} ms" for k, v in ms.items()))
+        g.close()
     print(json.dumps({"attitude_ab": out, "rows": m, "iterations": itn}))
 
 

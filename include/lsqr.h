@@ -124,8 +124,9 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         per-lane partials reduced only where a star ends;
  *                         1 a segmented scan over every 64-row chunk
  *   LSQR_OPT_ATT_GROUP_ROWS  rows per block of the (row block, attitude start)
- *                         order (default 12,582,912: an FP64 row vector slice of
- *                         96 MB); settable only before the first solve or aprod2
+ *                         order (default 2^26, >= 64); the attitude pass sweeps
+ *                         the blocks one after another; settable only before the
+ *                         first solve or aprod2
  *   LSQR_OPT_ATT_INTERLEAVE  aprod1 reads the 12 attitude values of a row from
  *                         a copy of the attitude section interleaved by axis
  *                         (x3[3 c + axis], rebuilt before every aprod1; the

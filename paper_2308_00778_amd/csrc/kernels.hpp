@@ -369,6 +369,26 @@ __device__ __forceinline__ void seg_finish(SegAcc<Acc, NV>& S, int lane, Emit&& 
     S.key = -1;
 }
 
+// Stateless variant: every segment present in the chunk is reduced and
+// emitted at once (a segment spanning several chunks is emitted once per
+// chunk, so emit must accumulate). Keeps no registers across chunks.
+template <typename Acc, int NV, typename Emit>
+__device__ __forceinline__ void seg_flush(int64_t key, const Acc (&v)[NV], int lane, Emit&& emit)
+{
+    uint64_t rest = __ballot(key != kNoStar);
+    while (rest != 0) {
+        const int l0 = __ffsll((unsigned long long)rest) - 1;
+        const int64_t k2 = __shfl(key, l0);
+        const bool mine = key == k2;
+        const uint64_t same = __ballot(mine);
+        Acc t[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) t[j] = wave_sum(mine ? v[j] : (Acc)0);
+        if (lane == 0) emit(k2, t);
+        rest &= ~same;
+    }
+}
+
 // x += A^T y (SQUARE: x_j += sum of squared coefficients of column j, used
 // for the column norms). wb: star-aligned row boundaries, one range per wave
 // (gridDim.x * kWavesPerBlock ranges). The instrumental columns are
@@ -1004,6 +1024,28 @@ __global__ __launch_bounds__(kBlock) void k_wave_bounds(const K* __restrict__ st
     wb[g] = r;
 }
 
+// Per-block t-aligned ranges of the sorted rows: block g occupies sorted
+// positions [g R, min((g+1) R, m)); its range w starts at the first key change
+// at or after g R + w len / nw (wb[g (nw + 1) + w], w = 0..nw).
+__global__ __launch_bounds__(kBlock) void k_group_bounds(const int32_t* __restrict__ key,
+                                                          int64_t m, int64_t group_rows,
+                                                          int64_t ngroups, int64_t nw,
+                                                          int64_t* __restrict__ wb)
+{
+    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= ngroups * (nw + 1)) return;
+    const int64_t g = idx / (nw + 1), w = idx - g * (nw + 1);
+    const int64_t b0 = g * group_rows;
+    const int64_t b1 = b0 + group_rows < m ? b0 + group_rows : m;
+    if (w == nw) {
+        wb[idx] = b1;
+        return;
+    }
+    int64_t r = b0 + w * (b1 - b0) / nw;  // nw <= 2^20, block < 2^31: no overflow
+    while (r > b0 && r < b1 && key[r] == key[r - 1]) ++r;
+    wb[idx] = r;
+}
+
 // p_j = 1/sqrt(ssq_j), 1 for an empty column (or for every column when not
 // preconditioning); resets ssq.
 __global__ __launch_bounds__(kBlock) void k_make_p(int64_t n, double* __restrict__ ssq,
@@ -1071,40 +1113,47 @@ __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val
     }
 }
 
-// S[t][12] = sum over rows with attitude start t of a_att * u, over t-aligned
-// per-wave ranges of the sorted rows (each t owned by one wave: plain stores).
+// S[key][12] = sum over rows with sort key (row block, attitude start) of
+// a_att * u: each key is one segment of the sorted rows, owned by one wave
+// (plain stores). Row block g occupies sorted positions [g R, (g+1) R); every
+// wave takes its t-aligned slice of block 0, then of block 1, and so on
+// (wb[g (nw + 1) + wave]), so that at any time the waves gather u from one
+// block's slice of the row vector, which stays in the last-level cache.
 // SEQ: u is already in sorted order (written by aprod1), else gathered as
 // u[perm[k]].
 template <typename T, typename Acc, typename VU, bool SEQ = false>
 __global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
     int64_t m, const T* __restrict__ att_sorted, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ tkey, const VU* __restrict__ u, Acc* __restrict__ S,
-    const int64_t* __restrict__ wb, const Scalars* __restrict__ sc)
+    const int64_t* __restrict__ wb, int64_t ngroups, const Scalars* __restrict__ sc)
 {
     constexpr int kAtt = kAxes * kParAxis;
     if (sc != nullptr && (sc->done || sc->beta_zero)) return;
     const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    const int64_t rb = wb[wave], re = wb[wave + 1];
-    SegAcc<Acc, kAtt> seg;
     auto emit = [S](int64_t t, const Acc (&tot)[kAtt]) {
 #pragma unroll
         for (int j = 0; j < kAtt; ++j) S[t * kAtt + j] = tot[j];
     };
-    for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
-        const int64_t k = r0 + lane;
-        const bool ok = k >= rb && k < re;
-        const int64_t kc = k < rb ? rb : (k < re ? k : re - 1);
-        const int64_t t = k < re ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
-        Acc ui = (Acc)0;
-        if (SEQ) ui = ok ? (Acc)ldnt(&u[kc]) : (Acc)0;
-        else ui = ok ? (Acc)u[ldnt(&perm[kc])] : (Acc)0;
-        Acc v[kAtt];
+    for (int64_t g = 0; g < ngroups; ++g) {
+        const int64_t rb = wb[g * (nw + 1) + wave], re = wb[g * (nw + 1) + wave + 1];
+        SegAcc<Acc, kAtt> seg;
+        for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
+            const int64_t k = r0 + lane;
+            const bool ok = k >= rb && k < re;
+            const int64_t kc = k < rb ? rb : (k < re ? k : re - 1);
+            const int64_t t = k < re ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
+            Acc ui = (Acc)0;
+            if (SEQ) ui = ok ? (Acc)ldnt(&u[kc]) : (Acc)0;
+            else ui = ok ? (Acc)u[ldnt(&perm[kc])] : (Acc)0;
+            Acc v[kAtt];
 #pragma unroll
-        for (int c = 0; c < kAtt; ++c) v[c] = (Acc)ldnt(&att_sorted[c * m + kc]) * ui;
-        seg_chunk(seg, t, v, lane, emit);
+            for (int c = 0; c < kAtt; ++c) v[c] = (Acc)ldnt(&att_sorted[c * m + kc]) * ui;
+            seg_chunk(seg, t, v, lane, emit);
+        }
+        seg_finish(seg, lane, emit);
     }
-    seg_finish(seg, lane, emit);
 }
 
 // q[att_base + a n_dfa + c] += sum over row blocks g and parameters q of
@@ -1377,6 +1426,187 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const Acc* __restrict_
     if (lds_instr) {
         for (int64_t j = threadIdx.x; j < ninst * K; j += NT) {
             const Acc v = lds[j];
+            if (v != (Acc)0) atomicAdd(&qins[j], v);
+        }
+    }
+}
+
+// X3[(3 c + axis) K + r] = VP[(att_base + axis n_dfa + c) K + r]: the attitude
+// section interleaved by axis, K values per column kept together.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_interleave_att(const double* __restrict__ VP,
+                                                            int64_t att_base, int64_t n_dfa,
+                                                            double* __restrict__ X3)
+{
+    const int64_t total = (int64_t)kAxes * n_dfa * K;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * kBlock) {
+        const int64_t col = j / K, r = j - col * K;
+        const int64_t c = col / kAxes, ax = col - c * kAxes;
+        X3[j] = VP[(att_base + ax * n_dfa + c) * K + r];
+    }
+}
+
+// Fused iteration pass of a K-tile (the batched form of the single-RHS fused
+// pass): per row, U~_r = Abar VP_r - coef_r U_r for every live RHS r, written
+// with its FP64 sum of squares per workgroup (part[blk][K]), and the same
+// registers scattered into Q += A^T U~ for the astrometric, instrumental and
+// global columns. Frozen RHS keep U and contribute nothing. Dynamic LDS: the
+// instrumental histogram [n_instr_cols][K] (lds_instr), then the
+// instrumental slice of VP (LDSX). In 1024-thread workgroups (128 registers
+// per lane) a multi-RHS tile reduces its star segments chunk by chunk instead
+// of carrying 5K running sums.
+template <typename T, typename Acc, int K, int NT, bool LDSX, bool ATTI>
+__global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ VP,
+                                               const Acc* __restrict__ X3, Acc* __restrict__ U,
+                                               Acc* __restrict__ Q, const int64_t* __restrict__ wb,
+                                               Acc* __restrict__ gpart, double* __restrict__ part,
+                                               int lds_instr, const Scalars* __restrict__ sc)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ Acc gred[K * (NT / kWave)];
+    __shared__ double sred[K * (NT / kWave)];
+    const uint32_t live = live_mask<K>(sc);
+    if (live == 0) return;
+    const T* __restrict__ val = static_cast<const T*>(s.val);
+    const int64_t m = s.m;
+    const int64_t ninst = s.n_instr_cols;
+    Acc* hist = reinterpret_cast<Acc*>(smem_raw);
+    const Acc* xi = VP + s.instr_base * K;
+    if (lds_instr)
+        for (int64_t j = threadIdx.x; j < ninst * K; j += NT) hist[j] = (Acc)0;
+    if (LDSX) {
+        const int64_t off =
+            lds_instr ? (ninst * K * (int64_t)sizeof(Acc) + 15) & ~(int64_t)15 : 0;
+        Acc* xl = reinterpret_cast<Acc*>(smem_raw + off);
+        for (int64_t j = threadIdx.x; j < ninst * K; j += NT) xl[j] = xi[j];
+        xi = xl;
+    }
+    if (lds_instr || LDSX) __syncthreads();
+
+    Acc coef[K], xg[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        coef[r] = (Acc)sc[r].coef_u;
+        xg[r] = VP[s.glob_base * K + r];
+    }
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave;
+    const int64_t rb = wb[wave], re = wb[wave + 1];
+    Acc* __restrict__ qins = Q + s.instr_base * K;
+    double ssq[K];
+    Acc gsum[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        ssq[r] = 0.0;
+        gsum[r] = (Acc)0;
+    }
+    constexpr bool kChunkFlush = NT > kBlock && K > 1;
+    SegAcc<Acc, kChunkFlush ? 1 : kAstro * K> seg;
+    auto astro_emit = [Q](int64_t star, const Acc (&tot)[kAstro * K]) {
+        Acc* dst = Q + kAstro * star * K;
+#pragma unroll
+        for (int j = 0; j < kAstro * K; ++j) dst[j] += tot[j];
+    };
+    for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
+        const int64_t i = r0 + lane;
+        const bool ok = i >= rb && i < re;
+        const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
+        const int64_t stc = ldnt(&s.star[ic]);
+        const int64_t st = i < re ? stc : kNoStar;
+        const int64_t t = ldnt(&s.att[ic]);
+        T a[kPar];
+#pragma unroll
+        for (int c = 0; c < kPar; ++c) a[c] = ldnt(&val[c * m + ic]);
+        int32_t ix[kInstr];
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
+
+        Acc d[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) d[r] = (Acc)0;
+        const Acc* xa = VP + kAstro * stc * K;
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j)
+#pragma unroll
+            for (int r = 0; r < K; ++r) d[r] += (Acc)a[j] * xa[j * K + r];
+#pragma unroll
+        for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+            for (int qq = 0; qq < kParAxis; ++qq) {
+                const Acc* xv = ATTI ? X3 + (kAxes * (t + qq) + ax) * K
+                                     : VP + (s.att_base + ax * s.n_dfa + t + qq) * K;
+                const Acc av = (Acc)a[kOffAtt + ax * kParAxis + qq];
+#pragma unroll
+                for (int r = 0; r < K; ++r) d[r] += av * xv[r];
+            }
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j)
+#pragma unroll
+            for (int r = 0; r < K; ++r) d[r] += (Acc)a[kOffInstr + j] * xi[ix[j] * K + r];
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            d[r] += (Acc)a[kOffGlob] * xg[r];
+            const bool on = ok && ((live >> r) & 1u);
+            const Acc nu = d[r] - coef[r] * U[ic * K + r];
+            if (on) U[ic * K + r] = nu;
+            d[r] = on ? nu : (Acc)0;
+            ssq[r] += (double)d[r] * (double)d[r];
+        }
+        if (ok) {
+#pragma unroll
+            for (int j = 0; j < kInstr; ++j) {
+                const Acc av = (Acc)a[kOffInstr + j];
+#pragma unroll
+                for (int r = 0; r < K; ++r) {
+                    if (!((live >> r) & 1u)) continue;
+                    if (lds_instr) atomicAdd(&hist[ix[j] * K + r], av * d[r]);
+                    else atomicAdd(&qins[ix[j] * K + r], av * d[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < K; ++r) gsum[r] += (Acc)a[kOffGlob] * d[r];
+        Acc pa[kAstro * K];
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j)
+#pragma unroll
+            for (int r = 0; r < K; ++r) pa[j * K + r] = (Acc)a[j] * d[r];
+        if (kChunkFlush) {
+            seg_flush(st, pa, lane, astro_emit);
+        } else {
+            if constexpr (!kChunkFlush) seg_chunk(seg, st, pa, lane, astro_emit);
+        }
+    }
+    if constexpr (!kChunkFlush) seg_finish(seg, lane, astro_emit);
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            gsum[r] += __shfl_down(gsum[r], off);
+            ssq[r] += __shfl_down(ssq[r], off);
+        }
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            gred[r * (NT / kWave) + threadIdx.x / kWave] = gsum[r];
+            sred[r * (NT / kWave) + threadIdx.x / kWave] = ssq[r];
+        }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        Acc g = (Acc)0;
+        double q2 = 0.0;
+        for (int k = 0; k < NT / kWave; ++k) {
+            g += gred[threadIdx.x * (NT / kWave) + k];
+            q2 += sred[threadIdx.x * (NT / kWave) + k];
+        }
+        gpart[(int64_t)blockIdx.x * K + threadIdx.x] = g;
+        part[(int64_t)blockIdx.x * K + threadIdx.x] = q2;
+    }
+    if (lds_instr) {
+        for (int64_t j = threadIdx.x; j < ninst * K; j += NT) {
+            const Acc v = hist[j];
             if (v != (Acc)0) atomicAdd(&qins[j], v);
         }
     }
@@ -1677,7 +1907,7 @@ template <typename T, typename Acc, int K>
 __global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
     int64_t m, const T* __restrict__ att_sorted, const int32_t* __restrict__ perm,
     const int32_t* __restrict__ tkey, const Acc* __restrict__ U, Acc* __restrict__ S,
-    const int64_t* __restrict__ wb, const Scalars* __restrict__ sc)
+    const int64_t* __restrict__ wb, int64_t ngroups, const Scalars* __restrict__ sc)
 {
     constexpr int kAtt = kAxes * kParAxis;
     uint32_t live = 0;
@@ -1685,32 +1915,36 @@ __global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
     for (int r = 0; r < K; ++r) live |= ((sc[r].done || sc[r].beta_zero) ? 0u : 1u) << r;
     if (live == 0) return;
     const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    const int64_t rb = wb[wave], re = wb[wave + 1];
-    SegAcc<Acc, kAtt * K> seg;
     auto emit = [S](int64_t t, const Acc (&tot)[kAtt * K]) {
 #pragma unroll
         for (int j = 0; j < kAtt * K; ++j) S[t * kAtt * K + j] = tot[j];
     };
-    for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
-        const int64_t k = r0 + lane;
-        const bool ok = k >= rb && k < re;
-        const int64_t kc = k < rb ? rb : (k < re ? k : re - 1);
-        const int64_t t = k < re ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
-        const int64_t i = ldnt(&perm[kc]);
-        Acc u[K];
+    for (int64_t g = 0; g < ngroups; ++g) {
+        const int64_t rb = wb[g * (nw + 1) + wave], re = wb[g * (nw + 1) + wave + 1];
+        SegAcc<Acc, kAtt * K> seg;
+        for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
+            const int64_t k = r0 + lane;
+            const bool ok = k >= rb && k < re;
+            const int64_t kc = k < rb ? rb : (k < re ? k : re - 1);
+            const int64_t t = k < re ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
+            const int64_t i = ldnt(&perm[kc]);
+            Acc u[K];
 #pragma unroll
-        for (int r = 0; r < K; ++r) u[r] = (ok && ((live >> r) & 1u)) ? U[i * K + r] : (Acc)0;
-        Acc v[kAtt * K];
+            for (int r = 0; r < K; ++r)
+                u[r] = (ok && ((live >> r) & 1u)) ? U[i * K + r] : (Acc)0;
+            Acc v[kAtt * K];
 #pragma unroll
-        for (int c = 0; c < kAtt; ++c) {
-            const Acc a = (Acc)ldnt(&att_sorted[c * m + kc]);
+            for (int c = 0; c < kAtt; ++c) {
+                const Acc a = (Acc)ldnt(&att_sorted[c * m + kc]);
 #pragma unroll
-            for (int r = 0; r < K; ++r) v[c * K + r] = a * u[r];
+                for (int r = 0; r < K; ++r) v[c * K + r] = a * u[r];
+            }
+            seg_chunk(seg, t, v, lane, emit);
         }
-        seg_chunk(seg, t, v, lane, emit);
+        seg_finish(seg, lane, emit);
     }
-    seg_finish(seg, lane, emit);
 }
 
 template <typename Acc, int K>

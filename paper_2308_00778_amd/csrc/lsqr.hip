@@ -97,7 +97,11 @@ constexpr int kBlock2 = 1024;                   // aprod2 main-pass workgroup si
 constexpr int kWavesPerCU = 16;                 // row ranges per compute unit in aprod2
 // Rows per block of the two-level attitude sort: the block's slice of an FP64
 // row vector (8 B/row) stays well inside the 256 MB last-level cache.
-constexpr int64_t kAttGroupBytes = 96ll << 20;
+// Rows per block of the (row block, attitude start) order. Measured on the
+// 1e8-row system: 2^26 rows per block (2 blocks) 3.2 ms per attitude pass,
+// 2^24 3.3 ms, 2^22 4.2 ms, 2^20 15 ms: longer segments and fewer block
+// switches win over a smaller gather footprint.
+constexpr int64_t kAttGroupRows = (int64_t)1 << 26;
 
 // Working vectors of one arithmetic precision of the LSQR loop.
 template <typename Acc>
@@ -158,7 +162,7 @@ struct lsqr_handle {
     int32_t* tkey = nullptr;      // [m] attitude start of each sorted row
     int32_t* invperm = nullptr;   // [m] sorted position of each row
     void* att_sorted = nullptr;   // [12][m] attitude coefficients in sorted order
-    int64_t* wb_att = nullptr;    // [nw + 1] t-aligned ranges of the sorted rows
+    int64_t* wb_att = nullptr;    // [att_groups][nw + 1] t-aligned ranges per row block
     int64_t att_group_rows = 0;   // rows per block of the two-level sort
     int64_t att_groups = 1;       // row blocks: S has att_groups * (n_dfa - 3) segments
     double* S_raw = nullptr;      // [(n_dfa-3)*12] partials of lsqr_aprod2
@@ -170,7 +174,7 @@ struct lsqr_handle {
         int kmax = 0;
         double *U = nullptr, *V = nullptr, *W = nullptr, *Y = nullptr, *VP = nullptr, *Q = nullptr;
         double *gpart = nullptr, *part1 = nullptr, *partc = nullptr, *partdd = nullptr,
-               *partxx = nullptr, *S = nullptr;
+               *partxx = nullptr, *S = nullptr, *X3 = nullptr;
         Scalars* sc = nullptr;
         int32_t* flag = nullptr;
         hipGraphExec_t graph[9] = {};  // by K
@@ -275,11 +279,11 @@ void launch_att_pass(lsqr_handle* h, const Acc* u, Acc* q, Acc* S, const Scalars
     if (us)
         hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, true>), ga, b, 0, st, h->sv.m,
                            (const T*)h->att_sorted, (const int32_t*)h->perm,
-                           (const int32_t*)h->tkey, us, S, h->wb_att, sc);
+                           (const int32_t*)h->tkey, us, S, h->wb_att, h->att_groups, sc);
     else
         hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, false>), ga, b, 0, st, h->sv.m,
                            (const T*)h->att_sorted, (const int32_t*)h->perm,
-                           (const int32_t*)h->tkey, u, S, h->wb_att, sc);
+                           (const int32_t*)h->tkey, u, S, h->wb_att, h->att_groups, sc);
     hipLaunchKernelGGL((k_att_combine<Acc>), dim3(h->nbc), b, 0, st, (const Acc*)S, h->sv.n_dfa,
                        h->att_groups, q + h->sv.att_base, sc);
 }
@@ -422,7 +426,7 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
     LSQR_TRY(dalloc(&h->perm, m));
     LSQR_TRY(dalloc(&h->tkey, m));
     LSQR_TRY(dalloc(&h->invperm, m));
-    LSQR_TRY(dalloc(&h->wb_att, h->nw + 1));
+    LSQR_TRY(dalloc(&h->wb_att, h->att_groups * (h->nw + 1)));
     LSQR_TRY(dalloc(&h->S_raw, att_segments(h) * kAxes * kParAxis));
     T* att_sorted = nullptr;
     LSQR_TRY(dalloc(&att_sorted, (int64_t)kAxes * kParAxis * m));
@@ -447,8 +451,9 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
         hipLaunchKernelGGL(k_invert_perm, dim3(std::min<int64_t>(cdiv(m, kBlock), 65536)),
                            dim3(kBlock), 0, st, (const int32_t*)h->perm, m, h->invperm);
         const int64_t nw = h->nw;
-        hipLaunchKernelGGL((k_wave_bounds<int32_t>), dim3(cdiv(nw + 1, kBlock)), dim3(kBlock), 0, st,
-                           (const int32_t*)h->tkey, m, nw, h->wb_att);
+        hipLaunchKernelGGL(k_group_bounds, dim3(cdiv(h->att_groups * (nw + 1), kBlock)),
+                           dim3(kBlock), 0, st, (const int32_t*)h->tkey, m, h->att_group_rows,
+                           h->att_groups, nw, h->wb_att);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
@@ -621,9 +626,10 @@ lsqr_status batch_alloc(lsqr_handle* h, int kmax)
         if (g) (void)hipGraphExecDestroy(g), g = nullptr;
     dfree(B.U); dfree(B.V); dfree(B.W); dfree(B.Y); dfree(B.VP); dfree(B.Q);
     dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
-    dfree(B.sc); dfree(B.flag); dfree(B.S);
+    dfree(B.sc); dfree(B.flag); dfree(B.S); dfree(B.X3);
     B.kmax = 0;
     LSQR_TRY(dalloc(&B.S, att_segments(h) * kAxes * kParAxis * kmax));
+    LSQR_TRY(dalloc(&B.X3, (int64_t)kAxes * h->sv.n_dfa * kmax));
     LSQR_TRY(dalloc(&B.U, m * kmax));
     LSQR_TRY(dalloc(&B.V, n * kmax));
     LSQR_TRY(dalloc(&B.W, n * kmax));
@@ -631,7 +637,7 @@ lsqr_status batch_alloc(lsqr_handle* h, int kmax)
     LSQR_TRY(dalloc(&B.VP, n * kmax));
     LSQR_TRY(dalloc(&B.Q, n * kmax));
     LSQR_TRY(dalloc(&B.gpart, (int64_t)h->nba * kmax));
-    LSQR_TRY(dalloc(&B.part1, (int64_t)h->nb1 * kmax));
+    LSQR_TRY(dalloc(&B.part1, (int64_t)std::max(h->nb1, h->nba) * kmax));
     LSQR_TRY(dalloc(&B.partc, (int64_t)h->nbc * kmax));
     LSQR_TRY(dalloc(&B.partdd, (int64_t)h->nbc * kmax));
     LSQR_TRY(dalloc(&B.partxx, (int64_t)h->nbc * kmax));
@@ -651,7 +657,7 @@ void batch_free(lsqr_handle* h)
         if (g) (void)hipGraphExecDestroy(g), g = nullptr;
     dfree(B.U); dfree(B.V); dfree(B.W); dfree(B.Y); dfree(B.VP); dfree(B.Q);
     dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
-    dfree(B.sc); dfree(B.flag); dfree(B.S);
+    dfree(B.sc); dfree(B.flag); dfree(B.S); dfree(B.X3);
     B.kmax = 0;
 }
 
@@ -663,16 +669,46 @@ size_t batch_lds(const lsqr_handle* h, int* lds_instr)
     return *lds_instr ? (size_t)bytes : 0;
 }
 
+// Workgroup shape of the batched row passes over the star-aligned ranges: K <= 2
+// fits the 128 registers a lane has in a 1024-thread workgroup; wider tiles
+// use 256-thread workgroups over the same ranges.
+template <int K>
+constexpr int batch_nt() { return K <= 2 ? kBlock2 : kBlock; }
+
+template <int K>
+int batch_grid(const lsqr_handle* h) { return K <= 2 ? h->nb2 : h->nba; }
+
+// The fused pass of a K = 2 tile holds two RHS worth of gathered vector
+// values as well as the row: 512-thread workgroups (256 registers per lane).
+template <int K>
+constexpr int fused_nt() { return K == 1 ? kBlock2 : (K == 2 ? kBlock1 : kBlock); }
+
+template <int K>
+int fused_grid(const lsqr_handle* h) { return (int)(h->nw / (fused_nt<K>() / kWave)); }
+
+template <typename T, int K>
+void batch_att_pass(lsqr_handle* h, hipStream_t st)
+{
+    auto& B = h->batch;
+    const int64_t ns = att_segments(h) * kAxes * kParAxis * K;
+    hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, ns, B.S, 0.0);
+    hipLaunchKernelGGL((batched::k_aprod2_att_sorted<T, double, K>), dim3(h->nba), dim3(kBlock), 0,
+                       st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->perm,
+                       (const int32_t*)h->tkey, (const double*)B.U, B.S, h->wb_att,
+                       h->att_groups, B.sc);
+    hipLaunchKernelGGL((batched::k_att_combine<double, K>), dim3(h->nbc), dim3(kBlock), 0, st,
+                       (const double*)B.S, h->sv.n_dfa, h->att_groups, B.Q + h->sv.att_base * K,
+                       B.sc);
+}
+
 template <typename T, int K>
 void batch_aprod2(lsqr_handle* h, hipStream_t st)
 {
     auto& B = h->batch;
     int li = 0;
     const size_t lds = batch_lds<K>(h, &li);
-    // K <= 2 fits the 128 registers a lane has in a 1024-thread workgroup;
-    // wider tiles keep 256-thread workgroups over the same row ranges.
-    constexpr int NT = K <= 2 ? kBlock2 : kBlock;
-    const int grid = K <= 2 ? h->nb2 : h->nba;
+    constexpr int NT = batch_nt<K>();
+    const int grid = batch_grid<K>(h);
     if (h->att_mode == 0)
         hipLaunchKernelGGL((batched::k_aprod2<T, double, K, true, NT>), dim3(grid), dim3(NT), lds,
                            st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
@@ -681,16 +717,49 @@ void batch_aprod2(lsqr_handle* h, hipStream_t st)
                            st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
     hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
                        (const double*)B.gpart, grid, B.Q + h->sv.glob_base * K, B.sc);
-    if (h->att_mode != 0) {
-        const int64_t ns = att_segments(h) * kAxes * kParAxis * K;
-        hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, ns, B.S, 0.0);
-        hipLaunchKernelGGL((batched::k_aprod2_att_sorted<T, double, K>), dim3(h->nba), dim3(kBlock),
-                           0, st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->perm,
-                           (const int32_t*)h->tkey, (const double*)B.U, B.S, h->wb_att, B.sc);
-        hipLaunchKernelGGL((batched::k_att_combine<double, K>), dim3(h->nbc), dim3(kBlock), 0, st,
-                           (const double*)B.S, h->sv.n_dfa, h->att_groups, B.Q + h->sv.att_base * K,
-                           B.sc);
+    if (h->att_mode != 0) batch_att_pass<T, K>(h, st);
+}
+
+// Fused pass of a K-tile: usable when its instrumental histogram fits in LDS
+// (device atomics for it would cost more than the second pass over A saves).
+template <int K>
+bool batch_fused_lds(const lsqr_handle* h, size_t* lds, int* ldsx)
+{
+    const int64_t bytes = h->sv.n_instr_cols * K * 8;
+    if (!use_fused(h) || bytes > kLdsInstrBudget) return false;
+    const int64_t hist = (bytes + 15) & ~(int64_t)15;
+    *ldsx = hist + bytes <= kLdsInstrBudget ? 1 : 0;
+    *lds = (size_t)(*ldsx ? hist + bytes : hist);
+    return true;
+}
+
+template <typename T, int K>
+void batch_fused(lsqr_handle* h, hipStream_t st, size_t lds, int ldsx)
+{
+    auto& B = h->batch;
+    constexpr int NT = fused_nt<K>();
+    const dim3 g(fused_grid<K>(h)), bm(NT);
+    const double* X3 = nullptr;
+    if (h->att_il) {
+        hipLaunchKernelGGL((batched::k_interleave_att<K>), dim3(h->nbc), dim3(kBlock), 0, st,
+                           (const double*)B.VP, h->sv.att_base, h->sv.n_dfa, B.X3);
+        X3 = B.X3;
     }
+    if (ldsx && X3)
+        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, true, true>), g, bm, lds, st, h->sv,
+                           (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1, B.sc);
+    else if (ldsx)
+        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, true, false>), g, bm, lds, st,
+                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1,
+                           B.sc);
+    else if (X3)
+        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, false, true>), g, bm, lds, st,
+                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1,
+                           B.sc);
+    else
+        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, false, false>), g, bm, lds, st,
+                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1,
+                           B.sc);
 }
 
 template <typename T, int K>
@@ -698,14 +767,28 @@ void batch_iteration(lsqr_handle* h, hipStream_t st, hipEvent_t* ev)
 {
     auto& B = h->batch;
     const int64_t n = h->sv.n;
+    size_t lds = 0;
+    int ldsx = 0;
     if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL((batched::k_aprod1<T, double, K>), dim3(h->nb1), dim3(kBlock), 0, st, h->sv,
-                       (const double*)B.VP, B.U, B.sc, B.part1);
-    if (ev) (void)hipEventRecord(ev[1], st);
-    hipLaunchKernelGGL((batched::k_scalar_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1, h->nb1,
-                       B.sc);
-    if (ev) (void)hipEventRecord(ev[2], st);
-    batch_aprod2<T, K>(h, st);
+    if (batch_fused_lds<K>(h, &lds, &ldsx)) {
+        batch_fused<T, K>(h, st, lds, ldsx);
+        if (ev) (void)hipEventRecord(ev[1], st);
+        hipLaunchKernelGGL((batched::k_scalar_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1,
+                           fused_grid<K>(h), B.sc);
+        if (ev) (void)hipEventRecord(ev[2], st);
+        hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
+                           (const double*)B.gpart, fused_grid<K>(h), B.Q + h->sv.glob_base * K,
+                           B.sc);
+        batch_att_pass<T, K>(h, st);
+    } else {
+        hipLaunchKernelGGL((batched::k_aprod1<T, double, K>), dim3(h->nb1), dim3(kBlock), 0, st,
+                           h->sv, (const double*)B.VP, B.U, B.sc, B.part1);
+        if (ev) (void)hipEventRecord(ev[1], st);
+        hipLaunchKernelGGL((batched::k_scalar_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1,
+                           h->nb1, B.sc);
+        if (ev) (void)hipEventRecord(ev[2], st);
+        batch_aprod2<T, K>(h, st);
+    }
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL((batched::k_col_a<double, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, B.Q,
                        B.V, B.sc, B.partc);
@@ -1018,7 +1101,7 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
         h->nba = (int)(nw / kWavesPerBlock);
     }
     h->nbc = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)h->num_cu * 4, cdiv(n, kBlock)));
-    h->att_group_rows = std::max<int64_t>(kWave, kAttGroupBytes / 8);
+    h->att_group_rows = kAttGroupRows;
     h->att_groups = cdiv(m, h->att_group_rows);
 
     lsqr_status st;

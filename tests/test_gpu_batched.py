@@ -34,17 +34,19 @@ def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("att_mode", [1, 0])
+# (attitude mode, fused pass): the fused pass serves attitude mode 1
+@pytest.mark.parametrize("att_mode,fused", [(1, 1), (1, 0), (0, 1)])
 @pytest.mark.parametrize("ktile", [1, 2, 4, 8])
-def test_batched_fixed_iterations(torch_cuda, c0, ktile, att_mode):
+def test_batched_fixed_iterations(torch_cuda, c0, ktile, att_mode, fused):
     torch = torch_cuda
     from paper_2308_00778_amd import LsqrSystem
 
     S, o, B = c0
     itn = 40
-    say(f"batched parity: c0 k=5 ktile={ktile} att_mode={att_mode} itn={itn}")
+    say(f"batched parity: c0 k=5 ktile={ktile} att_mode={att_mode} fused={fused} itn={itn}")
     g = LsqrSystem.from_host(S, "cuda:0")
     g.set_option("att_mode", att_mode)
+    g.set_option("fused", fused)
     g.set_option("att_group_rows", 7000)
     g.set_option("tests", 0)
     g.set_option("ktile", ktile)
@@ -109,3 +111,30 @@ def test_batched_autotune_picks_a_tile(torch_cuda, c0):
     assert all(t["ms_per_rhs_iter"][k] > 0 for k in (1, 2, 4))
     x_ref, _ = o.lsqr(B[:, 2], 30, atol=0.0, btol=0.0, conlim=0.0, tests=False)
     assert rel_inf(Xh[:, 2], x_ref) <= 1e-10
+
+
+# 9000 instrumental columns: the fused pass keeps the K = 2 histogram in LDS
+# (144 KB) and gathers the instrumental slice from memory; K = 4 does not fit
+# and runs the separate passes.
+@pytest.mark.parametrize("ktile", [2, 4])
+def test_batched_wide_instrumental(torch_cuda, ktile):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LsqrSystem
+
+    spec = synth.tiny(seed=24, n_stars=200, obs=(20, 60), n_dfa=300, n_instr_cols=9000)
+    S = synth.make_system(spec)
+    o = oracle.OracleSystem.from_synth(S)
+    xt = synth.x_true(spec)
+    B = np.stack([o.aprod1(xt, synth.noise(spec, S.m, rhs=j)) for j in range(3)], axis=1)
+    itn = 30
+    say(f"batched parity: wide_instr k=3 ktile={ktile} itn={itn}")
+    g = LsqrSystem.from_host(S, "cuda:0")
+    g.set_option("tests", 0)
+    g.set_option("ktile", ktile)
+    X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(B)).cuda(), itn, 0.0, 0.0)
+    Xh = X.cpu().numpy()
+    g.close()
+    for j in range(B.shape[1]):
+        x_ref, _ = o.lsqr(B[:, j], itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+        assert infos[j].itn == itn
+        assert rel_inf(Xh[:, j], x_ref) <= 1e-10, j
