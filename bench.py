@@ -8,7 +8,7 @@ Givens rotation, x/w update, stopping tests); the timed region is one
 lsqr_solve of exactly `steps` iterations (stopping tests off) with HIP events
 around every launch of the two row passes on the stream they run on: the
 fused pass (aprod1 with the astrometric, instrumental and global part of
-aprod2) and the row-reordered attitude pass. The same iterations with
+aprod2) and the bucket-order attitude pass. The same iterations with
 separate aprod1 / aprod2 launches are timed for comparison.
 
 Prints one JSON line.
@@ -30,12 +30,13 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 #   aprod1: 24 values + indices + u read and written
 #   aprod2: 24 values + indices + u read
 #   fused pass: as aprod1 (A is read once for both products)
-#   attitude pass: 12 reordered attitude values + int32 t and row + u gathered
+#   attitude pass: 12 attitude values in bucket order + int32 local start + u
+#   (read in bucket order)
 BYTES_PER_ROW = {"aprod1": 24 * 8 + 40 + 16, "aprod2": 24 * 8 + 40 + 8,
-                 "fused": 24 * 8 + 40 + 16, "attitude": 12 * 8 + 8 + 8}
+                 "fused": 24 * 8 + 40 + 16, "attitude": 12 * 8 + 4 + 8}
 # FP32 values with FP32 work vectors (the inner solve of the refinement)
 BYTES_PER_ROW_F32 = {"aprod1": 24 * 4 + 40 + 8, "aprod2": 24 * 4 + 40 + 4,
-                     "fused": 24 * 4 + 40 + 8, "attitude": 12 * 4 + 8 + 4}
+                     "fused": 24 * 4 + 40 + 8, "attitude": 12 * 4 + 4 + 4}
 
 
 def pass_names(fused: bool):
@@ -143,8 +144,8 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
     """Row-pass times of the iteration variants on one system: fused pass vs
     separate aprod1 / aprod2, attitude values interleaved or gathered from the
     three axis windows, and for aprod2 the device-atomics attitude scatter vs
-    the row-reordered pass (u gathered or written in sorted order by aprod1),
-    each astrometric reduction."""
+    the bucket-order pass, each astrometric reduction; then the attitude
+    bucket count."""
     import torch
 
     import synth
@@ -159,7 +160,7 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
     g.aprod1(synth.device_x_true(spec, dev), b)
     out = {}
     for fused, att, scan, il in ((1, 1, 0, 1), (1, 1, 0, 0), (0, 1, 0, 1), (0, 1, 0, 0),
-                                 (0, 2, 0, 1), (0, 1, 1, 1), (0, 0, 0, 1)):
+                                 (0, 1, 1, 1), (0, 0, 0, 1)):
         g.set_option("fused", fused)
         g.set_option("att_mode", att)
         g.set_option("astro_scan", scan)
@@ -169,25 +170,24 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
         g.solve(b, 2, atol=0.0, btol=0.0)
         x, info = g.solve(b, itn, atol=0.0, btol=0.0)
         ms = pass_times(g.kernel_times(), bool(fused and att == 1))
-        key = ("fused_" if fused else "") + \
-            ("atomics", "reordered_gather", "reordered_u_written_sorted")[att] + \
+        key = ("fused_" if fused else "") + ("atomics", "bucket_pass")[att] + \
             ("_scan" if scan else "_flush") + ("" if il else "_plain_att_gathers")
         out[key] = {**{f"{k}_ms": v for k, v in ms.items()},
                     "iteration_rows_ms": sum(ms.values()), "rnorm": info.rnorm}
         log(f"{key}: " + ", ".join(f"{k} {v:.3f} ms" for k, v in ms.items()))
     g.close()
-    # row-block size of the attitude order (fused default path; a fresh handle
-    # per size, the option is fixed once the reordering exists)
-    for rows in (1 << 20, 1 << 22, 1 << 24, 1 << 26):
+    # attitude bucket count (fused default path; a fresh handle per count, the
+    # option is fixed once the bucket order exists; 0 = the fewest that fit)
+    for nbk in (32, 64):
         g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
                        n_instr_cols=spec.n_instr_cols)
-        g.set_option("att_group_rows", rows)
+        g.set_option("att_buckets", nbk)
         g.set_option("tests", 0)
         g.set_option("profile", 1)
         g.solve(b, 2, atol=0.0, btol=0.0)
         x, info = g.solve(b, itn, atol=0.0, btol=0.0)
         ms = pass_times(g.kernel_times(), True)
-        key = f"fused_att_group_rows_{rows}"
+        key = f"fused_att_buckets_{nbk}"
         out[key] = {**{f"{k}_ms": v for k, v in ms.items()},
                     "iteration_rows_ms": sum(ms.values()), "rnorm": info.rnorm}
         log(f"{key}: " + ", ".join(f"{k} {v:.3f} ms" for k, v in ms.items()))

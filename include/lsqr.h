@@ -112,21 +112,23 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         read back with lsqr_kernel_times
  *   LSQR_OPT_OUTER_TOL    refinement: stop when ||d||_inf <= tol ||x||_inf
  *                         (default 1e-10)
- *   LSQR_OPT_ATT_MODE     attitude part of aprod2: 1 (default) a second pass over
- *                         the rows in (row block, attitude start) order (segmented
- *                         sums, no atomics; costs a reordered copy of the 12
- *                         attitude coefficients and three int32 per row, built
- *                         on first use, needs n_rows < 2^31), u gathered through
- *                         the permutation; 2 the same pass, with aprod1 also
- *                         writing u in the reordered order; 0 scatter-add with
- *                         device atomics (no extra memory, about 8x slower)
+ *   LSQR_OPT_ATT_MODE     attitude part of aprod2: 1 (default) a pass over the
+ *                         rows stably sorted by the bucket of their attitude start
+ *                         (W starts per bucket), each bucket's 3 x (W + 3)
+ *                         columns accumulated in an LDS histogram (no device
+ *                         atomics); costs a copy of the 12 attitude coefficients
+ *                         in that order and three int32 per row, built on first
+ *                         use, needs n_rows < 2^31; the solver keeps its row
+ *                         vector u in bucket order; 0 scatter-add with device
+ *                         atomics (no extra memory, about 10x slower)
  *   LSQR_OPT_ASTRO_SCAN   astrometric part of aprod2: 0 (default) running
  *                         per-lane partials reduced only where a star ends;
  *                         1 a segmented scan over every 64-row chunk
- *   LSQR_OPT_ATT_GROUP_ROWS  rows per block of the (row block, attitude start)
- *                         order (default 2^26, >= 64); the attitude pass sweeps
- *                         the blocks one after another; settable only before the
- *                         first solve or aprod2
+ *   LSQR_OPT_ATT_BUCKETS  number of attitude buckets: 0 (default) the fewest
+ *                         whose FP64 histogram fits in LDS (16 for 10^5 attitude
+ *                         columns per axis), n > 0 that many (raised if they do
+ *                         not fit); settable only before the first solve or
+ *                         aprod2
  *   LSQR_OPT_ATT_INTERLEAVE  aprod1 reads the 12 attitude values of a row from
  *                         a copy of the attitude section interleaved by axis
  *                         (x3[3 c + axis], rebuilt before every aprod1; the
@@ -151,7 +153,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_ATT_MODE 7
 #define LSQR_OPT_ASTRO_SCAN 8
 #define LSQR_OPT_KTILE 9
-#define LSQR_OPT_ATT_GROUP_ROWS 10
+#define LSQR_OPT_ATT_BUCKETS 10
 #define LSQR_OPT_ATT_INTERLEAVE 11
 #define LSQR_OPT_FUSED 12
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);

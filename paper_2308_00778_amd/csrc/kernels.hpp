@@ -202,17 +202,16 @@ enum Aprod1Mode : int {
 // RESID modes). NT threads per block. LDSX: the instrumental slice of x
 // (n_instr_cols values) is first copied into LDS, so that the six random
 // instrumental gathers per row hit LDS instead of L2.
-// ys (optional): y is also written in the attitude-sorted row order,
-// ys[invperm[i]] = y[i], so that the reordered attitude pass of aprod2 reads
-// it sequentially instead of gathering it.
+// inv (optional, LSQR and RESID modes): placement of the row vector, the value
+// of row i lives at y[inv[i]] (the attitude-bucket order of the solver's work
+// vector); nullptr: y[i].
 template <typename T, typename Acc, typename VX, typename VY, int MODE, int NT = kBlock,
           bool LDSX = false, bool ATTI = false>
 __global__ __launch_bounds__(NT) void k_aprod1(SysView s, const VX* __restrict__ x,
                                                 VY* __restrict__ y, const double* __restrict__ b,
                                                 const Scalars* __restrict__ sc,
                                                 double* __restrict__ part,
-                                                const int32_t* __restrict__ invperm = nullptr,
-                                                VY* __restrict__ ys = nullptr,
+                                                const int32_t* __restrict__ inv = nullptr,
                                                 const VX* __restrict__ x3 = nullptr)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -238,16 +237,16 @@ __global__ __launch_bounds__(NT) void k_aprod1(SysView s, const VX* __restrict__
             y[i0] = (VY)((Acc)y[i0] + d0);
             if (has1) y[i1] = (VY)((Acc)y[i1] + d1);
         } else {
-            const VY n0 = MODE == A1_LSQR ? (VY)(d0 - coef * (Acc)y[i0]) : (VY)((Acc)b[i0] - d0);
-            y[i0] = n0;
+            const int64_t p0 = inv ? (int64_t)ldnt(&inv[i0]) : i0;
+            const VY n0 = MODE == A1_LSQR ? (VY)(d0 - coef * (Acc)y[p0]) : (VY)((Acc)b[i0] - d0);
+            y[p0] = n0;
             ssq += (double)n0 * (double)n0;
-            if (ys) ys[ldnt(&invperm[i0])] = n0;
             if (has1) {
+                const int64_t p1 = inv ? (int64_t)ldnt(&inv[i1]) : i1;
                 const VY n1 =
-                    MODE == A1_LSQR ? (VY)(d1 - coef * (Acc)y[i1]) : (VY)((Acc)b[i1] - d1);
-                y[i1] = n1;
+                    MODE == A1_LSQR ? (VY)(d1 - coef * (Acc)y[p1]) : (VY)((Acc)b[i1] - d1);
+                y[p1] = n1;
                 ssq += (double)n1 * (double)n1;
-                if (ys) ys[ldnt(&invperm[i1])] = n1;
             }
         }
     }
@@ -395,20 +394,22 @@ __device__ __forceinline__ void seg_flush(int64_t key, const Acc (&v)[NV], int l
 // accumulated in LDS when lds_instr != 0 (n_instr_cols * sizeof(Acc) bytes of
 // dynamic shared memory), else by device atomics. gpart[blockIdx.x] gets the
 // workgroup's global-column partial; k_glob_sum adds them up.
-// ATT = false leaves the attitude columns to the row-reordered pass
-// (k_aprod2_att_sorted) and skips loading them. SCAN selects the astrometric
+// ATT = false leaves the attitude columns to the bucket-order pass
+// (k_att_hist) and skips loading them. SCAN selects the astrometric
 // reduction: a segmented scan every chunk (true) or the accumulate-and-flush
 // segments of seg_chunk (false).
+// inv (optional): the value of row i is u[inv[i]].
 template <typename T, typename Acc, typename VU, bool SQUARE, bool ATT = true, bool SCAN = true,
           int NT = kBlock>
 __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__ u,
                                                     Acc* __restrict__ q,
                                                     const int64_t* __restrict__ wb,
                                                     Acc* __restrict__ gpart, int lds_instr,
-                                                    const Scalars* __restrict__ sc)
+                                                    const Scalars* __restrict__ sc,
+                                                    const int32_t* __restrict__ inv = nullptr)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    Acc* lds = reinterpret_cast<Acc*>(smem_raw);
+    double* lds = reinterpret_cast<double*>(smem_raw);  // FP64 histogram (see k_att_hist)
     __shared__ Acc gred[NT / kWave];
     if (sc != nullptr && (sc->done || sc->beta_zero)) return;
 
@@ -416,7 +417,7 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
     const int64_t m = s.m;
     const int64_t ninst = s.n_instr_cols;
     if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst; j += NT) lds[j] = (Acc)0;
+        for (int64_t j = threadIdx.x; j < ninst; j += NT) lds[j] = 0.0;
         __syncthreads();
     }
 
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
         Acc ui = (Acc)0;
-        if (!SQUARE) ui = ok ? (Acc)u[ic] : (Acc)0;
+        if (!SQUARE) ui = ok ? (Acc)u[inv ? (int64_t)ldnt(&inv[ic]) : ic] : (Acc)0;
 
         Acc contrib[kPar];
 #pragma unroll
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
             // instrumental
 #pragma unroll
             for (int j = 0; j < kInstr; ++j) {
-                if (lds_instr) atomicAdd(&lds[ix[j]], contrib[kOffInstr + j]);
+                if (lds_instr) atomicAdd(&lds[ix[j]], (double)contrib[kOffInstr + j]);
                 else atomicAdd(&qins[ix[j]], contrib[kOffInstr + j]);
             }
         }
@@ -531,8 +532,8 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
     // instrumental flush: one device atomic per column per workgroup
     if (lds_instr) {
         for (int64_t j = threadIdx.x; j < ninst; j += NT) {
-            const Acc v = lds[j];
-            if (v != (Acc)0) atomicAdd(&qins[j], v);
+            const double v = lds[j];
+            if (v != 0.0) atomicAdd(&qins[j], (Acc)v);
         }
     }
 }
@@ -548,17 +549,20 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
 // so A is read once per iteration for these sections; the attitude columns
 // are left to the row-reordered pass, which reads u~_{i+1}.
 //   x: vp = p .* v (Acc), x3: its interleaved attitude section (ATTI),
-//   u: u~ [m], overwritten, part[blockIdx.x]: FP64 sum of squares of the
+//   u: u~ [m], overwritten (row i at u[inv[i]], or u[i] without inv),
+//   part[blockIdx.x]: FP64 sum of squares of the
 //   stored u~, q: A^T u~ accumulator (astro, instr, glob sections),
 //   gpart[blockIdx.x]: global-column partial, wb: star-aligned wave ranges.
-// Dynamic LDS: the instrumental histogram (lds_instr, n_instr_cols Acc) and,
-// after it, the instrumental slice of x (LDSX, n_instr_cols Acc).
+// Dynamic LDS: the instrumental histogram (lds_instr, n_instr_cols FP64, see
+// k_att_hist) and, after it, the instrumental slice of x (LDSX,
+// n_instr_cols Acc).
 template <typename T, typename Acc, int NT, bool LDSX, bool ATTI>
 __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ x,
                                                const Acc* __restrict__ x3, Acc* __restrict__ u,
                                                Acc* __restrict__ q, const int64_t* __restrict__ wb,
                                                Acc* __restrict__ gpart, double* __restrict__ part,
-                                               int lds_instr, const Scalars* __restrict__ sc)
+                                               int lds_instr, const Scalars* __restrict__ sc,
+                                               const int32_t* __restrict__ inv)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ Acc gred[NT / kWave];
@@ -568,12 +572,12 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
     const T* __restrict__ val = static_cast<const T*>(s.val);
     const int64_t m = s.m;
     const int64_t ninst = s.n_instr_cols;
-    Acc* hist = reinterpret_cast<Acc*>(smem_raw);
+    double* hist = reinterpret_cast<double*>(smem_raw);
     const Acc* xi = x + s.instr_base;
     if (lds_instr)
-        for (int64_t j = threadIdx.x; j < ninst; j += NT) hist[j] = (Acc)0;
+        for (int64_t j = threadIdx.x; j < ninst; j += NT) hist[j] = 0.0;
     if (LDSX) {
-        const int64_t off = lds_instr ? (ninst * (int64_t)sizeof(Acc) + 15) & ~(int64_t)15 : 0;
+        const int64_t off = lds_instr ? (ninst * 8 + 15) & ~(int64_t)15 : 0;
         Acc* xl = reinterpret_cast<Acc*>(smem_raw + off);
         for (int64_t j = threadIdx.x; j < ninst; j += NT) xl[j] = xi[j];
         xi = xl;
@@ -610,7 +614,8 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         int32_t ix[kInstr];
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
-        const Acc uo = u[ic];
+        const int64_t pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
+        const Acc uo = u[pu];
 
         // Eq. (2): the row's dot product with vp, in section order
         Acc d = (Acc)0;
@@ -630,7 +635,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         for (int j = 0; j < kInstr; ++j) d += (Acc)a[kOffInstr + j] * xi[ix[j]];
         d += (Acc)a[kOffGlob] * xg;
         d -= coef * uo;
-        if (ok) u[ic] = d;
+        if (ok) u[pu] = d;
         if (!ok) d = (Acc)0;
         ssq += (double)d * (double)d;
 
@@ -639,7 +644,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
 #pragma unroll
             for (int j = 0; j < kInstr; ++j) {
                 const Acc c = (Acc)a[kOffInstr + j] * d;
-                if (lds_instr) atomicAdd(&hist[ix[j]], c);
+                if (lds_instr) atomicAdd(&hist[ix[j]], (double)c);
                 else atomicAdd(&qins[ix[j]], c);
             }
         }
@@ -674,8 +679,8 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
     }
     if (lds_instr) {
         for (int64_t j = threadIdx.x; j < ninst; j += NT) {
-            const Acc v = hist[j];
-            if (v != (Acc)0) atomicAdd(&qins[j], v);
+            const double v = hist[j];
+            if (v != 0.0) atomicAdd(&qins[j], (Acc)v);
         }
     }
 }
@@ -774,18 +779,20 @@ __global__ __launch_bounds__(kBlock) void k_col_init(int64_t n, const double* __
     }
 }
 
-// u~ = b (stored as VU) ; FP64 sum of squares of the stored values.
+// u~ = b (stored as VU, row i at u[inv[i]] or u[i]) ; FP64 sum of squares of
+// the stored values.
 template <typename VU>
 __global__ __launch_bounds__(kBlock) void k_copy_ssq(int64_t m, const double* __restrict__ b,
                                                       VU* __restrict__ u,
-                                                      double* __restrict__ part)
+                                                      double* __restrict__ part,
+                                                      const int32_t* __restrict__ inv)
 {
     __shared__ double red[kWavesPerBlock];
     double ssq = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * kBlock) {
         const VU v = (VU)b[i];
-        u[i] = v;
+        u[inv ? (int64_t)inv[i] : i] = v;
         ssq += (double)v * (double)v;
     }
     const double r = block_sum(ssq, red);
@@ -1024,28 +1031,6 @@ __global__ __launch_bounds__(kBlock) void k_wave_bounds(const K* __restrict__ st
     wb[g] = r;
 }
 
-// Per-block t-aligned ranges of the sorted rows: block g occupies sorted
-// positions [g R, min((g+1) R, m)); its range w starts at the first key change
-// at or after g R + w len / nw (wb[g (nw + 1) + w], w = 0..nw).
-__global__ __launch_bounds__(kBlock) void k_group_bounds(const int32_t* __restrict__ key,
-                                                          int64_t m, int64_t group_rows,
-                                                          int64_t ngroups, int64_t nw,
-                                                          int64_t* __restrict__ wb)
-{
-    const int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= ngroups * (nw + 1)) return;
-    const int64_t g = idx / (nw + 1), w = idx - g * (nw + 1);
-    const int64_t b0 = g * group_rows;
-    const int64_t b1 = b0 + group_rows < m ? b0 + group_rows : m;
-    if (w == nw) {
-        wb[idx] = b1;
-        return;
-    }
-    int64_t r = b0 + w * (b1 - b0) / nw;  // nw <= 2^20, block < 2^31: no overflow
-    while (r > b0 && r < b1 && key[r] == key[r - 1]) ++r;
-    wb[idx] = r;
-}
-
 // p_j = 1/sqrt(ssq_j), 1 for an empty column (or for every column when not
 // preconditioning); resets ssq.
 __global__ __launch_bounds__(kBlock) void k_make_p(int64_t n, double* __restrict__ ssq,
@@ -1059,22 +1044,23 @@ __global__ __launch_bounds__(kBlock) void k_make_p(int64_t n, double* __restrict
     }
 }
 
-// ----------------------------------------------- row-reordered attitude
-// Rows sorted by their attitude start t (a stable radix sort at set-up) turn
-// the attitude scatter into a segmented reduction: every row with the same t
-// contributes to the same 3 x 4 columns.
-// Sort key of row i: (row block, attitude start). Rows are grouped into
-// contiguous blocks of group_rows rows and sorted by t inside each block, so
-// that the u values one stretch of the sorted order touches lie in one block
-// (a slice small enough to stay in the GPU's last-level cache).
-__global__ __launch_bounds__(kBlock) void k_att_keys(const int64_t* __restrict__ att, int64_t m,
-                                                      int64_t group_rows, int64_t nt,
-                                                      int32_t* __restrict__ keys,
-                                                      int32_t* __restrict__ rows)
+// ------------------------------------------------ attitude in bucket order
+// The attitude columns of a row are 3 windows of 4 consecutive columns at the
+// row's start t. Rows stably sorted by the bucket of t (t / W, W starts per
+// bucket) put every bucket's rows together while keeping star order inside a
+// bucket; the columns one bucket touches are 3 x (W + 3), few enough for an
+// LDS histogram, so Eq. (3) for the attitude section becomes a sequential
+// sweep with LDS atomics and no device atomics. The solver keeps its row
+// vector u~ in this order (row i at u[inv[i]]): the attitude sweep reads it
+// sequentially, and the star-order passes reach it through inv, whose targets
+// form one run per bucket for any stretch of consecutive rows.
+__global__ __launch_bounds__(kBlock) void k_bucket_keys(const int64_t* __restrict__ att, int64_t m,
+                                                         int64_t width, int32_t* __restrict__ keys,
+                                                         int32_t* __restrict__ rows)
 {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * kBlock) {
-        keys[i] = (int32_t)((i / group_rows) * nt + att[i]);
+        keys[i] = (int32_t)(att[i] / width);
         rows[i] = (int32_t)i;
     }
 }
@@ -1087,7 +1073,21 @@ __global__ __launch_bounds__(kBlock) void k_invert_perm(const int32_t* __restric
         invperm[perm[k]] = (int32_t)k;
 }
 
-// us[k] = u[perm[k]]
+// bstart[b] = first sorted position of bucket b (b = 0..nb; empty buckets
+// included), from the sorted keys.
+__global__ __launch_bounds__(kBlock) void k_bucket_starts(const int32_t* __restrict__ skeys,
+                                                           int64_t m, int64_t nb,
+                                                           int64_t* __restrict__ bstart)
+{
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k <= m;
+         k += (int64_t)gridDim.x * kBlock) {
+        const int64_t prev = k > 0 ? (int64_t)skeys[k - 1] : -1;
+        const int64_t cur = k < m ? (int64_t)skeys[k] : nb;
+        for (int64_t b = prev + 1; b <= cur; ++b) bstart[b] = k;
+    }
+}
+
+// us[k] = u[perm[k]]: a vector in row order placed in bucket order
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_gather_perm(const V* __restrict__ u,
                                                          const int32_t* __restrict__ perm,
@@ -1098,11 +1098,14 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const V* __restrict__ u,
         us[k] = u[perm[k]];
 }
 
-// att_sorted[c][k] = values[kOffAtt + c][perm[k]], c < 12
+// att_sorted[c][k] = values[kOffAtt + c][perm[k]], c < 12 ;
+// tloc[k] = t of row perm[k] minus its bucket's first start.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val, int64_t m,
+__global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val,
+                                                        const int64_t* __restrict__ att, int64_t m,
                                                         const int32_t* __restrict__ perm,
-                                                        T* __restrict__ att_sorted)
+                                                        int64_t width, T* __restrict__ att_sorted,
+                                                        int32_t* __restrict__ tloc)
 {
     constexpr int kAtt = kAxes * kParAxis;
     for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m;
@@ -1110,74 +1113,81 @@ __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val
         const int64_t i = perm[k];
 #pragma unroll
         for (int c = 0; c < kAtt; ++c) att_sorted[c * m + k] = val[(kOffAtt + c) * m + i];
+        const int64_t t = att[i];
+        tloc[k] = (int32_t)(t - (t / width) * width);
     }
 }
 
-// S[key][12] = sum over rows with sort key (row block, attitude start) of
-// a_att * u: each key is one segment of the sorted rows, owned by one wave
-// (plain stores). Row block g occupies sorted positions [g R, (g+1) R); every
-// wave takes its t-aligned slice of block 0, then of block 1, and so on
-// (wb[g (nw + 1) + wave]), so that at any time the waves gather u from one
-// block's slice of the row vector, which stays in the last-level cache.
-// SEQ: u is already in sorted order (written by aprod1), else gathered as
-// u[perm[k]].
-template <typename T, typename Acc, typename VU, bool SEQ = false>
-__global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
-    int64_t m, const T* __restrict__ att_sorted, const int32_t* __restrict__ perm,
-    const int32_t* __restrict__ tkey, const VU* __restrict__ u, Acc* __restrict__ S,
-    const int64_t* __restrict__ wb, int64_t ngroups, const Scalars* __restrict__ sc)
+// Attitude part of Eq. (3) over the rows in bucket order. Workgroup w covers
+// the g-th of G equal slices of bucket b = w / G (g = w % G): an LDS
+// histogram hist[axis][W + 3] gets a * u for the 12 coefficients of each of
+// its rows, then is stored as S2[w][r][axis][W + 3]; k_att_reduce adds the
+// slices. The histogram and S2 are FP64 whatever Acc is: gfx950's LDS FP64
+// atomic add runs at 7.6x the rate of the FP32 one (measured, random
+// addresses over 150 KB: 1550 vs 204 G/s), and the sums are more accurate.
+// U is in bucket order ([m][K], K right-hand sides swept one after another).
+// Frozen RHS (done or beta_zero) are skipped.
+template <typename T, typename Acc, int K, int NT>
+__global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict__ att_sorted,
+                                                  const int32_t* __restrict__ tloc,
+                                                  const int64_t* __restrict__ bstart,
+                                                  int64_t width, int G, const Acc* __restrict__ U,
+                                                  double* __restrict__ S2,
+                                                  const Scalars* __restrict__ sc)
 {
-    constexpr int kAtt = kAxes * kParAxis;
-    if (sc != nullptr && (sc->done || sc->beta_zero)) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    auto emit = [S](int64_t t, const Acc (&tot)[kAtt]) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* hist = reinterpret_cast<double*>(smem_raw);
+    const int64_t span = width + kParAxis - 1;
+    const int64_t bk = blockIdx.x / G, g = blockIdx.x - bk * G;
+    const int64_t b0 = bstart[bk], len = bstart[bk + 1] - b0;
+    const int64_t r0 = b0 + g * len / G, r1 = b0 + (g + 1) * len / G;
+    for (int r = 0; r < K; ++r) {
+        if (sc != nullptr && (sc[r].done || sc[r].beta_zero)) continue;  // uniform
+        for (int64_t e = threadIdx.x; e < kAxes * span; e += NT) hist[e] = 0.0;
+        __syncthreads();
+        for (int64_t k = r0 + threadIdx.x; k < r1; k += NT) {
+            const int64_t tl = ldnt(&tloc[k]);
+            const double uk = (double)U[k * K + r];
+            T a[kAxes * kParAxis];  // all loads issued before the first atomic
 #pragma unroll
-        for (int j = 0; j < kAtt; ++j) S[t * kAtt + j] = tot[j];
-    };
-    for (int64_t g = 0; g < ngroups; ++g) {
-        const int64_t rb = wb[g * (nw + 1) + wave], re = wb[g * (nw + 1) + wave + 1];
-        SegAcc<Acc, kAtt> seg;
-        for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
-            const int64_t k = r0 + lane;
-            const bool ok = k >= rb && k < re;
-            const int64_t kc = k < rb ? rb : (k < re ? k : re - 1);
-            const int64_t t = k < re ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
-            Acc ui = (Acc)0;
-            if (SEQ) ui = ok ? (Acc)ldnt(&u[kc]) : (Acc)0;
-            else ui = ok ? (Acc)u[ldnt(&perm[kc])] : (Acc)0;
-            Acc v[kAtt];
+            for (int c = 0; c < kAxes * kParAxis; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
 #pragma unroll
-            for (int c = 0; c < kAtt; ++c) v[c] = (Acc)ldnt(&att_sorted[c * m + kc]) * ui;
-            seg_chunk(seg, t, v, lane, emit);
+            for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+                for (int qq = 0; qq < kParAxis; ++qq)
+                    atomicAdd(&hist[ax * span + tl + qq], (double)a[ax * kParAxis + qq] * uk);
         }
-        seg_finish(seg, lane, emit);
+        __syncthreads();
+        double* out = S2 + ((int64_t)blockIdx.x * K + r) * kAxes * span;
+        for (int64_t e = threadIdx.x; e < kAxes * span; e += NT) out[e] = hist[e];
+        __syncthreads();
     }
 }
 
-// q[att_base + a n_dfa + c] += sum over row blocks g and parameters q of
-// S[g][c - q][a][q] (valid starts only). S holds ngroups * nt segments.
-template <typename Acc>
-__global__ __launch_bounds__(kBlock) void k_att_combine(const Acc* __restrict__ S, int64_t n_dfa,
-                                                         int64_t ngroups, Acc* __restrict__ qatt,
-                                                         const Scalars* __restrict__ sc)
+// q_att[(axis n_dfa + c) K + r] += sum of the slices of the (at most two)
+// buckets whose window holds column c.
+template <typename Acc, int K>
+__global__ __launch_bounds__(kBlock) void k_att_reduce(const double* __restrict__ S2, int64_t nb,
+                                                        int G, int64_t width, int64_t n_dfa,
+                                                        Acc* __restrict__ qatt,
+                                                        const Scalars* __restrict__ sc)
 {
-    constexpr int kAtt = kAxes * kParAxis;
-    if (sc != nullptr && (sc->done || sc->beta_zero)) return;
-    const int64_t nt = n_dfa - kParAxis + 1;  // valid starts 0 .. nt-1
-    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < kAxes * n_dfa;
-         j += (int64_t)gridDim.x * kBlock) {
-        const int64_t ax = j / n_dfa, c = j - ax * n_dfa;
-        Acc sum = (Acc)0;
-        for (int64_t g = 0; g < ngroups; ++g) {
-#pragma unroll
-            for (int qq = 0; qq < kParAxis; ++qq) {
-                const int64_t t = c - qq;
-                if (t >= 0 && t < nt) sum += S[(g * nt + t) * kAtt + ax * kParAxis + qq];
-            }
+    const int64_t span = width + kParAxis - 1;
+    const int64_t total = (int64_t)kAxes * n_dfa * K;
+    for (int64_t idx = (int64_t)blockIdx.x * kBlock + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * kBlock) {
+        const int64_t col = idx / K;
+        const int r = (int)(idx - col * K);
+        if (sc != nullptr && (sc[r].done || sc[r].beta_zero)) continue;
+        const int64_t ax = col / n_dfa, c = col - ax * n_dfa;
+        const int64_t bhi = c / width < nb - 1 ? c / width : nb - 1;
+        double sum = 0.0;
+        for (int64_t bk = bhi; bk >= 0 && c - bk * width < span; --bk) {
+            const int64_t off = c - bk * width;
+            for (int g = 0; g < G; ++g)
+                sum += S2[(((bk * G + g) * K + r) * kAxes + ax) * span + off];
         }
-        qatt[j] += sum;
+        qatt[idx] = (Acc)((double)qatt[idx] + sum);
     }
 }
 
@@ -1229,11 +1239,13 @@ __device__ __forceinline__ void block_sums_k(double (&v)[K], double* __restrict_
     }
 }
 
-// U[i][r] = B[i][r] (B row stride ldb), FP64 sums of squares per RHS.
+// U[p(i)][r] = B[i][r] (B row stride ldb; p(i) = inv[i], or i without inv),
+// FP64 sums of squares per RHS.
 template <typename VU, int K>
 __global__ __launch_bounds__(kBlock) void k_copy_ssq(int64_t m, const double* __restrict__ B,
                                                       int64_t ldb, VU* __restrict__ U,
-                                                      double* __restrict__ part)
+                                                      double* __restrict__ part,
+                                                      const int32_t* __restrict__ inv)
 {
     __shared__ double red[K * kWavesPerBlock];
     double ssq[K];
@@ -1241,22 +1253,25 @@ __global__ __launch_bounds__(kBlock) void k_copy_ssq(int64_t m, const double* __
     for (int r = 0; r < K; ++r) ssq[r] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * kBlock) {
+        const int64_t pi = inv ? (int64_t)inv[i] : i;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             const VU v = (VU)B[i * ldb + r];
-            U[i * K + r] = v;
+            U[pi * K + r] = v;
             ssq[r] += (double)v * (double)v;
         }
     }
     block_sums_k<K>(ssq, part, red);
 }
 
-// U = A VP - coef_r U per live RHS; sums of squares of the new U per RHS.
+// U = A VP - coef_r U per live RHS (row i at U[inv[i]] or U[i]); sums of
+// squares of the new U per RHS.
 template <typename T, typename Acc, int K>
 __global__ __launch_bounds__(kBlock) void k_aprod1(SysView s, const Acc* __restrict__ VP,
                                                     Acc* __restrict__ U,
                                                     const Scalars* __restrict__ sc,
-                                                    double* __restrict__ part)
+                                                    double* __restrict__ part,
+                                                    const int32_t* __restrict__ inv)
 {
     __shared__ double red[K * kWavesPerBlock];
     const uint32_t live = live_mask<K>(sc);
@@ -1306,7 +1321,7 @@ __global__ __launch_bounds__(kBlock) void k_aprod1(SysView s, const Acc* __restr
         load_k<Acc, K>(VP + s.glob_base * K, xv);
 #pragma unroll
         for (int r = 0; r < K; ++r) sum[r] += (Acc)a[kOffGlob] * xv[r];
-        Acc* u = U + i * K;
+        Acc* u = U + (inv ? (int64_t)ldnt(&inv[i]) : i) * K;
 #pragma unroll
         for (int r = 0; r < K; ++r) {
             if (!((live >> r) & 1u)) continue;
@@ -1327,7 +1342,8 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const Acc* __restrict_
                                                     Acc* __restrict__ Q,
                                                     const int64_t* __restrict__ wb,
                                                     Acc* __restrict__ gpart, int lds_instr,
-                                                    const Scalars* __restrict__ sc)
+                                                    const Scalars* __restrict__ sc,
+                                                    const int32_t* __restrict__ inv)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Acc* lds = reinterpret_cast<Acc*>(smem_raw);
@@ -1373,9 +1389,10 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const Acc* __restrict_
         int32_t ix[kInstr];
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
+        const int64_t pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
         Acc u[K];
 #pragma unroll
-        for (int r = 0; r < K; ++r) u[r] = (ok && ((live >> r) & 1u)) ? U[ic * K + r] : (Acc)0;
+        for (int r = 0; r < K; ++r) u[r] = (ok && ((live >> r) & 1u)) ? U[pu * K + r] : (Acc)0;
 
         if (ok) {
 #pragma unroll
@@ -1461,7 +1478,8 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
                                                const Acc* __restrict__ X3, Acc* __restrict__ U,
                                                Acc* __restrict__ Q, const int64_t* __restrict__ wb,
                                                Acc* __restrict__ gpart, double* __restrict__ part,
-                                               int lds_instr, const Scalars* __restrict__ sc)
+                                               int lds_instr, const Scalars* __restrict__ sc,
+                                               const int32_t* __restrict__ inv)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ Acc gred[K * (NT / kWave)];
@@ -1522,6 +1540,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
 
+        const int64_t pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
         Acc d[K];
 #pragma unroll
         for (int r = 0; r < K; ++r) d[r] = (Acc)0;
@@ -1548,8 +1567,8 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         for (int r = 0; r < K; ++r) {
             d[r] += (Acc)a[kOffGlob] * xg[r];
             const bool on = ok && ((live >> r) & 1u);
-            const Acc nu = d[r] - coef[r] * U[ic * K + r];
-            if (on) U[ic * K + r] = nu;
+            const Acc nu = d[r] - coef[r] * U[pu * K + r];
+            if (on) U[pu * K + r] = nu;
             d[r] = on ? nu : (Acc)0;
             ssq[r] += (double)d[r] * (double)d[r];
         }
@@ -1902,85 +1921,6 @@ __global__ __launch_bounds__(kBlock) void k_scalar_stop(const double* __restrict
     }
 }
 
-// Row-reordered attitude pass for K right-hand sides: S[t][12][K].
-template <typename T, typename Acc, int K>
-__global__ __launch_bounds__(kBlock) void k_aprod2_att_sorted(
-    int64_t m, const T* __restrict__ att_sorted, const int32_t* __restrict__ perm,
-    const int32_t* __restrict__ tkey, const Acc* __restrict__ U, Acc* __restrict__ S,
-    const int64_t* __restrict__ wb, int64_t ngroups, const Scalars* __restrict__ sc)
-{
-    constexpr int kAtt = kAxes * kParAxis;
-    uint32_t live = 0;
-#pragma unroll
-    for (int r = 0; r < K; ++r) live |= ((sc[r].done || sc[r].beta_zero) ? 0u : 1u) << r;
-    if (live == 0) return;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    auto emit = [S](int64_t t, const Acc (&tot)[kAtt * K]) {
-#pragma unroll
-        for (int j = 0; j < kAtt * K; ++j) S[t * kAtt * K + j] = tot[j];
-    };
-    for (int64_t g = 0; g < ngroups; ++g) {
-        const int64_t rb = wb[g * (nw + 1) + wave], re = wb[g * (nw + 1) + wave + 1];
-        SegAcc<Acc, kAtt * K> seg;
-        for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
-            const int64_t k = r0 + lane;
-            const bool ok = k >= rb && k < re;
-            const int64_t kc = k < rb ? rb : (k < re ? k : re - 1);
-            const int64_t t = k < re ? (int64_t)ldnt(&tkey[kc]) : kNoStar;
-            const int64_t i = ldnt(&perm[kc]);
-            Acc u[K];
-#pragma unroll
-            for (int r = 0; r < K; ++r)
-                u[r] = (ok && ((live >> r) & 1u)) ? U[i * K + r] : (Acc)0;
-            Acc v[kAtt * K];
-#pragma unroll
-            for (int c = 0; c < kAtt; ++c) {
-                const Acc a = (Acc)ldnt(&att_sorted[c * m + kc]);
-#pragma unroll
-                for (int r = 0; r < K; ++r) v[c * K + r] = a * u[r];
-            }
-            seg_chunk(seg, t, v, lane, emit);
-        }
-        seg_finish(seg, lane, emit);
-    }
-}
-
-template <typename Acc, int K>
-__global__ __launch_bounds__(kBlock) void k_att_combine(const Acc* __restrict__ S, int64_t n_dfa,
-                                                         int64_t ngroups, Acc* __restrict__ qatt,
-                                                         const Scalars* __restrict__ sc)
-{
-    constexpr int kAtt = kAxes * kParAxis;
-    uint32_t live = 0;
-#pragma unroll
-    for (int r = 0; r < K; ++r) live |= ((sc[r].done || sc[r].beta_zero) ? 0u : 1u) << r;
-    if (live == 0) return;
-    const int64_t nt = n_dfa - kParAxis + 1;
-    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < kAxes * n_dfa;
-         j += (int64_t)gridDim.x * kBlock) {
-        const int64_t ax = j / n_dfa, c = j - ax * n_dfa;
-        Acc sum[K];
-#pragma unroll
-        for (int r = 0; r < K; ++r) sum[r] = (Acc)0;
-        for (int64_t g = 0; g < ngroups; ++g) {
-#pragma unroll
-            for (int qq = 0; qq < kParAxis; ++qq) {
-                const int64_t t = c - qq;
-                if (t >= 0 && t < nt)
-#pragma unroll
-                    for (int r = 0; r < K; ++r)
-                        sum[r] += S[((g * nt + t) * kAtt + ax * kParAxis + qq) * K + r];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < K; ++r)
-            if ((live >> r) & 1u) qatt[j * K + r] += sum[r];
-    }
-}
-
-// Tile-wide flag for the host: 1 when every RHS of the tile is done.
 template <int K>
 __global__ void k_all_done(Scalars* __restrict__ sc, int32_t* __restrict__ flag)
 {

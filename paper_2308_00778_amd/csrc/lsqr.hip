@@ -97,11 +97,13 @@ constexpr int kBlock2 = 1024;                   // aprod2 main-pass workgroup si
 constexpr int kWavesPerCU = 16;                 // row ranges per compute unit in aprod2
 // Rows per block of the two-level attitude sort: the block's slice of an FP64
 // row vector (8 B/row) stays well inside the 256 MB last-level cache.
-// Rows per block of the (row block, attitude start) order. Measured on the
-// 1e8-row system: 2^26 rows per block (2 blocks) 3.2 ms per attitude pass,
-// 2^24 3.3 ms, 2^22 4.2 ms, 2^20 15 ms: longer segments and fewer block
-// switches win over a smaller gather footprint.
-constexpr int64_t kAttGroupRows = (int64_t)1 << 26;
+// Attitude buckets: as few as the FP64 LDS histogram of a bucket allows
+// (3 x (W + 3) columns within kLdsInstrBudget), because the row-vector
+// accesses of the star-order passes through inv cost more the more runs they
+// split into (measured on 1e8 rows: +0.17 ms at 16 buckets, +0.65 ms at 25,
+// +1.6 ms at 100).
+constexpr int64_t kAttWidthMax = kLdsInstrBudget / (kAxes * 8) - (kParAxis - 1);
+constexpr int kAttBlock = 1024;  // attitude-pass workgroup (one per CU: the histogram fills LDS)
 
 // Working vectors of one arithmetic precision of the LSQR loop.
 template <typename Acc>
@@ -110,8 +112,6 @@ struct Path {
     Acc* vp = nullptr;     // [n] p .* v, gathered by aprod1
     Acc* q = nullptr;      // [n] aprod2 accumulator (zero between uses)
     Acc* gpart = nullptr;  // [nb2] global-column partials
-    Acc* S = nullptr;      // [(n_dfa-3)*12] attitude partials of the reordered pass
-    Acc* us = nullptr;     // [m] u~ in attitude-sorted row order (reordered pass)
     Acc* vp3 = nullptr;    // [3 n_dfa] attitude section of vp interleaved by axis
     size_t lds = 0;        // dynamic LDS bytes of aprod2
     int lds_instr = 0;
@@ -157,15 +157,18 @@ struct lsqr_handle {
     Path<double> p64;
     Path<float> p32;
 
-    // row-reordered attitude pass (built on first use)
-    int32_t* perm = nullptr;      // [m] rows sorted by attitude start
-    int32_t* tkey = nullptr;      // [m] attitude start of each sorted row
-    int32_t* invperm = nullptr;   // [m] sorted position of each row
-    void* att_sorted = nullptr;   // [12][m] attitude coefficients in sorted order
-    int64_t* wb_att = nullptr;    // [att_groups][nw + 1] t-aligned ranges per row block
-    int64_t att_group_rows = 0;   // rows per block of the two-level sort
-    int64_t att_groups = 1;       // row blocks: S has att_groups * (n_dfa - 3) segments
-    double* S_raw = nullptr;      // [(n_dfa-3)*12] partials of lsqr_aprod2
+    // attitude bucket order (built on first use in attitude mode 1)
+    int32_t* perm = nullptr;      // [m] rows in bucket order
+    int32_t* invperm = nullptr;   // [m] bucket-order position of each row
+    int32_t* tloc = nullptr;      // [m] attitude start minus its bucket's first start
+    void* att_sorted = nullptr;   // [12][m] attitude coefficients in bucket order
+    int64_t* bstart = nullptr;    // [nbk + 1] first position of each bucket
+    int64_t nbk = 0;              // buckets
+    int64_t bwidth = 0;           // attitude starts per bucket (W)
+    int att_g = 1;                // attitude-pass workgroups per bucket
+    int64_t att_buckets = 0;      // requested bucket count (0: as few as fit)
+    double* S2 = nullptr;         // [nbk att_g][3][W + 3] slices of the attitude pass
+    double* us_raw = nullptr;     // [m] lsqr_aprod2's row vector in bucket order
     double* x3_raw = nullptr;     // interleaved attitude section of lsqr_aprod1's x
     bool att_ready = false;
 
@@ -174,7 +177,7 @@ struct lsqr_handle {
         int kmax = 0;
         double *U = nullptr, *V = nullptr, *W = nullptr, *Y = nullptr, *VP = nullptr, *Q = nullptr;
         double *gpart = nullptr, *part1 = nullptr, *partc = nullptr, *partdd = nullptr,
-               *partxx = nullptr, *S = nullptr, *X3 = nullptr;
+               *partxx = nullptr, *S2 = nullptr, *X3 = nullptr;
         Scalars* sc = nullptr;
         int32_t* flag = nullptr;
         hipGraphExec_t graph[9] = {};  // by K
@@ -189,7 +192,7 @@ struct lsqr_handle {
     int chunk = 16;
     int use_graph = 1;
     int profile = 0;
-    int att_mode = 1;    // 0: attitude scatter with device atomics, 1: row-reordered pass
+    int att_mode = 1;    // 0: attitude scatter with device atomics, 1: bucket-order pass
     int astro_scan = 0;  // 1: segmented scan per chunk, 0: accumulate-and-flush segments
     int att_il = 1;      // aprod1 gathers attitude values from the interleaved copy
     int fused = 1;       // one pass for aprod1 and the non-attitude part of aprod2
@@ -204,34 +207,39 @@ struct lsqr_handle {
 
 namespace {
 
-inline int64_t att_segments(const lsqr_handle* h)
+// Placement of the solver's row vector: bucket order in attitude mode 1.
+inline const int32_t* row_map(const lsqr_handle* h)
 {
-    return h->att_groups * (h->sv.n_dfa - kParAxis + 1);
+    return h->att_mode == 1 ? h->invperm : nullptr;
 }
+
+inline int64_t att_span(const lsqr_handle* h) { return h->bwidth + kParAxis - 1; }
+inline int64_t att_slices(const lsqr_handle* h) { return h->nbk * h->att_g; }
 
 // ------------------------------------------------------------ launch helpers
 // aprod1 with the instrumental slice of x staged in LDS when it fits.
 // x3 (optional): interleaved attitude section of x, already written
 // (k_interleave_att).
+// inv (optional): placement of y (row i at y[inv[i]]).
 template <typename T, typename Acc, typename VX, typename VY, int MODE>
 void launch_aprod1(const lsqr_handle* h, const VX* x, VY* y, const double* b, const Scalars* sc,
-                   double* part, hipStream_t st, VY* ys = nullptr, const VX* x3 = nullptr)
+                   double* part, hipStream_t st, const int32_t* inv = nullptr,
+                   const VX* x3 = nullptr)
 {
     const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(VX);
-    const int32_t* ip = ys ? h->invperm : nullptr;
     const dim3 g(h->nb1), b1(kBlock1);
     if (bytes <= kLdsXBudget && x3)
         hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, true, true>), g, b1,
-                           (size_t)bytes, st, h->sv, x, y, b, sc, part, ip, ys, x3);
+                           (size_t)bytes, st, h->sv, x, y, b, sc, part, inv, x3);
     else if (bytes <= kLdsXBudget)
         hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, true, false>), g, b1,
-                           (size_t)bytes, st, h->sv, x, y, b, sc, part, ip, ys, x3);
+                           (size_t)bytes, st, h->sv, x, y, b, sc, part, inv, x3);
     else if (x3)
         hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, false, true>), g, b1, 0, st,
-                           h->sv, x, y, b, sc, part, ip, ys, x3);
+                           h->sv, x, y, b, sc, part, inv, x3);
     else
         hipLaunchKernelGGL((k_aprod1<T, Acc, VX, VY, MODE, kBlock1, false, false>), g, b1, 0, st,
-                           h->sv, x, y, b, sc, part, ip, ys, x3);
+                           h->sv, x, y, b, sc, part, inv, x3);
 }
 
 template <typename V>
@@ -252,71 +260,62 @@ void launch_fused(const lsqr_handle* h, Path<Acc>& P, hipStream_t st)
     if (P.f_ldsx && x3)
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, true, true>), g, bm, P.lds_f, st, h->sv,
                            (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
-                           h->sc);
+                           h->sc, row_map(h));
     else if (P.f_ldsx)
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, true, false>), g, bm, P.lds_f, st, h->sv,
                            (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
-                           h->sc);
+                           h->sc, row_map(h));
     else if (x3)
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, false, true>), g, bm, P.lds_f, st, h->sv,
                            (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
-                           h->sc);
+                           h->sc, row_map(h));
     else
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, false, false>), g, bm, P.lds_f, st, h->sv,
                            (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
-                           h->sc);
+                           h->sc, row_map(h));
 }
 
-// Attitude part of aprod2 by the row-reordered pass: S = segment sums over the
-// sorted rows, then q_att += their combination.
+// Attitude part of aprod2 in bucket order: per-workgroup LDS histograms of
+// each bucket's columns (ub: the row vector in bucket order), then their sum.
 template <typename T, typename Acc>
-void launch_att_pass(lsqr_handle* h, const Acc* u, Acc* q, Acc* S, const Scalars* sc,
-                     hipStream_t st, const Acc* us = nullptr)
+void launch_att_pass(lsqr_handle* h, const Acc* ub, Acc* q, const Scalars* sc, hipStream_t st)
 {
-    const dim3 ga(h->nba), b(kBlock);
-    const int64_t ns = att_segments(h) * kAxes * kParAxis;
-    hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), b, 0, st, ns, S, (Acc)0);
-    if (us)
-        hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, true>), ga, b, 0, st, h->sv.m,
-                           (const T*)h->att_sorted, (const int32_t*)h->perm,
-                           (const int32_t*)h->tkey, us, S, h->wb_att, h->att_groups, sc);
-    else
-        hipLaunchKernelGGL((k_aprod2_att_sorted<T, Acc, Acc, false>), ga, b, 0, st, h->sv.m,
-                           (const T*)h->att_sorted, (const int32_t*)h->perm,
-                           (const int32_t*)h->tkey, u, S, h->wb_att, h->att_groups, sc);
-    hipLaunchKernelGGL((k_att_combine<Acc>), dim3(h->nbc), b, 0, st, (const Acc*)S, h->sv.n_dfa,
-                       h->att_groups, q + h->sv.att_base, sc);
+    const size_t lds = (size_t)(kAxes * att_span(h) * 8);
+    hipLaunchKernelGGL((k_att_hist<T, Acc, 1, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock),
+                       lds, st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
+                       (const int64_t*)h->bstart, h->bwidth, h->att_g, ub, h->S2, sc);
+    hipLaunchKernelGGL((k_att_reduce<Acc, 1>), dim3(h->nbc), dim3(kBlock), 0, st,
+                       (const double*)h->S2, h->nbk, h->att_g, h->bwidth, h->sv.n_dfa,
+                       q + h->sv.att_base, sc);
 }
 
 // q += A^T u for the LSQR loop (and lsqr_aprod2): the main pass over the rows
-// in star order, the global-column second stage and, in the row-reordered
-// attitude mode, the attitude pass over the t-sorted rows.
-// us: u in attitude-sorted order (read sequentially by the attitude pass), or
-// nullptr to gather u through the permutation.
+// in star order (row i of u at u[inv[i]], or u[i] without inv), the
+// global-column second stage and, in attitude mode 1, the attitude pass over
+// ub, the same vector in bucket order.
 template <typename T, typename Acc>
-void launch_aprod2(lsqr_handle* h, const Acc* u, Acc* q, Acc* gpart, Acc* S, size_t lds,
-                   int lds_instr, const Scalars* sc, hipStream_t st, const Acc* us = nullptr)
+void launch_aprod2(lsqr_handle* h, const Acc* u, const int32_t* inv, Acc* q, Acc* gpart,
+                   size_t lds, int lds_instr, const Scalars* sc, hipStream_t st, const Acc* ub)
 {
     const dim3 g(h->nb2), bm(kBlock2), b(kBlock);
     const bool att = h->att_mode == 0;
     if (att && h->astro_scan)
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, true, kBlock2>), g, bm, lds, st, h->sv,
-                           u, q, h->wb, gpart, lds_instr, sc);
+                           u, q, h->wb, gpart, lds_instr, sc, inv);
     else if (att)
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, false, kBlock2>), g, bm, lds, st,
-                           h->sv, u, q, h->wb, gpart, lds_instr, sc);
+                           h->sv, u, q, h->wb, gpart, lds_instr, sc, inv);
     else if (h->astro_scan)
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, true, kBlock2>), g, bm, lds, st,
-                           h->sv, u, q, h->wb, gpart, lds_instr, sc);
+                           h->sv, u, q, h->wb, gpart, lds_instr, sc, inv);
     else
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, false, kBlock2>), g, bm, lds, st,
-                           h->sv, u, q, h->wb, gpart, lds_instr, sc);
+                           h->sv, u, q, h->wb, gpart, lds_instr, sc, inv);
     hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), b, 0, st, gpart, h->nb2, q + h->sv.glob_base, sc);
-    if (!att) launch_att_pass<T, Acc>(h, u, q, S, sc, st, us);
+    if (!att) launch_att_pass<T, Acc>(h, ub, q, sc, st);
 }
 
-// The fused pass serves the default attitude mode (row-reordered pass with u
-// gathered through the permutation).
+// The fused pass serves the default attitude mode (bucket-order pass).
 inline bool use_fused(const lsqr_handle* h) { return h->fused && h->att_mode == 1; }
 
 // One LSQR iteration; ev (optional) = 4 events bracketing aprod1 and aprod2
@@ -334,16 +333,16 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
         if (ev) (void)hipEventRecord(ev[2], st);
         hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), dim3(kBlock), 0, st, P.gpart, h->nb2,
                            P.q + h->sv.glob_base, h->sc);
-        launch_att_pass<T, Acc>(h, P.u, P.q, P.S, h->sc, st);
+        launch_att_pass<T, Acc>(h, P.u, P.q, h->sc, st);
     } else {
-        Acc* us = h->att_mode == 2 ? P.us : nullptr;
         launch_aprod1<T, Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u, nullptr, h->sc,
-                                                h->part1, st, us,
+                                                h->part1, st, row_map(h),
                                                 h->att_il ? (const Acc*)P.vp3 : nullptr);
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
         if (ev) (void)hipEventRecord(ev[2], st);
-        launch_aprod2<T, Acc>(h, P.u, P.q, P.gpart, P.S, P.lds, P.lds_instr, h->sc, st, us);
+        launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.lds, P.lds_instr, h->sc, st,
+                              P.u);
     }
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
@@ -355,21 +354,16 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
                        h->sc);
 }
 
-// Initialisation given u~ (already written) and ||u~||^2 partials in part1.
-// u_sorted_ready: u~ was also written in sorted order (residual kernel).
+// Initialisation given u~ (already written, placed by row_map) and ||u~||^2
+// partials in part1.
 template <typename T, typename Acc>
-void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st, bool u_sorted_ready = false)
+void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st)
 {
     const int64_t n = h->sv.n;
     hipLaunchKernelGGL(k_scalar_init_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, P.q, (Acc)0);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->v, 0.0);
-    Acc* us = h->att_mode == 2 ? P.us : nullptr;
-    if (us && !u_sorted_ready)
-        hipLaunchKernelGGL((k_gather_perm<Acc>), dim3(std::min<int64_t>(cdiv(h->sv.m, kBlock), 65536)),
-                           dim3(kBlock), 0, st, (const Acc*)P.u, (const int32_t*)h->perm, h->sv.m,
-                           us);
-    launch_aprod2<T, Acc>(h, P.u, P.q, P.gpart, P.S, P.lds, P.lds_instr, h->sc, st, us);
+    launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.lds, P.lds_instr, h->sc, st, P.u);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
                        h->sc, h->partc);
     hipLaunchKernelGGL(k_scalar_init_alpha, dim3(1), dim3(kBlock), 0, st, h->partc, h->nbc, h->sc);
@@ -386,26 +380,42 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     LSQR_TRY(dalloc(&P.vp, n));
     LSQR_TRY(dalloc(&P.q, n));
     LSQR_TRY(dalloc(&P.gpart, h->nb2));
-    LSQR_TRY(dalloc(&P.S, att_segments(h) * kAxes * kParAxis));
-    LSQR_TRY(dalloc(&P.us, m));
     LSQR_TRY(dalloc(&P.vp3, (int64_t)kAxes * h->sv.n_dfa));
-    const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(Acc);
-    P.lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
-    P.lds = P.lds_instr ? (size_t)bytes : 0;
+    // LDS histograms are FP64 whatever Acc is (k_att_hist)
+    const int64_t hbytes = h->sv.n_instr_cols * 8;
+    const int64_t xbytes = h->sv.n_instr_cols * (int64_t)sizeof(Acc);
+    P.lds_instr = hbytes <= kLdsInstrBudget ? 1 : 0;
+    P.lds = P.lds_instr ? (size_t)hbytes : 0;
     // fused pass: the histogram first (device atomics otherwise cost far
     // more), then the slice of vp if both fit
     P.f_instr = P.lds_instr;
-    const int64_t hist = P.f_instr ? (bytes + 15) & ~(int64_t)15 : 0;
-    P.f_ldsx = hist + bytes <= kLdsInstrBudget ? 1 : 0;
-    P.lds_f = (size_t)(P.f_ldsx ? hist + bytes : hist);
+    const int64_t hist = P.f_instr ? (hbytes + 15) & ~(int64_t)15 : 0;
+    P.f_ldsx = hist + xbytes <= kLdsInstrBudget ? 1 : 0;
+    P.lds_f = (size_t)(P.f_ldsx ? hist + xbytes : hist);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n, P.q, (Acc)0);
     HIP_TRY(hipGetLastError());
     P.ready = true;
     return LSQR_OK;
 }
 
-// Row-reordered attitude structures: a stable radix sort of the rows by t,
-// the attitude coefficients gathered into that order, t-aligned wave ranges.
+// Attitude bucket geometry: the fewest buckets whose FP64 histogram fits in
+// LDS, or the requested count (raised if needed); workgroups per bucket so
+// that the attitude pass runs in one round of one workgroup per CU.
+void att_geometry(lsqr_handle* h)
+{
+    const int64_t nt = h->sv.n_dfa - kParAxis + 1;
+    int64_t nb = h->att_buckets > 0 ? h->att_buckets : cdiv(nt, kAttWidthMax);
+    nb = std::max<int64_t>(1, std::min(nb, nt));
+    int64_t w = cdiv(nt, nb);
+    if (w > kAttWidthMax) w = kAttWidthMax;
+    h->bwidth = w;
+    h->nbk = cdiv(nt, w);
+    h->att_g = (int)std::max<int64_t>(1, h->num_cu / h->nbk);
+}
+
+// Attitude bucket order: a stable radix sort of the rows by t / W, the
+// attitude coefficients and local starts gathered into that order, the
+// inverse permutation and the bucket boundaries.
 template <typename T>
 lsqr_status prepare_att_sorted(lsqr_handle* h)
 {
@@ -413,55 +423,51 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
     const int64_t m = h->sv.m;
     if (m >= ((int64_t)1 << 31) || h->sv.n_dfa >= ((int64_t)1 << 31))
         return fail(LSQR_E_UNSUPPORTED,
-                    "row-reordered attitude pass needs n_rows < 2^31 and n_dfa < 2^31");
+                    "the attitude bucket order needs n_rows < 2^31 and n_dfa < 2^31");
+    att_geometry(h);
     hipStream_t st = h->stream;
-    int32_t *keys = nullptr, *rows = nullptr;
+    int32_t *keys = nullptr, *rows = nullptr, *skeys = nullptr;
     void* temp = nullptr;
     size_t temp_bytes = 0;
-    const int64_t nt = h->sv.n_dfa - kParAxis + 1;
-    if (h->att_groups * nt >= ((int64_t)1 << 31))
-        return fail(LSQR_E_UNSUPPORTED, "too many attitude sort segments");
     int bits = 1;
-    while (bits < 31 && ((int64_t)1 << bits) < h->att_groups * nt) ++bits;
+    while (bits < 31 && ((int64_t)1 << bits) < h->nbk) ++bits;
     LSQR_TRY(dalloc(&h->perm, m));
-    LSQR_TRY(dalloc(&h->tkey, m));
     LSQR_TRY(dalloc(&h->invperm, m));
-    LSQR_TRY(dalloc(&h->wb_att, h->att_groups * (h->nw + 1)));
-    LSQR_TRY(dalloc(&h->S_raw, att_segments(h) * kAxes * kParAxis));
+    LSQR_TRY(dalloc(&h->tloc, m));
+    LSQR_TRY(dalloc(&h->bstart, h->nbk + 1));
+    LSQR_TRY(dalloc(&h->S2, att_slices(h) * kAxes * att_span(h)));
     T* att_sorted = nullptr;
     LSQR_TRY(dalloc(&att_sorted, (int64_t)kAxes * kParAxis * m));
     h->att_sorted = att_sorted;
     LSQR_TRY(dalloc(&keys, m));
     lsqr_status rc = dalloc(&rows, m);
+    if (rc == LSQR_OK) rc = dalloc(&skeys, m);
     hipError_t e = hipSuccess;
+    const dim3 gm(std::min<int64_t>(cdiv(m, kBlock), 65536)), bb(kBlock);
     if (rc == LSQR_OK) {
-        hipLaunchKernelGGL(k_att_keys, dim3(std::min<int64_t>(cdiv(m, kBlock), 65536)), dim3(kBlock),
-                           0, st, h->sv.att, m, h->att_group_rows, nt, keys, rows);
-        e = rocprim::radix_sort_pairs(nullptr, temp_bytes, keys, h->tkey, rows, h->perm,
-                                      (size_t)m, 0, bits, st);
+        hipLaunchKernelGGL(k_bucket_keys, gm, bb, 0, st, h->sv.att, m, h->bwidth, keys, rows);
+        e = rocprim::radix_sort_pairs(nullptr, temp_bytes, keys, skeys, rows, h->perm, (size_t)m,
+                                      0, bits, st);
         if (e == hipSuccess) rc = dalloc(reinterpret_cast<char**>(&temp), (int64_t)temp_bytes);
     }
     if (rc == LSQR_OK && e == hipSuccess)
-        e = rocprim::radix_sort_pairs(temp, temp_bytes, keys, h->tkey, rows, h->perm, (size_t)m, 0,
+        e = rocprim::radix_sort_pairs(temp, temp_bytes, keys, skeys, rows, h->perm, (size_t)m, 0,
                                       bits, st);
     if (rc == LSQR_OK && e == hipSuccess) {
-        hipLaunchKernelGGL((k_att_gather<T>), dim3(std::min<int64_t>(cdiv(m, kBlock), 65536)),
-                           dim3(kBlock), 0, st, (const T*)h->sv.val, m, (const int32_t*)h->perm,
-                           att_sorted);
-        hipLaunchKernelGGL(k_invert_perm, dim3(std::min<int64_t>(cdiv(m, kBlock), 65536)),
-                           dim3(kBlock), 0, st, (const int32_t*)h->perm, m, h->invperm);
-        const int64_t nw = h->nw;
-        hipLaunchKernelGGL(k_group_bounds, dim3(cdiv(h->att_groups * (nw + 1), kBlock)),
-                           dim3(kBlock), 0, st, (const int32_t*)h->tkey, m, h->att_group_rows,
-                           h->att_groups, nw, h->wb_att);
+        hipLaunchKernelGGL((k_att_gather<T>), gm, bb, 0, st, (const T*)h->sv.val, h->sv.att, m,
+                           (const int32_t*)h->perm, h->bwidth, att_sorted, h->tloc);
+        hipLaunchKernelGGL(k_invert_perm, gm, bb, 0, st, (const int32_t*)h->perm, m, h->invperm);
+        hipLaunchKernelGGL(k_bucket_starts, dim3(std::min<int64_t>(cdiv(m + 1, kBlock), 65536)), bb,
+                           0, st, (const int32_t*)skeys, m, h->nbk, h->bstart);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
     if (temp) (void)hipFree(temp);
     dfree(keys);
     dfree(rows);
+    dfree(skeys);
     if (rc != LSQR_OK) return rc;
-    if (e != hipSuccess) return fail(LSQR_E_HIP, "attitude reordering: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(LSQR_E_HIP, "attitude bucket order: %s", hipGetErrorString(e));
     h->att_ready = true;
     return LSQR_OK;
 }
@@ -481,8 +487,6 @@ void release_path(Path<Acc>& P)
     dfree(P.vp);
     dfree(P.q);
     dfree(P.gpart);
-    dfree(P.S);
-    dfree(P.us);
     dfree(P.vp3);
     P.ready = false;
 }
@@ -603,7 +607,7 @@ lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_l
     }
     LSQR_TRY(upload_controls(h, itn_limit, atol, btol));
     hipLaunchKernelGGL((k_copy_ssq<double>), dim3(h->nb1), dim3(kBlock), 0, h->stream, m, b, P.u,
-                       h->part1);
+                       h->part1, row_map(h));
     launch_init<T, double>(h, P, h->stream);
     HIP_TRY(hipGetLastError());
     LSQR_TRY(read_scalars(h));
@@ -619,16 +623,17 @@ lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_l
 lsqr_status batch_alloc(lsqr_handle* h, int kmax)
 {
     auto& B = h->batch;
-    if (B.kmax >= kmax) return LSQR_OK;
+    if (B.kmax >= kmax && (B.S2 || !h->att_ready)) return LSQR_OK;
+    kmax = std::max(kmax, B.kmax);
     const int64_t m = h->sv.m, n = h->sv.n;
     // free the smaller set (graphs reference it)
     for (auto& g : B.graph)
         if (g) (void)hipGraphExecDestroy(g), g = nullptr;
     dfree(B.U); dfree(B.V); dfree(B.W); dfree(B.Y); dfree(B.VP); dfree(B.Q);
     dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
-    dfree(B.sc); dfree(B.flag); dfree(B.S); dfree(B.X3);
+    dfree(B.sc); dfree(B.flag); dfree(B.S2); dfree(B.X3);
     B.kmax = 0;
-    LSQR_TRY(dalloc(&B.S, att_segments(h) * kAxes * kParAxis * kmax));
+    if (h->att_ready) LSQR_TRY(dalloc(&B.S2, att_slices(h) * kAxes * att_span(h) * kmax));
     LSQR_TRY(dalloc(&B.X3, (int64_t)kAxes * h->sv.n_dfa * kmax));
     LSQR_TRY(dalloc(&B.U, m * kmax));
     LSQR_TRY(dalloc(&B.V, n * kmax));
@@ -657,7 +662,7 @@ void batch_free(lsqr_handle* h)
         if (g) (void)hipGraphExecDestroy(g), g = nullptr;
     dfree(B.U); dfree(B.V); dfree(B.W); dfree(B.Y); dfree(B.VP); dfree(B.Q);
     dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
-    dfree(B.sc); dfree(B.flag); dfree(B.S); dfree(B.X3);
+    dfree(B.sc); dfree(B.flag); dfree(B.S2); dfree(B.X3);
     B.kmax = 0;
 }
 
@@ -690,15 +695,14 @@ template <typename T, int K>
 void batch_att_pass(lsqr_handle* h, hipStream_t st)
 {
     auto& B = h->batch;
-    const int64_t ns = att_segments(h) * kAxes * kParAxis * K;
-    hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, ns, B.S, 0.0);
-    hipLaunchKernelGGL((batched::k_aprod2_att_sorted<T, double, K>), dim3(h->nba), dim3(kBlock), 0,
-                       st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->perm,
-                       (const int32_t*)h->tkey, (const double*)B.U, B.S, h->wb_att,
-                       h->att_groups, B.sc);
-    hipLaunchKernelGGL((batched::k_att_combine<double, K>), dim3(h->nbc), dim3(kBlock), 0, st,
-                       (const double*)B.S, h->sv.n_dfa, h->att_groups, B.Q + h->sv.att_base * K,
+    const size_t lds = (size_t)(kAxes * att_span(h) * 8);
+    hipLaunchKernelGGL((k_att_hist<T, double, K, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock),
+                       lds, st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
+                       (const int64_t*)h->bstart, h->bwidth, h->att_g, (const double*)B.U, B.S2,
                        B.sc);
+    hipLaunchKernelGGL((k_att_reduce<double, K>), dim3(h->nbc), dim3(kBlock), 0, st,
+                       (const double*)B.S2, h->nbk, h->att_g, h->bwidth, h->sv.n_dfa,
+                       B.Q + h->sv.att_base * K, B.sc);
 }
 
 template <typename T, int K>
@@ -711,10 +715,12 @@ void batch_aprod2(lsqr_handle* h, hipStream_t st)
     const int grid = batch_grid<K>(h);
     if (h->att_mode == 0)
         hipLaunchKernelGGL((batched::k_aprod2<T, double, K, true, NT>), dim3(grid), dim3(NT), lds,
-                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
+                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc,
+                           row_map(h));
     else
         hipLaunchKernelGGL((batched::k_aprod2<T, double, K, false, NT>), dim3(grid), dim3(NT), lds,
-                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc);
+                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc,
+                           row_map(h));
     hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
                        (const double*)B.gpart, grid, B.Q + h->sv.glob_base * K, B.sc);
     if (h->att_mode != 0) batch_att_pass<T, K>(h, st);
@@ -747,19 +753,20 @@ void batch_fused(lsqr_handle* h, hipStream_t st, size_t lds, int ldsx)
     }
     if (ldsx && X3)
         hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, true, true>), g, bm, lds, st, h->sv,
-                           (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1, B.sc);
+                           (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1, B.sc,
+                           row_map(h));
     else if (ldsx)
         hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, true, false>), g, bm, lds, st,
                            h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1,
-                           B.sc);
+                           B.sc, row_map(h));
     else if (X3)
         hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, false, true>), g, bm, lds, st,
                            h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1,
-                           B.sc);
+                           B.sc, row_map(h));
     else
         hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, false, false>), g, bm, lds, st,
                            h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1,
-                           B.sc);
+                           B.sc, row_map(h));
 }
 
 template <typename T, int K>
@@ -782,7 +789,7 @@ void batch_iteration(lsqr_handle* h, hipStream_t st, hipEvent_t* ev)
         batch_att_pass<T, K>(h, st);
     } else {
         hipLaunchKernelGGL((batched::k_aprod1<T, double, K>), dim3(h->nb1), dim3(kBlock), 0, st,
-                           h->sv, (const double*)B.VP, B.U, B.sc, B.part1);
+                           h->sv, (const double*)B.VP, B.U, B.sc, B.part1, row_map(h));
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL((batched::k_scalar_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1,
                            h->nb1, B.sc);
@@ -823,7 +830,7 @@ lsqr_status batch_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X,
     }
     HIP_TRY(hipMemcpyAsync(B.sc, host, K * sizeof(Scalars), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL((batched::k_copy_ssq<double, K>), dim3(h->nb1), dim3(kBlock), 0, st, m, Bm,
-                       ldb, B.U, B.part1);
+                       ldb, B.U, B.part1, row_map(h));
     hipLaunchKernelGGL((batched::k_scalar_init_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1,
                        h->nb1, B.sc);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n * K, B.Q, 0.0);
@@ -1101,8 +1108,6 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
         h->nba = (int)(nw / kWavesPerBlock);
     }
     h->nbc = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)h->num_cu * 4, cdiv(n, kBlock)));
-    h->att_group_rows = kAttGroupRows;
-    h->att_groups = cdiv(m, h->att_group_rows);
 
     lsqr_status st;
     const int64_t nw = h->nw;
@@ -1187,11 +1192,12 @@ lsqr_status lsqr_destroy(lsqr_handle* h)
     batch_free(h);
     dfree(h->wb);
     dfree(h->perm);
-    dfree(h->tkey);
+    dfree(h->tloc);
     dfree(h->invperm);
+    dfree(h->bstart);
+    dfree(h->S2);
+    dfree(h->us_raw);
     dfree(h->x3_raw);
-    dfree(h->wb_att);
-    dfree(h->S_raw);
     if (h->att_sorted) (void)hipFree(h->att_sorted);
     h->att_sorted = nullptr;
     dfree(h->p);
@@ -1235,8 +1241,8 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         return LSQR_OK;
     case LSQR_OPT_ATT_MODE:
     case LSQR_OPT_ASTRO_SCAN: {
-        if (option == LSQR_OPT_ATT_MODE && !(value == 0.0 || value == 1.0 || value == 2.0))
-            return fail(LSQR_E_INVALID, "attitude mode must be 0, 1 or 2");
+        if (option == LSQR_OPT_ATT_MODE && !(value == 0.0 || value == 1.0))
+            return fail(LSQR_E_INVALID, "attitude mode must be 0 or 1");
         const int v = option == LSQR_OPT_ATT_MODE ? (int)value : (value != 0.0 ? 1 : 0);
         int& slot = option == LSQR_OPT_ATT_MODE ? h->att_mode : h->astro_scan;
         if (slot != v) {  // captured graphs bake in the kernel choice
@@ -1266,13 +1272,12 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
             return fail(LSQR_E_INVALID, "k-tile must be 0 (autotune), 1, 2, 4 or 8");
         h->ktile = (int)value;
         return LSQR_OK;
-    case LSQR_OPT_ATT_GROUP_ROWS: {
-        if (h->att_ready || h->p64.ready || h->p32.ready || h->batch.kmax > 0 || h->S_raw)
-            return fail(LSQR_E_STATE, "attitude row blocks must be set before the first solve");
-        if (!(value >= (double)kWave && value <= 2147483647.0))
-            return fail(LSQR_E_INVALID, "rows per attitude block must be in [64, 2^31)");
-        h->att_group_rows = (int64_t)value;
-        h->att_groups = cdiv(h->sv.m, h->att_group_rows);
+    case LSQR_OPT_ATT_BUCKETS: {
+        if (h->att_ready)
+            return fail(LSQR_E_STATE, "attitude buckets must be set before the first solve");
+        if (!(value >= 0.0 && value <= 2147483647.0))
+            return fail(LSQR_E_INVALID, "attitude bucket count must be in [0, 2^31)");
+        h->att_buckets = (int64_t)value;
         return LSQR_OK;
     }
     case LSQR_OPT_OUTER_TOL:
@@ -1312,12 +1317,22 @@ lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y)
     const int64_t bytes = h->sv.n_instr_cols * 8;
     const int lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
     const size_t lds = lds_instr ? (size_t)bytes : 0;
+    // y in row order for the star-order pass; a copy in bucket order for the
+    // attitude pass
+    const double* yb = nullptr;
+    if (h->att_mode == 1) {
+        if (!h->us_raw) LSQR_TRY(dalloc(&h->us_raw, h->sv.m));
+        hipLaunchKernelGGL((k_gather_perm<double>),
+                           dim3(std::min<int64_t>(cdiv(h->sv.m, kBlock), 65536)), dim3(kBlock), 0,
+                           h->user_stream, y, (const int32_t*)h->perm, h->sv.m, h->us_raw);
+        yb = h->us_raw;
+    }
     if (h->value_type == LSQR_F64)
-        launch_aprod2<double, double>(h, y, x, h->gpart_raw, h->S_raw, lds, lds_instr, nullptr,
-                                      h->user_stream);
+        launch_aprod2<double, double>(h, y, nullptr, x, h->gpart_raw, lds, lds_instr, nullptr,
+                                      h->user_stream, yb);
     else
-        launch_aprod2<float, double>(h, y, x, h->gpart_raw, h->S_raw, lds, lds_instr, nullptr,
-                                     h->user_stream);
+        launch_aprod2<float, double>(h, y, nullptr, x, h->gpart_raw, lds, lds_instr, nullptr,
+                                     h->user_stream, yb);
     HIP_TRY(hipGetLastError());
     return LSQR_OK;
 }
@@ -1391,9 +1406,8 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
             x3 = h->x3_raw;
         }
         launch_aprod1<float, double, double, float, A1_RESID>(h, (const double*)x, P.u, b, nullptr,
-                                                              h->part1, h->stream,
-                                                              h->att_mode == 2 ? P.us : nullptr, x3);
-        launch_init<float, float>(h, P, h->stream, true);
+                                                              h->part1, h->stream, row_map(h), x3);
+        launch_init<float, float>(h, P, h->stream);
         HIP_TRY(hipGetLastError());
         LSQR_TRY(read_scalars(h));
         if (outer == 1) bnorm = h->sc_host->bnorm;

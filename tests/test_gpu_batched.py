@@ -47,7 +47,7 @@ def test_batched_fixed_iterations(torch_cuda, c0, ktile, att_mode, fused):
     g = LsqrSystem.from_host(S, "cuda:0")
     g.set_option("att_mode", att_mode)
     g.set_option("fused", fused)
-    g.set_option("att_group_rows", 7000)
+    g.set_option("att_buckets", 4)
     g.set_option("tests", 0)
     g.set_option("ktile", ktile)
     X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(B)).cuda(), itn, 0.0, 0.0)
