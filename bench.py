@@ -262,6 +262,105 @@ def batched_leg(cfg: int, dev, singles: int = 2):
     return out
 
 
+def largest_leg(cfg: int, dev):
+    """The largest single-GPU workload (FP32 values, uneven stars): the FP64
+    solve of the FP32-stored system, the FP32 + FP64 refinement solve, and its
+    k noise realisations batched (FP64 arithmetic on the FP32 values, k-tile
+    2 to stay within HBM), all to convergence at atol = btol = 1e-12."""
+    import torch
+
+    import synth
+    from paper_2308_00778_amd import LsqrError, LsqrSystem
+
+    def free_gb():
+        return torch.cuda.mem_get_info(dev)[0] / 1e9
+
+    spec = synth.CONFIGS[cfg]
+    k = spec.n_rhs
+    t0 = time.perf_counter()
+    arrays, first = synth.device_system(spec, dev)
+    m = int(first[-1])
+    g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
+                   n_instr_cols=spec.n_instr_cols)
+    xt = synth.device_x_true(spec, dev)
+    b = synth.device_noise(spec, m, 0, dev)
+    g.aprod1(xt, b)
+    torch.cuda.synchronize()
+    log(f"largest leg: m={m} n={g.n} ready in {time.perf_counter() - t0:.1f} s, "
+        f"{free_gb():.0f} GB free")
+    out = {"workload": f"{spec.n_stars} stars x U{{{spec.obs_lo}..{spec.obs_hi}}} obs = {m} rows "
+                       f"x {g.n} unknowns, FP32 values, N_DFA={spec.n_dfa}, "
+                       f"{spec.n_instr_cols} instrumental, k = {k}"}
+    g.solve(b, 2, atol=0.0, btol=0.0)
+    g.solve_refined(b, 2, atol=1e-6, btol=1e-6, outer_limit=1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x64, i64 = g.solve(b, 500, atol=1e-12, btol=1e-12)
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    x32, i32 = g.solve_refined(b, 200, atol=1e-6, btol=1e-6, outer_limit=10)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t2
+    g.set_option("profile", 1)
+    g.set_option("tests", 0)
+    g.solve(b, 16, atol=0.0, btol=0.0)
+    ms64 = pass_times(g.kernel_times(), True)
+    g.solve_refined(b, 16, atol=0.0, btol=0.0, outer_limit=1)
+    ms32 = pass_times(g.kernel_times(), True)
+    g.set_option("profile", 0)
+    g.set_option("tests", 1)
+    # FP64 arithmetic on FP32 values: 24 x 4 + 40 + u 16 per fused row, 12 x 4 + 4 + 8
+    # per attitude row; the FP32 inner solve: BYTES_PER_ROW_F32
+    bpr64 = {"fused": 24 * 4 + 40 + 16, "attitude": 12 * 4 + 4 + 8}
+    out.update({
+        "fp64_seconds": t_fp64, "fp64_itn": i64.itn, "fp64_istop": i64.istop,
+        "refined_seconds": t_ref, "refined_inner_itn": i32.itn,
+        "refined_outer_steps": i32.outer_steps, "speedup_vs_fp64": t_fp64 / t_ref,
+        "rel_inf_err_vs_fp64": rel_inf(x32, x64),
+        "fp64_kernels": {kk: {"ms": v, "GBps": bpr64[kk] * m / (v * 1e-3) / 1e9,
+                              "bytes_per_row": bpr64[kk]} for kk, v in ms64.items()},
+        "inner_kernels": {kk: {"ms": v, "GBps": BYTES_PER_ROW_F32[kk] * m / (v * 1e-3) / 1e9,
+                               "bytes_per_row": BYTES_PER_ROW_F32[kk]} for kk, v in ms32.items()},
+    })
+    log(f"largest leg: fp64 {t_fp64:.2f} s ({i64.itn} it), refined {t_ref:.2f} s "
+        f"({i32.itn} inner, {i32.outer_steps} outer), err {out['rel_inf_err_vs_fp64']:.2e}; "
+        f"{free_gb():.0f} GB free")
+    del x32
+    torch.cuda.empty_cache()
+    try:
+        B = torch.empty((m, k), dtype=torch.float64, device=dev)
+        B[:, 0] = b
+        del b
+        for j in range(1, k):
+            bj = synth.device_noise(spec, m, j, dev)
+            g.aprod1(xt, bj)
+            B[:, j] = bj
+            del bj
+        torch.cuda.synchronize()
+        g.set_option("ktile", 2)
+        t3 = time.perf_counter()
+        X, infos = g.solve_batched(B, 500, 1e-12, 1e-12)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t3
+        rhs_itn = sum(i.itn for i in infos)
+        out["batched"] = {"k": k, "k_tile": 2, "seconds": t_b, "rhs_iterations": rhs_itn,
+                          "rhs_iter_per_s": rhs_itn / t_b,
+                          "fp64_single_rhs_iter_per_s": i64.itn / t_fp64,
+                          "rel_inf_err_rhs0_vs_single": rel_inf(X[:, 0], x64),
+                          "itn_per_rhs": [i.itn for i in infos]}
+        log(f"largest leg: batched {rhs_itn} RHS-iterations in {t_b:.2f} s, "
+            f"{free_gb():.0f} GB free")
+        del B, X
+    except (LsqrError, torch.cuda.OutOfMemoryError) as e:
+        out["batched"] = {"skipped": f"{type(e).__name__}: {e}"}
+        log(f"largest leg: batched skipped ({e})")
+    g.close()
+    del arrays, x64
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration(dev, gib: float = 4.0, reps: int = 5):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -284,7 +383,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="refine,batched",
                     help="comma list of extra legs: refine (FP32 + FP64 refinement), "
-                         "batched (k right-hand sides), none")
+                         "batched (k right-hand sides), largest (the 1e9-row FP32 "
+                         "workload, about 270 GB of HBM), none")
     ap.add_argument("--copy", action="store_true", help="only run the copy calibration")
     ap.add_argument("--attitude-ab", action="store_true",
                     help="only time the attitude variants of aprod2")
@@ -398,6 +498,8 @@ def main():
         result["fp32_refine"] = refine_leg(2, dev)
     if "batched" in forms:
         result["batched"] = batched_leg(3, dev)
+    if "largest" in forms:
+        result["largest"] = largest_leg(4, dev)
     if not args.no_cpu_baseline:
         log("timing the oracle on a sample ...")
         result["cpu_baseline"] = cpu_baseline(spec)

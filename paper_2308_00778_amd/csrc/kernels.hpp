@@ -390,9 +390,10 @@ __device__ __forceinline__ void seg_flush(int64_t key, const Acc (&v)[NV], int l
 
 // x += A^T y (SQUARE: x_j += sum of squared coefficients of column j, used
 // for the column norms). wb: star-aligned row boundaries, one range per wave
-// (gridDim.x * kWavesPerBlock ranges). The instrumental columns are
-// accumulated in LDS when lds_instr != 0 (n_instr_cols * sizeof(Acc) bytes of
-// dynamic shared memory), else by device atomics. gpart[blockIdx.x] gets the
+// (gridDim.x * kWavesPerBlock ranges). Instrumental columns [0, hcols) are
+// accumulated in an FP64 LDS histogram (hcols * 8 bytes of dynamic shared
+// memory) flushed with one device atomic per column per workgroup; columns
+// from hcols on are left to k_instr_tail. gpart[blockIdx.x] gets the
 // workgroup's global-column partial; k_glob_sum adds them up.
 // ATT = false leaves the attitude columns to the bucket-order pass
 // (k_att_hist) and skips loading them. SCAN selects the astrometric
@@ -404,7 +405,7 @@ template <typename T, typename Acc, typename VU, bool SQUARE, bool ATT = true, b
 __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__ u,
                                                     Acc* __restrict__ q,
                                                     const int64_t* __restrict__ wb,
-                                                    Acc* __restrict__ gpart, int lds_instr,
+                                                    Acc* __restrict__ gpart, int64_t hcols,
                                                     const Scalars* __restrict__ sc,
                                                     const int32_t* __restrict__ inv = nullptr)
 {
@@ -415,11 +416,8 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
 
     const T* __restrict__ val = static_cast<const T*>(s.val);
     const int64_t m = s.m;
-    const int64_t ninst = s.n_instr_cols;
-    if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst; j += NT) lds[j] = 0.0;
-        __syncthreads();
-    }
+    for (int64_t j = threadIdx.x; j < hcols; j += NT) lds[j] = 0.0;
+    __syncthreads();
 
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave;
@@ -475,10 +473,8 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
             }
             // instrumental
 #pragma unroll
-            for (int j = 0; j < kInstr; ++j) {
-                if (lds_instr) atomicAdd(&lds[ix[j]], (double)contrib[kOffInstr + j]);
-                else atomicAdd(&qins[ix[j]], contrib[kOffInstr + j]);
-            }
+            for (int j = 0; j < kInstr; ++j)
+                if (ix[j] < hcols) atomicAdd(&lds[ix[j]], (double)contrib[kOffInstr + j]);
         }
         gsum += contrib[kOffGlob];
 
@@ -530,11 +526,9 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
         gpart[blockIdx.x] = g;
     }
     // instrumental flush: one device atomic per column per workgroup
-    if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst; j += NT) {
-            const double v = lds[j];
-            if (v != 0.0) atomicAdd(&qins[j], (Acc)v);
-        }
+    for (int64_t j = threadIdx.x; j < hcols; j += NT) {
+        const double v = lds[j];
+        if (v != 0.0) atomicAdd(&qins[j], (Acc)v);
     }
 }
 
@@ -553,15 +547,15 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
 //   part[blockIdx.x]: FP64 sum of squares of the
 //   stored u~, q: A^T u~ accumulator (astro, instr, glob sections),
 //   gpart[blockIdx.x]: global-column partial, wb: star-aligned wave ranges.
-// Dynamic LDS: the instrumental histogram (lds_instr, n_instr_cols FP64, see
-// k_att_hist) and, after it, the instrumental slice of x (LDSX,
-// n_instr_cols Acc).
+// Dynamic LDS: the FP64 histogram of instrumental columns [0, hcols) (see
+// k_att_hist; columns from hcols on are left to k_instr_tail) and, after it,
+// the instrumental slice of x (LDSX, n_instr_cols Acc).
 template <typename T, typename Acc, int NT, bool LDSX, bool ATTI>
 __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ x,
                                                const Acc* __restrict__ x3, Acc* __restrict__ u,
                                                Acc* __restrict__ q, const int64_t* __restrict__ wb,
                                                Acc* __restrict__ gpart, double* __restrict__ part,
-                                               int lds_instr, const Scalars* __restrict__ sc,
+                                               int64_t hcols, const Scalars* __restrict__ sc,
                                                const int32_t* __restrict__ inv)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -574,15 +568,14 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
     const int64_t ninst = s.n_instr_cols;
     double* hist = reinterpret_cast<double*>(smem_raw);
     const Acc* xi = x + s.instr_base;
-    if (lds_instr)
-        for (int64_t j = threadIdx.x; j < ninst; j += NT) hist[j] = 0.0;
+    for (int64_t j = threadIdx.x; j < hcols; j += NT) hist[j] = 0.0;
     if (LDSX) {
-        const int64_t off = lds_instr ? (ninst * 8 + 15) & ~(int64_t)15 : 0;
+        const int64_t off = (hcols * 8 + 15) & ~(int64_t)15;
         Acc* xl = reinterpret_cast<Acc*>(smem_raw + off);
         for (int64_t j = threadIdx.x; j < ninst; j += NT) xl[j] = xi[j];
         xi = xl;
     }
-    if (lds_instr || LDSX) __syncthreads();
+    __syncthreads();
 
     const Acc coef = (Acc)sc->coef_u;
     const Acc xg = x[s.glob_base];
@@ -643,9 +636,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         if (ok) {
 #pragma unroll
             for (int j = 0; j < kInstr; ++j) {
-                const Acc c = (Acc)a[kOffInstr + j] * d;
-                if (lds_instr) atomicAdd(&hist[ix[j]], (double)c);
-                else atomicAdd(&qins[ix[j]], c);
+                if (ix[j] < hcols) atomicAdd(&hist[ix[j]], (double)((Acc)a[kOffInstr + j] * d));
             }
         }
         gsum += (Acc)a[kOffGlob] * d;
@@ -677,11 +668,67 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         gpart[blockIdx.x] = g;
         part[blockIdx.x] = r;
     }
-    if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst; j += NT) {
-            const double v = hist[j];
-            if (v != 0.0) atomicAdd(&qins[j], (Acc)v);
+    for (int64_t j = threadIdx.x; j < hcols; j += NT) {
+        const double v = hist[j];
+        if (v != 0.0) atomicAdd(&qins[j], (Acc)v);
+    }
+}
+
+// Instrumental columns [c0, c1) of Eq. (3) (or of the squared column norms,
+// SQUARE) when the row passes keep only the first columns in LDS: workgroup b
+// sweeps rows [b m / G, (b+1) m / G) with an FP64 LDS histogram of the
+// window, then flushes it with one device atomic per column. U holds K
+// values per row, row i at U[inv[i] K + r] (U[i K + r] without inv); frozen
+// RHS (done or beta_zero) are skipped.
+template <typename T, typename Acc, int K, bool SQUARE, int NT>
+__global__ __launch_bounds__(NT) void k_instr_tail(SysView s, const Acc* __restrict__ U,
+                                                    const int32_t* __restrict__ inv,
+                                                    Acc* __restrict__ Q, int64_t c0, int64_t c1,
+                                                    const Scalars* __restrict__ sc)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* hist = reinterpret_cast<double*>(smem_raw);
+    uint32_t live = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+        live |= (sc != nullptr && (sc[r].done || sc[r].beta_zero)) ? 0u : (1u << r);
+    if (live == 0) return;
+    const T* __restrict__ val = static_cast<const T*>(s.val);
+    const int64_t m = s.m, w = c1 - c0;
+    for (int64_t e = threadIdx.x; e < w * K; e += NT) hist[e] = 0.0;
+    __syncthreads();
+    const int64_t r0 = blockIdx.x * m / gridDim.x, r1 = (blockIdx.x + 1) * m / gridDim.x;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
+        int32_t ix[kInstr];
+        T a[kInstr];
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) {
+            ix[j] = ldnt(&s.instr[j * m + i]);
+            a[j] = ldnt(&val[(kOffInstr + j) * m + i]);
         }
+        double u[K];
+        if (!SQUARE) {
+            const int64_t pu = inv ? (int64_t)ldnt(&inv[i]) : i;
+#pragma unroll
+            for (int r = 0; r < K; ++r) u[r] = ((live >> r) & 1u) ? (double)U[pu * K + r] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) {
+            const int64_t c = (int64_t)ix[j] - c0;
+            if (c < 0 || c >= w) continue;
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                if (!((live >> r) & 1u)) continue;
+                const double av = (double)(Acc)a[j];
+                atomicAdd(&hist[c * K + r], SQUARE ? av * av : (double)((Acc)a[j] * (Acc)u[r]));
+            }
+        }
+    }
+    __syncthreads();
+    Acc* __restrict__ qins = Q + (s.instr_base + c0) * K;
+    for (int64_t e = threadIdx.x; e < w * K; e += NT) {
+        const double v = hist[e];
+        if (v != 0.0) atomicAdd(&qins[e], (Acc)v);
     }
 }
 
@@ -1335,18 +1382,18 @@ __global__ __launch_bounds__(kBlock) void k_aprod1(SysView s, const Acc* __restr
 
 // Q += A^T U over star-aligned per-wave ranges (astrometric: accumulate-and-
 // flush segments, attitude: device atomics, instrumental: LDS histogram
-// [n_instr_cols][K] when lds_instr, else device atomics, global: partials
-// gpart[blk][K]). Frozen RHS contribute nothing.
+// [hcols][K] of columns [0, hcols), the others left to k_instr_tail, global:
+// partials gpart[blk][K]). Frozen RHS contribute nothing.
 template <typename T, typename Acc, int K, bool ATT = true, int NT = kBlock>
 __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const Acc* __restrict__ U,
                                                     Acc* __restrict__ Q,
                                                     const int64_t* __restrict__ wb,
-                                                    Acc* __restrict__ gpart, int lds_instr,
+                                                    Acc* __restrict__ gpart, int64_t hcols,
                                                     const Scalars* __restrict__ sc,
                                                     const int32_t* __restrict__ inv)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    Acc* lds = reinterpret_cast<Acc*>(smem_raw);
+    double* lds = reinterpret_cast<double*>(smem_raw);
     __shared__ Acc gred[K * (NT / kWave)];
     uint32_t live = 0;
 #pragma unroll
@@ -1354,11 +1401,8 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const Acc* __restrict_
     if (live == 0) return;
     const T* __restrict__ val = static_cast<const T*>(s.val);
     const int64_t m = s.m;
-    const int64_t ninst = s.n_instr_cols;
-    if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst * K; j += NT) lds[j] = (Acc)0;
-        __syncthreads();
-    }
+    for (int64_t j = threadIdx.x; j < hcols * K; j += NT) lds[j] = 0.0;
+    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave = (int64_t)blockIdx.x * (NT / kWave) + threadIdx.x / kWave;
     const int64_t rb = wb[wave], re = wb[wave + 1];
@@ -1408,11 +1452,11 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const Acc* __restrict_
 #pragma unroll
             for (int j = 0; j < kInstr; ++j) {
                 const Acc av = (Acc)a[kOffInstr + j];
+                if (ix[j] >= hcols) continue;
 #pragma unroll
                 for (int r = 0; r < K; ++r) {
                     if (!((live >> r) & 1u)) continue;
-                    if (lds_instr) atomicAdd(&lds[ix[j] * K + r], av * u[r]);
-                    else atomicAdd(&qins[ix[j] * K + r], av * u[r]);
+                    atomicAdd(&lds[ix[j] * K + r], (double)(av * u[r]));
                 }
             }
         }
@@ -1440,11 +1484,9 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const Acc* __restrict_
         for (int k = 0; k < NT / kWave; ++k) g += gred[threadIdx.x * (NT / kWave) + k];
         gpart[(int64_t)blockIdx.x * K + threadIdx.x] = g;
     }
-    if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst * K; j += NT) {
-            const Acc v = lds[j];
-            if (v != (Acc)0) atomicAdd(&qins[j], v);
-        }
+    for (int64_t j = threadIdx.x; j < hcols * K; j += NT) {
+        const double v = lds[j];
+        if (v != 0.0) atomicAdd(&qins[j], (Acc)v);
     }
 }
 
@@ -1469,8 +1511,8 @@ __global__ __launch_bounds__(kBlock) void k_interleave_att(const double* __restr
 // with its FP64 sum of squares per workgroup (part[blk][K]), and the same
 // registers scattered into Q += A^T U~ for the astrometric, instrumental and
 // global columns. Frozen RHS keep U and contribute nothing. Dynamic LDS: the
-// instrumental histogram [n_instr_cols][K] (lds_instr), then the
-// instrumental slice of VP (LDSX). In 1024-thread workgroups (128 registers
+// FP64 histogram [hcols][K] of instrumental columns [0, hcols) (the others
+// are left to k_instr_tail), then the instrumental slice of VP (LDSX). In 1024-thread workgroups (128 registers
 // per lane) a multi-RHS tile reduces its star segments chunk by chunk instead
 // of carrying 5K running sums.
 template <typename T, typename Acc, int K, int NT, bool LDSX, bool ATTI>
@@ -1478,7 +1520,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
                                                const Acc* __restrict__ X3, Acc* __restrict__ U,
                                                Acc* __restrict__ Q, const int64_t* __restrict__ wb,
                                                Acc* __restrict__ gpart, double* __restrict__ part,
-                                               int lds_instr, const Scalars* __restrict__ sc,
+                                               int64_t hcols, const Scalars* __restrict__ sc,
                                                const int32_t* __restrict__ inv)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1489,18 +1531,16 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
     const T* __restrict__ val = static_cast<const T*>(s.val);
     const int64_t m = s.m;
     const int64_t ninst = s.n_instr_cols;
-    Acc* hist = reinterpret_cast<Acc*>(smem_raw);
+    double* hist = reinterpret_cast<double*>(smem_raw);
     const Acc* xi = VP + s.instr_base * K;
-    if (lds_instr)
-        for (int64_t j = threadIdx.x; j < ninst * K; j += NT) hist[j] = (Acc)0;
+    for (int64_t j = threadIdx.x; j < hcols * K; j += NT) hist[j] = 0.0;
     if (LDSX) {
-        const int64_t off =
-            lds_instr ? (ninst * K * (int64_t)sizeof(Acc) + 15) & ~(int64_t)15 : 0;
+        const int64_t off = (hcols * K * 8 + 15) & ~(int64_t)15;
         Acc* xl = reinterpret_cast<Acc*>(smem_raw + off);
         for (int64_t j = threadIdx.x; j < ninst * K; j += NT) xl[j] = xi[j];
         xi = xl;
     }
-    if (lds_instr || LDSX) __syncthreads();
+    __syncthreads();
 
     Acc coef[K], xg[K];
 #pragma unroll
@@ -1575,12 +1615,12 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         if (ok) {
 #pragma unroll
             for (int j = 0; j < kInstr; ++j) {
+                if (ix[j] >= hcols) continue;
                 const Acc av = (Acc)a[kOffInstr + j];
 #pragma unroll
                 for (int r = 0; r < K; ++r) {
                     if (!((live >> r) & 1u)) continue;
-                    if (lds_instr) atomicAdd(&hist[ix[j] * K + r], av * d[r]);
-                    else atomicAdd(&qins[ix[j] * K + r], av * d[r]);
+                    atomicAdd(&hist[ix[j] * K + r], (double)(av * d[r]));
                 }
             }
         }
@@ -1623,11 +1663,9 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         gpart[(int64_t)blockIdx.x * K + threadIdx.x] = g;
         part[(int64_t)blockIdx.x * K + threadIdx.x] = q2;
     }
-    if (lds_instr) {
-        for (int64_t j = threadIdx.x; j < ninst * K; j += NT) {
-            const Acc v = hist[j];
-            if (v != (Acc)0) atomicAdd(&qins[j], v);
-        }
+    for (int64_t j = threadIdx.x; j < hcols * K; j += NT) {
+        const double v = hist[j];
+        if (v != 0.0) atomicAdd(&qins[j], (Acc)v);
     }
 }
 

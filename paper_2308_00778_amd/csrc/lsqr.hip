@@ -113,10 +113,9 @@ struct Path {
     Acc* q = nullptr;      // [n] aprod2 accumulator (zero between uses)
     Acc* gpart = nullptr;  // [nb2] global-column partials
     Acc* vp3 = nullptr;    // [3 n_dfa] attitude section of vp interleaved by axis
-    size_t lds = 0;        // dynamic LDS bytes of aprod2
-    int lds_instr = 0;
+    int64_t hcols = 0;     // instrumental columns kept in the row passes' LDS histogram
+    size_t lds = 0;        // dynamic LDS bytes of aprod2's main pass
     size_t lds_f = 0;      // dynamic LDS bytes of the fused pass
-    int f_instr = 0;       // fused pass: instrumental histogram in LDS
     int f_ldsx = 0;        // fused pass: instrumental slice of vp in LDS
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
@@ -217,6 +216,29 @@ inline int64_t att_span(const lsqr_handle* h) { return h->bwidth + kParAxis - 1;
 inline int64_t att_slices(const lsqr_handle* h) { return h->nbk * h->att_g; }
 
 // ------------------------------------------------------------ launch helpers
+// Instrumental columns a row pass keeps in its FP64 LDS histogram for K
+// right-hand sides; the remaining columns go to k_instr_tail windows.
+inline int64_t instr_hcols(const lsqr_handle* h, int64_t K)
+{
+    return std::min<int64_t>(h->sv.n_instr_cols, kLdsInstrBudget / (8 * K));
+}
+
+// Tail windows [hcols, n_instr_cols) of the instrumental part of Eq. (3), one
+// launch per window of kLdsInstrBudget bytes (nothing when hcols covers all).
+template <typename T, typename Acc, int K, bool SQUARE>
+void launch_instr_tail(const lsqr_handle* h, const Acc* U, const int32_t* inv, Acc* Q,
+                       int64_t hcols, const Scalars* sc, hipStream_t st)
+{
+    const int64_t ninst = h->sv.n_instr_cols;
+    const int64_t tw = std::max<int64_t>(1, kLdsInstrBudget / (8 * K));
+    for (int64_t c0 = hcols; c0 < ninst; c0 += tw) {
+        const int64_t c1 = std::min(ninst, c0 + tw);
+        hipLaunchKernelGGL((k_instr_tail<T, Acc, K, SQUARE, kAttBlock>), dim3(h->num_cu),
+                           dim3(kAttBlock), (size_t)((c1 - c0) * K * 8), st, h->sv, U, inv, Q, c0,
+                           c1, sc);
+    }
+}
+
 // aprod1 with the instrumental slice of x staged in LDS when it fits.
 // x3 (optional): interleaved attitude section of x, already written
 // (k_interleave_att).
@@ -259,20 +281,21 @@ void launch_fused(const lsqr_handle* h, Path<Acc>& P, hipStream_t st)
     const Acc* x3 = h->att_il ? (const Acc*)P.vp3 : nullptr;
     if (P.f_ldsx && x3)
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, true, true>), g, bm, P.lds_f, st, h->sv,
-                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
+                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.hcols,
                            h->sc, row_map(h));
     else if (P.f_ldsx)
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, true, false>), g, bm, P.lds_f, st, h->sv,
-                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
+                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.hcols,
                            h->sc, row_map(h));
     else if (x3)
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, false, true>), g, bm, P.lds_f, st, h->sv,
-                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
+                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.hcols,
                            h->sc, row_map(h));
     else
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, false, false>), g, bm, P.lds_f, st, h->sv,
-                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.f_instr,
+                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.hcols,
                            h->sc, row_map(h));
+    launch_instr_tail<T, Acc, 1, false>(h, P.u, row_map(h), P.q, P.hcols, h->sc, st);
 }
 
 // Attitude part of aprod2 in bucket order: per-workgroup LDS histograms of
@@ -295,23 +318,25 @@ void launch_att_pass(lsqr_handle* h, const Acc* ub, Acc* q, const Scalars* sc, h
 // ub, the same vector in bucket order.
 template <typename T, typename Acc>
 void launch_aprod2(lsqr_handle* h, const Acc* u, const int32_t* inv, Acc* q, Acc* gpart,
-                   size_t lds, int lds_instr, const Scalars* sc, hipStream_t st, const Acc* ub)
+                   int64_t hcols, const Scalars* sc, hipStream_t st, const Acc* ub)
 {
+    const size_t lds = (size_t)(hcols * 8);
     const dim3 g(h->nb2), bm(kBlock2), b(kBlock);
     const bool att = h->att_mode == 0;
     if (att && h->astro_scan)
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, true, kBlock2>), g, bm, lds, st, h->sv,
-                           u, q, h->wb, gpart, lds_instr, sc, inv);
+                           u, q, h->wb, gpart, hcols, sc, inv);
     else if (att)
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, false, kBlock2>), g, bm, lds, st,
-                           h->sv, u, q, h->wb, gpart, lds_instr, sc, inv);
+                           h->sv, u, q, h->wb, gpart, hcols, sc, inv);
     else if (h->astro_scan)
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, true, kBlock2>), g, bm, lds, st,
-                           h->sv, u, q, h->wb, gpart, lds_instr, sc, inv);
+                           h->sv, u, q, h->wb, gpart, hcols, sc, inv);
     else
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, false, false, kBlock2>), g, bm, lds, st,
-                           h->sv, u, q, h->wb, gpart, lds_instr, sc, inv);
+                           h->sv, u, q, h->wb, gpart, hcols, sc, inv);
     hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), b, 0, st, gpart, h->nb2, q + h->sv.glob_base, sc);
+    launch_instr_tail<T, Acc, 1, false>(h, u, inv, q, hcols, sc, st);
     if (!att) launch_att_pass<T, Acc>(h, ub, q, sc, st);
 }
 
@@ -341,8 +366,7 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
         if (ev) (void)hipEventRecord(ev[2], st);
-        launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.lds, P.lds_instr, h->sc, st,
-                              P.u);
+        launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.hcols, h->sc, st, P.u);
     }
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
@@ -363,7 +387,7 @@ void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st)
     hipLaunchKernelGGL(k_scalar_init_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, P.q, (Acc)0);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->v, 0.0);
-    launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.lds, P.lds_instr, h->sc, st, P.u);
+    launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.hcols, h->sc, st, P.u);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
                        h->sc, h->partc);
     hipLaunchKernelGGL(k_scalar_init_alpha, dim3(1), dim3(kBlock), 0, st, h->partc, h->nbc, h->sc);
@@ -381,17 +405,14 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     LSQR_TRY(dalloc(&P.q, n));
     LSQR_TRY(dalloc(&P.gpart, h->nb2));
     LSQR_TRY(dalloc(&P.vp3, (int64_t)kAxes * h->sv.n_dfa));
-    // LDS histograms are FP64 whatever Acc is (k_att_hist)
-    const int64_t hbytes = h->sv.n_instr_cols * 8;
+    // LDS histograms are FP64 whatever Acc is (k_att_hist); the fused pass
+    // keeps the histogram and, if both fit, the instrumental slice of vp
+    P.hcols = instr_hcols(h, 1);
+    P.lds = (size_t)(P.hcols * 8);
+    const int64_t hist = (P.hcols * 8 + 15) & ~(int64_t)15;
     const int64_t xbytes = h->sv.n_instr_cols * (int64_t)sizeof(Acc);
-    P.lds_instr = hbytes <= kLdsInstrBudget ? 1 : 0;
-    P.lds = P.lds_instr ? (size_t)hbytes : 0;
-    // fused pass: the histogram first (device atomics otherwise cost far
-    // more), then the slice of vp if both fit
-    P.f_instr = P.lds_instr;
-    const int64_t hist = P.f_instr ? (hbytes + 15) & ~(int64_t)15 : 0;
     P.f_ldsx = hist + xbytes <= kLdsInstrBudget ? 1 : 0;
-    P.lds_f = (size_t)(P.f_ldsx ? hist + xbytes : hist);
+    P.lds_f = (size_t)(P.f_ldsx ? hist + xbytes : P.hcols * 8);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n, P.q, (Acc)0);
     HIP_TRY(hipGetLastError());
     P.ready = true;
@@ -399,8 +420,10 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
 }
 
 // Attitude bucket geometry: the fewest buckets whose FP64 histogram fits in
-// LDS, or the requested count (raised if needed); workgroups per bucket so
-// that the attitude pass runs in one round of one workgroup per CU.
+// LDS, or the requested count (raised if needed). Workgroups per bucket G:
+// one workgroup fits per CU, so the pass takes ceil(nbk G / CUs) rounds of
+// 1/G of a bucket each; G minimises that (up to max(8, CUs / nbk), ties to
+// the smaller G, which keeps the slices to add up few).
 void att_geometry(lsqr_handle* h)
 {
     const int64_t nt = h->sv.n_dfa - kParAxis + 1;
@@ -410,7 +433,18 @@ void att_geometry(lsqr_handle* h)
     if (w > kAttWidthMax) w = kAttWidthMax;
     h->bwidth = w;
     h->nbk = cdiv(nt, w);
-    h->att_g = (int)std::max<int64_t>(1, h->num_cu / h->nbk);
+    const int64_t cu = std::max(1, h->num_cu);
+    const int64_t gmax = std::max<int64_t>(8, cu / h->nbk);
+    int64_t best = 1;
+    double best_cost = 1e300;
+    for (int64_t g = 1; g <= gmax; ++g) {
+        const double cost = (double)cdiv(h->nbk * g, cu) / (double)g;
+        if (cost < best_cost - 1e-12) {
+            best_cost = cost;
+            best = g;
+        }
+    }
+    h->att_g = (int)best;
 }
 
 // Attitude bucket order: a stable radix sort of the rows by t / W, the
@@ -666,13 +700,6 @@ void batch_free(lsqr_handle* h)
     B.kmax = 0;
 }
 
-template <int K>
-size_t batch_lds(const lsqr_handle* h, int* lds_instr)
-{
-    const int64_t bytes = h->sv.n_instr_cols * K * 8;
-    *lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
-    return *lds_instr ? (size_t)bytes : 0;
-}
 
 // Workgroup shape of the batched row passes over the star-aligned ranges: K <= 2
 // fits the 128 registers a lane has in a 1024-thread workgroup; wider tiles
@@ -709,40 +736,44 @@ template <typename T, int K>
 void batch_aprod2(lsqr_handle* h, hipStream_t st)
 {
     auto& B = h->batch;
-    int li = 0;
-    const size_t lds = batch_lds<K>(h, &li);
+    const int64_t hc = instr_hcols(h, K);
+    const size_t lds = (size_t)(hc * K * 8);
     constexpr int NT = batch_nt<K>();
     const int grid = batch_grid<K>(h);
     if (h->att_mode == 0)
         hipLaunchKernelGGL((batched::k_aprod2<T, double, K, true, NT>), dim3(grid), dim3(NT), lds,
-                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc,
+                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, hc, B.sc,
                            row_map(h));
     else
         hipLaunchKernelGGL((batched::k_aprod2<T, double, K, false, NT>), dim3(grid), dim3(NT), lds,
-                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, li, B.sc,
+                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, hc, B.sc,
                            row_map(h));
     hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
                        (const double*)B.gpart, grid, B.Q + h->sv.glob_base * K, B.sc);
+    launch_instr_tail<T, double, K, false>(h, (const double*)B.U, row_map(h), B.Q, hc, B.sc, st);
     if (h->att_mode != 0) batch_att_pass<T, K>(h, st);
 }
 
-// Fused pass of a K-tile: usable when its instrumental histogram fits in LDS
-// (device atomics for it would cost more than the second pass over A saves).
+// LDS of the fused pass of a K-tile: the histogram of the first hc
+// instrumental columns and, when every column is in it and both fit, the
+// instrumental slice of VP.
 template <int K>
-bool batch_fused_lds(const lsqr_handle* h, size_t* lds, int* ldsx)
+size_t batch_fused_lds(const lsqr_handle* h, int64_t* hc, int* ldsx)
 {
-    const int64_t bytes = h->sv.n_instr_cols * K * 8;
-    if (!use_fused(h) || bytes > kLdsInstrBudget) return false;
-    const int64_t hist = (bytes + 15) & ~(int64_t)15;
-    *ldsx = hist + bytes <= kLdsInstrBudget ? 1 : 0;
-    *lds = (size_t)(*ldsx ? hist + bytes : hist);
-    return true;
+    *hc = instr_hcols(h, K);
+    const int64_t hist = (*hc * K * 8 + 15) & ~(int64_t)15;
+    const int64_t xbytes = h->sv.n_instr_cols * K * 8;
+    *ldsx = hist + xbytes <= kLdsInstrBudget ? 1 : 0;
+    return (size_t)(*ldsx ? hist + xbytes : *hc * K * 8);
 }
 
 template <typename T, int K>
-void batch_fused(lsqr_handle* h, hipStream_t st, size_t lds, int ldsx)
+void batch_fused(lsqr_handle* h, hipStream_t st)
 {
     auto& B = h->batch;
+    int64_t hc = 0;
+    int ldsx = 0;
+    const size_t lds = batch_fused_lds<K>(h, &hc, &ldsx);
     constexpr int NT = fused_nt<K>();
     const dim3 g(fused_grid<K>(h)), bm(NT);
     const double* X3 = nullptr;
@@ -753,20 +784,21 @@ void batch_fused(lsqr_handle* h, hipStream_t st, size_t lds, int ldsx)
     }
     if (ldsx && X3)
         hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, true, true>), g, bm, lds, st, h->sv,
-                           (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1, B.sc,
+                           (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc, B.sc,
                            row_map(h));
     else if (ldsx)
         hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, true, false>), g, bm, lds, st,
-                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1,
+                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc,
                            B.sc, row_map(h));
     else if (X3)
         hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, false, true>), g, bm, lds, st,
-                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1,
+                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc,
                            B.sc, row_map(h));
     else
         hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, false, false>), g, bm, lds, st,
-                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, 1,
+                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc,
                            B.sc, row_map(h));
+    launch_instr_tail<T, double, K, false>(h, (const double*)B.U, row_map(h), B.Q, hc, B.sc, st);
 }
 
 template <typename T, int K>
@@ -774,11 +806,9 @@ void batch_iteration(lsqr_handle* h, hipStream_t st, hipEvent_t* ev)
 {
     auto& B = h->batch;
     const int64_t n = h->sv.n;
-    size_t lds = 0;
-    int ldsx = 0;
     if (ev) (void)hipEventRecord(ev[0], st);
-    if (batch_fused_lds<K>(h, &lds, &ldsx)) {
-        batch_fused<T, K>(h, st, lds, ldsx);
+    if (use_fused(h)) {
+        batch_fused<T, K>(h, st);
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL((batched::k_scalar_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1,
                            fused_grid<K>(h), B.sc);
@@ -1158,18 +1188,20 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     // 3. column scaling p from the column norms (squared-coefficient aprod2)
     double* ssq = nullptr;
     if ((st = dalloc(&ssq, n)) != LSQR_OK) return bail(st);
-    const int64_t bytes64 = s.n_instr_cols * 8;
-    const int lds_instr = bytes64 <= kLdsInstrBudget ? 1 : 0;
-    const size_t lds = lds_instr ? (size_t)bytes64 : 0;
+    const int64_t hc = instr_hcols(h, 1);
+    const size_t lds = (size_t)(hc * 8);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st0, n, ssq, 0.0);
-    if (h->value_type == LSQR_F64)
+    if (h->value_type == LSQR_F64) {
         hipLaunchKernelGGL((k_aprod2<double, double, double, true, true, true, kBlock2>),
                            dim3(h->nb2), dim3(kBlock2), lds, st0, s, (const double*)nullptr, ssq,
-                           h->wb, h->gpart_raw, lds_instr, (const Scalars*)nullptr);
-    else
+                           h->wb, h->gpart_raw, hc, (const Scalars*)nullptr);
+        launch_instr_tail<double, double, 1, true>(h, nullptr, nullptr, ssq, hc, nullptr, st0);
+    } else {
         hipLaunchKernelGGL((k_aprod2<float, double, double, true, true, true, kBlock2>),
                            dim3(h->nb2), dim3(kBlock2), lds, st0, s, (const double*)nullptr, ssq,
-                           h->wb, h->gpart_raw, lds_instr, (const Scalars*)nullptr);
+                           h->wb, h->gpart_raw, hc, (const Scalars*)nullptr);
+        launch_instr_tail<float, double, 1, true>(h, nullptr, nullptr, ssq, hc, nullptr, st0);
+    }
     hipLaunchKernelGGL((k_glob_sum<double>), dim3(1), dim3(kBlock), 0, st0, h->gpart_raw, h->nb2,
                        ssq + s.glob_base, (const Scalars*)nullptr);
     hipLaunchKernelGGL(k_make_p, dim3(h->nbc), dim3(kBlock), 0, st0, n, ssq, h->p, h->precondition);
@@ -1314,9 +1346,7 @@ lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y)
     LSQR_TRY(check_handle(h));
     if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
     LSQR_TRY(ensure_att(h));
-    const int64_t bytes = h->sv.n_instr_cols * 8;
-    const int lds_instr = bytes <= kLdsInstrBudget ? 1 : 0;
-    const size_t lds = lds_instr ? (size_t)bytes : 0;
+    const int64_t hc = instr_hcols(h, 1);
     // y in row order for the star-order pass; a copy in bucket order for the
     // attitude pass
     const double* yb = nullptr;
@@ -1328,10 +1358,10 @@ lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y)
         yb = h->us_raw;
     }
     if (h->value_type == LSQR_F64)
-        launch_aprod2<double, double>(h, y, nullptr, x, h->gpart_raw, lds, lds_instr, nullptr,
+        launch_aprod2<double, double>(h, y, nullptr, x, h->gpart_raw, hc, nullptr,
                                       h->user_stream, yb);
     else
-        launch_aprod2<float, double>(h, y, nullptr, x, h->gpart_raw, lds, lds_instr, nullptr,
+        launch_aprod2<float, double>(h, y, nullptr, x, h->gpart_raw, hc, nullptr,
                                      h->user_stream, yb);
     HIP_TRY(hipGetLastError());
     return LSQR_OK;

@@ -45,6 +45,10 @@ SPECS = {
     "few_rows": synth.tiny(seed=23, n_stars=3, obs=(10, 14), n_dfa=5, n_instr_cols=7),
     "wide_instr": synth.tiny(seed=24, n_stars=200, obs=(20, 60), n_dfa=300,
                              n_instr_cols=9000),  # instrumental histogram beyond the LDS budget
+    # 25,000 instrumental columns: beyond one FP64 LDS histogram (19,456), the
+    # rest in a tail window
+    "huge_instr": synth.tiny(seed=27, n_stars=300, obs=(30, 60), n_dfa=200,
+                             n_instr_cols=25000),
     # FP32 values, 8,997 attitude starts: the default layout has two buckets
     # of FP64 histograms (exact operators and fixed-iteration solves only:
     # more attitude columns than rows)
@@ -132,7 +136,7 @@ def test_aprod2_parity(torch_cuda, name, variant):
     assert np.all(np.abs(got - want) <= c * EPS * bound + 1e-300)
 
 
-@pytest.mark.parametrize("name", ["c0", "ragged", "wide_instr"])
+@pytest.mark.parametrize("name", ["c0", "ragged", "wide_instr", "huge_instr"])
 def test_precond_parity(torch_cuda, name):
     torch = torch_cuda
     S, o = system(name)
@@ -154,7 +158,7 @@ def _b(S, o, rhs=0):
 # differ by 2e-9 at k = 30 on the 36-unknown "one_star" system, 1e-15 at 15).
 @pytest.mark.parametrize("name,itn", [("c0", 50), ("c0", 200), ("ragged", 120),
                                        ("one_star", 15), ("few_rows", 15), ("wide_instr", 60),
-                                       ("wide_att_f32", 30)])
+                                       ("huge_instr", 30), ("wide_att_f32", 30)])
 @pytest.mark.parametrize("graph", [1, 0])
 def test_solve_fixed_iterations(torch_cuda, name, itn, graph):
     _solve_fixed(torch_cuda, name, itn, graph, VARIANTS[0])
