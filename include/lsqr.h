@@ -140,6 +140,12 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         (u~ = Abar v - alpha u is row-local, so every row's new
  *                         value is scattered as soon as it is computed), then
  *                         runs the attitude pass; 0: separate aprod1 and aprod2
+ *   LSQR_OPT_VARIANCE     1: lsqr_solve also accumulates the variance estimate of
+ *                         the unknowns, sum over iterations of (w/rho)^2 (Algorithm
+ *                         1, variances at the end of each iteration; Paige &
+ *                         Saunders' diagonal estimate of (Abar^T Abar)^-1), read
+ *                         back re-multiplied by p^2 with lsqr_get_variance;
+ *                         0 (default) off. One FP64 update per column per iteration
  *   LSQR_OPT_KTILE        batched solves: right-hand sides advanced together per
  *                         pass over A (1, 2, 4, 8), 0 (default) = autotune once
  *                         per handle
@@ -156,6 +162,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_ATT_BUCKETS 10
 #define LSQR_OPT_ATT_INTERLEAVE 11
 #define LSQR_OPT_FUSED 12
+#define LSQR_OPT_VARIANCE 13
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
 
 /* aprod mode 1, Eq. (2): y[m] += A x[n] with the raw (unscaled) A.
@@ -165,6 +172,14 @@ lsqr_status lsqr_aprod1(lsqr_handle* h, const double* x, double* y);
 
 /* aprod mode 2, Eq. (3): x[n] += A^T y[m] with the raw A. Same conventions. */
 lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y);
+
+/* Variance estimate of the unknowns from the last lsqr_solve run with
+ * LSQR_OPT_VARIANCE = 1: var_out[j] = p_j^2 sum_k (w_kj / rho_k)^2 (Algorithm 1,
+ * variances re-multiplied by p after the loop), FP64 [n], device. Standard
+ * errors follow as sqrt(var_j) times the residual standard deviation. Returns
+ * LSQR_E_STATE if the last solve did not compute it (option off, or a refined
+ * or batched solve since). Synchronous. */
+lsqr_status lsqr_get_variance(lsqr_handle* h, double* var_out);
 
 /* Copy the column scaling p (FP64 [n]) into p_out (device). */
 lsqr_status lsqr_get_precond(lsqr_handle* h, double* p_out);

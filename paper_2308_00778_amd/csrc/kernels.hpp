@@ -772,7 +772,9 @@ __global__ __launch_bounds__(kBlock) void k_col_a(int64_t n, const double* __res
 }
 
 // v = v~/alpha ; vp = p .* v ; y += t1 w ; w = v + t2 w ;
-// partials of ||w/rho||^2 and ||y||^2.
+// partials of ||w/rho||^2 and ||y||^2 ; var (optional) += (w/rho)^2, the
+// per-iteration variance term of Algorithm 1 (diagonal estimate of
+// (Abar^T Abar)^-1, rescaled by p^2 after the loop).
 template <typename VP>
 __global__ __launch_bounds__(kBlock) void k_col_b(int64_t n, const double* __restrict__ p,
                                                    double* __restrict__ v,
@@ -780,7 +782,8 @@ __global__ __launch_bounds__(kBlock) void k_col_b(int64_t n, const double* __res
                                                    double* __restrict__ y, VP* __restrict__ vp,
                                                    const Scalars* __restrict__ sc,
                                                    double* __restrict__ part_dd,
-                                                   double* __restrict__ part_xx)
+                                                   double* __restrict__ part_xx,
+                                                   double* __restrict__ var)
 {
     __shared__ double red[kWavesPerBlock];
     if (sc->done) return;
@@ -795,6 +798,7 @@ __global__ __launch_bounds__(kBlock) void k_col_b(int64_t n, const double* __res
         const double wj = w[j];
         const double dk = wj * ir;
         dd += dk * dk;
+        if (var) var[j] += dk * dk;
         const double yj = y[j] + t1 * wj;
         y[j] = yj;
         xx += yj * yj;
@@ -852,6 +856,18 @@ __global__ __launch_bounds__(kBlock) void k_fill(int64_t n, V* __restrict__ a, V
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * kBlock)
         a[j] = value;
+}
+
+// out = p^2 .* var: the variance estimate re-multiplied by the column
+// scaling (Algorithm 1 after the loop)
+__global__ __launch_bounds__(kBlock) void k_unprecond_var(int64_t n,
+                                                           const double* __restrict__ p,
+                                                           const double* __restrict__ var,
+                                                           double* __restrict__ out)
+{
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * kBlock)
+        out[j] = p[j] * p[j] * var[j];
 }
 
 // x = p .* y (un-preconditioning, Algorithm 1 after the loop)

@@ -27,6 +27,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -170,6 +171,11 @@ struct lsqr_handle {
     double* us_raw = nullptr;     // [m] lsqr_aprod2's row vector in bucket order
     double* x3_raw = nullptr;     // interleaved attitude section of lsqr_aprod1's x
     bool att_ready = false;
+
+    // variance estimate of the last lsqr_solve (LSQR_OPT_VARIANCE)
+    double* var = nullptr;        // [n] sum of (w/rho)^2 in the scaled space
+    int var_on = 0;               // accumulate during solves
+    int var_valid = 0;            // var belongs to the last solve
 
     // batched right-hand sides (tile buffers for the largest K, reused per tile)
     struct Batch {
@@ -373,7 +379,8 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
                        h->sc, h->partc);
     hipLaunchKernelGGL(k_scalar_alpha, dim3(1), dim3(kBlock), 0, st, h->partc, h->nbc, h->sc);
     hipLaunchKernelGGL((k_col_b<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, h->v, h->w,
-                       h->y, P.vp, h->sc, h->partdd, h->partxx);
+                       h->y, P.vp, h->sc, h->partdd, h->partxx,
+                       (std::is_same<Acc, double>::value && h->var_on) ? h->var : nullptr);
     hipLaunchKernelGGL(k_scalar_stop, dim3(1), dim3(kBlock), 0, st, h->partdd, h->partxx, h->nbc,
                        h->sc);
 }
@@ -640,6 +647,12 @@ lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_l
         h->n1 = h->n2 = 0;
     }
     LSQR_TRY(upload_controls(h, itn_limit, atol, btol));
+    h->var_valid = 0;
+    if (h->var_on) {
+        if (!h->var) LSQR_TRY(dalloc(&h->var, n));
+        hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n, h->var,
+                           0.0);
+    }
     hipLaunchKernelGGL((k_copy_ssq<double>), dim3(h->nb1), dim3(kBlock), 0, h->stream, m, b, P.u,
                        h->part1, row_map(h));
     launch_init<T, double>(h, P, h->stream);
@@ -650,6 +663,7 @@ lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_l
     HIP_TRY(hipGetLastError());
     LSQR_TRY(read_scalars(h));
     fill_info(h, info, h->sc_host->itn, 0, h->sc_host->bnorm);
+    h->var_valid = h->var_on;
     return LSQR_OK;
 }
 
@@ -1229,6 +1243,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h)
     dfree(h->bstart);
     dfree(h->S2);
     dfree(h->us_raw);
+    dfree(h->var);
     dfree(h->x3_raw);
     if (h->att_sorted) (void)hipFree(h->att_sorted);
     h->att_sorted = nullptr;
@@ -1312,6 +1327,17 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         h->att_buckets = (int64_t)value;
         return LSQR_OK;
     }
+    case LSQR_OPT_VARIANCE: {
+        const int v = value != 0.0 ? 1 : 0;
+        if (h->var_on != v) {  // captured graphs bake in the variance pointer
+            if (h->p64.graph) (void)hipGraphExecDestroy(h->p64.graph);
+            if (h->p32.graph) (void)hipGraphExecDestroy(h->p32.graph);
+            h->p64.graph = nullptr;
+            h->p32.graph = nullptr;
+        }
+        h->var_on = v;
+        return LSQR_OK;
+    }
     case LSQR_OPT_OUTER_TOL:
         if (!(value >= 0.0)) return fail(LSQR_E_INVALID, "outer tolerance must be >= 0");
         h->outer_tol = value;
@@ -1376,6 +1402,19 @@ lsqr_status lsqr_get_precond(lsqr_handle* h, double* p_out)
     return LSQR_OK;
 }
 
+lsqr_status lsqr_get_variance(lsqr_handle* h, double* var_out)
+{
+    LSQR_TRY(check_handle(h));
+    if (!var_out) return fail(LSQR_E_INVALID, "null output");
+    if (!h->var_valid || !h->var)
+        return fail(LSQR_E_STATE, "no variance: run lsqr_solve with LSQR_OPT_VARIANCE = 1");
+    hipLaunchKernelGGL(k_unprecond_var, dim3(h->nbc), dim3(kBlock), 0, h->stream, h->sv.n, h->p,
+                       (const double*)h->var, var_out);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LSQR_OK;
+}
+
 lsqr_status lsqr_num_cols(lsqr_handle* h, int64_t* n_out)
 {
     if (!h || !n_out) return fail(LSQR_E_INVALID, "null argument");
@@ -1409,6 +1448,7 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
         return fail(LSQR_E_INVALID, "itn_limit >= 0 and outer_limit >= 1 required");
     if (!(atol >= 0.0) || !(btol >= 0.0)) return fail(LSQR_E_INVALID, "atol, btol must be >= 0");
     HIP_TRY(hipStreamSynchronize(h->user_stream));
+    h->var_valid = 0;
     LSQR_TRY(ensure_att(h));
     LSQR_TRY((prepare_path<float, float>(h, h->p32)));
     Path<float>& P = h->p32;
@@ -1471,6 +1511,7 @@ lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32
     if (itn_limit < 0) return fail(LSQR_E_INVALID, "itn_limit must be >= 0");
     if (!(atol >= 0.0) || !(btol >= 0.0)) return fail(LSQR_E_INVALID, "atol, btol must be >= 0");
     HIP_TRY(hipStreamSynchronize(h->user_stream));
+    h->var_valid = 0;
     LSQR_TRY(ensure_att(h));
     if (h->value_type == LSQR_F64)
         LSQR_TRY(solve_batched<double>(h, B, X, k, itn_limit, atol, btol, infos));

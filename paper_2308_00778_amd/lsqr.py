@@ -24,10 +24,11 @@ LSQR_F32 = 1
 
 OPTIONS = {"conlim": 1, "tests": 2, "chunk": 3, "graph": 4, "profile": 5, "outer_tol": 6,
            "att_mode": 7, "astro_scan": 8, "ktile": 9, "att_buckets": 10,
-           "att_interleave": 11, "fused": 12}
+           "att_interleave": 11, "fused": 12, "variance": 13}
 
 SYMBOLS = ("lsqr_create", "lsqr_destroy", "lsqr_set_option", "lsqr_aprod1", "lsqr_aprod2",
-           "lsqr_get_precond", "lsqr_num_cols", "lsqr_solve", "lsqr_solve_refined",
+           "lsqr_get_precond", "lsqr_get_variance", "lsqr_num_cols", "lsqr_solve",
+           "lsqr_solve_refined",
            "lsqr_solve_batched", "lsqr_batch_tuning", "lsqr_kernel_times", "lsqr_last_error")
 
 
@@ -90,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "lsqr_aprod1": ([H, P, P], I32),
         "lsqr_aprod2": ([H, P, P], I32),
         "lsqr_get_precond": ([H, P], I32),
+        "lsqr_get_variance": ([H, P], I32),
         "lsqr_num_cols": ([H, ctypes.POINTER(I64)], I32),
         "lsqr_solve": ([H, P, P, I32, F64, F64, ctypes.POINTER(_Info)], I32),
         "lsqr_solve_refined": ([H, P, P, I32, F64, F64, I32, ctypes.POINTER(_Info)], I32),
@@ -218,6 +220,14 @@ class LsqrSystem:
         p = torch.empty(self.n, dtype=torch.float64, device=self.device)
         _check(_lib.lsqr_get_precond(self._h, _dev_ptr(p, torch.float64, (self.n,), "p")))
         return p
+
+    def variance(self):
+        """p^2 .* sum (w/rho)^2 of the last solve run with option variance = 1."""
+        import torch
+
+        var = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _check(_lib.lsqr_get_variance(self._h, _dev_ptr(var, torch.float64, (self.n,), "var")))
+        return var
 
     @staticmethod
     def _info(ci: _Info) -> Info:

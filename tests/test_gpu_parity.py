@@ -217,6 +217,41 @@ def _solve_fixed(torch_cuda, name, itn, graph, variant, interleave=1, fused=1):
         assert abs(a - r) <= tol * abs(r), (k, a, r)
 
 
+# Iteration counts before convergence: the variance sums (w/rho)^2 over all
+# iterations, and past convergence those terms depend on rounding like the
+# anorm/acond estimates. On "ragged" the oracle and SciPy's LSQR (calc_var)
+# differ by 1.5e-13 at 20 iterations, 3.4e-11 at 30, 2.8e-9 at 40 and 3.6% at
+# 60, while their iterates x still agree.
+@pytest.mark.parametrize("name,itn", [("c0", 50), ("ragged", 25), ("huge_instr", 30)])
+def test_variance_parity(torch_cuda, name, itn):
+    # Algorithm 1's per-iteration variance term, re-multiplied by p^2
+    torch = torch_cuda
+    from paper_2308_00778_amd import LSQR_E_STATE, LsqrError
+
+    S, o = system(name)
+    b = _b(S, o)
+    x_ref, _, var_ref = o.lsqr(b, itn, atol=0.0, btol=0.0, conlim=0.0, tests=False,
+                               want_var=True)
+    say(f"variance parity: {name} itn={itn}")
+    g = gpu_system(torch, S)
+    g.set_option("tests", 0)
+    with pytest.raises(LsqrError) as ei:  # nothing computed yet
+        g.variance()
+    assert ei.value.status == LSQR_E_STATE
+    g.set_option("variance", 1)
+    x, info = g.solve(torch.from_numpy(b).cuda(), itn, atol=0.0, btol=0.0)
+    var = g.variance().cpu().numpy()
+    xg = x.cpu().numpy()
+    g.set_option("variance", 0)
+    g.solve(torch.from_numpy(b).cuda(), 5, atol=0.0, btol=0.0)
+    with pytest.raises(LsqrError):  # the last solve did not compute it
+        g.variance()
+    g.close()
+    assert rel_inf(xg, x_ref) <= 1e-10
+    assert np.all(var >= 0.0)
+    assert rel_inf(var, var_ref) <= 1e-10
+
+
 def test_solve_stopping_rules(torch_cuda):
     torch = torch_cuda
     S, o = system("c0")
