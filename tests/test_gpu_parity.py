@@ -273,6 +273,55 @@ def test_solve_stopping_rules(torch_cuda):
     assert np.linalg.norm(p * o.aprod2(r)) <= 1e-9 * info.anorm * np.linalg.norm(r)
 
 
+def test_repeated_solves_reuse_graphs(torch_cuda):
+    # One handle, three solves: the captured iteration graph and the workspaces
+    # are reused across right-hand sides and iteration counts.
+    torch = torch_cuda
+    S, o = system("c0")
+    b1 = _b(S, o, rhs=0)
+    b2 = _b(S, o, rhs=1)
+    say("repeated solves on one handle: c0")
+    g = gpu_system(torch, S)
+    g.set_option("tests", 0)
+    g.set_option("chunk", 5)
+    runs = [(b1, 40), (b2, 33), (b1, 40), (b2, 12)]
+    xs = []
+    for b, itn in runs:
+        x, info = g.solve(torch.from_numpy(b).cuda(), itn, atol=0.0, btol=0.0)
+        assert info.itn == itn
+        xs.append(x.cpu().numpy())
+    g.close()
+    for (b, itn), xg in zip(runs, xs):
+        x_ref, _ = o.lsqr(b, itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+        assert rel_inf(xg, x_ref) <= 1e-10
+    assert rel_inf(xs[2], xs[0]) <= 1e-13  # same solve again: rounding order only
+
+
+def test_option_errors(torch_cuda):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LSQR_E_INVALID, LSQR_E_STATE, LsqrError
+
+    S, o = system("few_rows")
+    say("option validation: few_rows")
+    g = gpu_system(torch, S)
+    bad = [("att_mode", 2), ("ktile", 3), ("chunk", 0), ("att_buckets", -1), ("outer_tol", -1.0)]
+    for name, value in bad:
+        with pytest.raises(LsqrError) as ei:
+            g.set_option(name, value)
+        assert ei.value.status == LSQR_E_INVALID, name
+    g.set_option("att_buckets", 2)
+    g.set_option("tests", 0)
+    b = _b(S, o)
+    g.solve(torch.from_numpy(b).cuda(), 5, atol=0.0, btol=0.0)
+    with pytest.raises(LsqrError) as ei:  # the bucket order exists now
+        g.set_option("att_buckets", 3)
+    assert ei.value.status == LSQR_E_STATE
+    with pytest.raises(LsqrError) as ei:  # refinement needs FP32-stored values
+        g.solve_refined(torch.from_numpy(b).cuda(), 5, atol=1e-6, btol=1e-6, outer_limit=2)
+    assert ei.value.status == LSQR_E_STATE
+    g.close()
+
+
 def test_zero_rhs_and_zero_iterations(torch_cuda):
     torch = torch_cuda
     S, o = system("ragged")
