@@ -5,19 +5,21 @@
  * AVU-GSR solver (Cesare et al., "The MPI + CUDA Gaia AVU-GSR Parallel Solver
  * Toward Next-generation Exascale Infrastructures", Eq. (1)) in the least
  * squares sense with LSQR (Paige & Saunders, ACM TOMS 8, 1982), entirely on
- * one GPU. Each row of A is one observation and holds exactly
+ * one GPU. Each row of A is one observation and holds
  *     n_astro = 5 astrometric coefficients  (columns n_astro*star + j),
  *     n_axes * n_par_axis = 3 * 4 attitude coefficients (axis a, parameter q:
  *         column att_base + a*n_dfa + att_start + q, one att_start per row
  *         shared by the three axes),
  *     n_instr = 6 instrumental coefficients (columns instr_base + instr_idx),
- *     n_glob  = 1 global coefficient (column glob_base),
+ *     n_glob  = 1 global coefficient (column glob_base + g),
  * the row layout of the paper's Sect. 2 (dense per-row coefficient array A_d
- * with index arrays M_i and I_c). Columns are ordered
+ * with index arrays M_i and I_c); subset layouts (fewer astrometric or
+ * instrumental coefficients, no attitude section, up to 5 global columns)
+ * are accepted as well. Columns are ordered
  *     astrometric [0, att_base) | attitude [att_base, instr_base) |
  *     instrumental [instr_base, glob_base) | global [glob_base, n)
- * with att_base = 5*n_stars, instr_base = att_base + 3*n_dfa,
- * glob_base = instr_base + n_instr_cols, n = glob_base + 1.
+ * with att_base = n_astro*n_stars, instr_base = att_base + n_axes*n_dfa,
+ * glob_base = instr_base + n_instr_cols, n = glob_base + n_glob.
  *
  * All array arguments are DEVICE pointers (memory of the GPU the handle was
  * created on) unless stated otherwise. lsqr_aprod1/lsqr_aprod2 run
@@ -52,23 +54,31 @@ typedef int32_t lsqr_status;
  * and unchanged until lsqr_destroy. */
 typedef struct lsqr_system {
     int64_t n_rows;       /* m, number of observation rows (> 0)                 */
-    int64_t n_stars;      /* stars; astrometric columns = 5 * n_stars             */
-    int32_t n_astro;      /* must be 5                                            */
-    int32_t n_axes;       /* must be 3                                            */
-    int32_t n_par_axis;   /* must be 4                                            */
-    int32_t n_instr;      /* must be 6                                            */
+    int64_t n_stars;      /* stars; astrometric columns = n_astro * n_stars       */
+    int32_t n_astro;      /* 0..5 astrometric coefficients per row (5)            */
+    int32_t n_axes;       /* 3 attitude axes, or 0: no attitude section           */
+    int32_t n_par_axis;   /* 4 attitude parameters per axis (ignored if no axes)  */
+    int32_t n_instr;      /* 0..6 instrumental coefficients per row (6)           */
     int64_t n_dfa;        /* attitude degrees of freedom per axis (>= n_par_axis) */
-    int64_t n_instr_cols; /* instrumental columns (> 0)                           */
-    int32_t n_glob;       /* must be 1                                            */
+    int64_t n_instr_cols; /* instrumental columns (>= n_instr)                    */
+    int32_t n_glob;       /* 0..5 global coefficients per row (1)                 */
     int32_t value_type;   /* LSQR_F64 or LSQR_F32                                 */
     int32_t precondition; /* 1: scale columns to unit norm (Sect. 2), 0: no       */
     int32_t reserved;
-    /* [24][n_rows] structure of arrays, row i of section c at c*n_rows + i,
-     * section order astro(5) | att axis0(4) axis1(4) axis2(4) | instr(6) | glob */
+    /* [n_par][n_rows] structure of arrays, row i of coefficient c at
+     * c*n_rows + i, coefficient order astro(n_astro) | att axis0(4) axis1(4)
+     * axis2(4) (if n_axes) | instr(n_instr) | glob(n_glob); n_par = 24 for the
+     * full layout. Column order astro | att | instr | glob (Algorithms 2-3):
+     * astro n_astro*star + j, att n_astro*n_stars + axis*n_dfa + t + q, instr
+     * after the n_axes*n_dfa attitude columns, glob after the n_instr_cols
+     * instrumental columns. Layouts other than 5 + 3x4 + 6 + 1 run separate
+     * aprod1/aprod2 passes with run-time section sizes and no batched solve. */
     const void* values;
     const int64_t* star_of_row; /* [n_rows], non-decreasing, in [0, n_stars)      */
-    const int64_t* att_start;   /* [n_rows], in [0, n_dfa - n_par_axis]           */
-    const int32_t* instr_idx;   /* [6][n_rows] SoA, in [0, n_instr_cols)          */
+    const int64_t* att_start;   /* [n_rows], in [0, n_dfa - n_par_axis]; NULL ok
+                                   without attitude section                       */
+    const int32_t* instr_idx;   /* [n_instr][n_rows] SoA, in [0, n_instr_cols);
+                                   NULL ok when n_instr = 0                       */
     void* stream;               /* hipStream_t for all work, NULL = null stream   */
 } lsqr_system;
 

@@ -60,6 +60,10 @@ struct SysView {
     int64_t att_base;
     int64_t instr_base;
     int64_t glob_base;
+    // section sizes and value-row offsets (general layouts; the full layout
+    // is 5, 12, 6, 1 at offsets 5, 17, 23)
+    int32_t na, natt, ni, ng;
+    int32_t off_att, off_instr, off_glob;
 };
 
 // LSQR state kept on the device so that a whole iteration runs without a
@@ -686,6 +690,7 @@ __global__ __launch_bounds__(NT) void k_instr_tail(SysView s, const Acc* __restr
                                                     Acc* __restrict__ Q, int64_t c0, int64_t c1,
                                                     const Scalars* __restrict__ sc)
 {
+    const int ni = s.ni, oins = s.off_instr;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* hist = reinterpret_cast<double*>(smem_raw);
     uint32_t live = 0;
@@ -703,8 +708,8 @@ __global__ __launch_bounds__(NT) void k_instr_tail(SysView s, const Acc* __restr
         T a[kInstr];
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) {
-            ix[j] = ldnt(&s.instr[j * m + i]);
-            a[j] = ldnt(&val[(kOffInstr + j) * m + i]);
+            ix[j] = j < ni ? ldnt(&s.instr[j * m + i]) : -1;
+            a[j] = j < ni ? ldnt(&val[(oins + j) * m + i]) : (T)0;
         }
         double u[K];
         if (!SQUARE) {
@@ -729,6 +734,170 @@ __global__ __launch_bounds__(NT) void k_instr_tail(SysView s, const Acc* __restr
     for (int64_t e = threadIdx.x; e < w * K; e += NT) {
         const double v = hist[e];
         if (v != 0.0) atomicAdd(&qins[e], (Acc)v);
+    }
+}
+
+// --------------------------------------------------------- general layouts
+// Rows whose sections differ from 5 + 3 x 4 + 6 + 1 (sections absent, fewer
+// astrometric or instrumental coefficients, up to kGlobMax global columns):
+// section sizes and value-row offsets come from the system view at run time,
+// aprod1 and aprod2 run as separate passes, and the attitude columns go
+// through the bucket-order pass (or device atomics) as in the full layout.
+constexpr int kGlobMax = 5;
+
+// Eq. (2) for a general layout; modes, y placement (inv) and part as k_aprod1.
+template <typename T, typename Acc, typename VX, typename VY, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gen_aprod1(SysView s, const VX* __restrict__ x,
+                                                        VY* __restrict__ y,
+                                                        const double* __restrict__ b,
+                                                        const Scalars* __restrict__ sc,
+                                                        double* __restrict__ part,
+                                                        const int32_t* __restrict__ inv)
+{
+    __shared__ double red[kWavesPerBlock];
+    if (MODE == A1_LSQR && sc->done) return;
+    const T* __restrict__ val = static_cast<const T*>(s.val);
+    const int64_t m = s.m;
+    const Acc coef = (MODE == A1_LSQR) ? (Acc)sc->coef_u : (Acc)0;
+    double ssq = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kBlock) {
+        Acc d = (Acc)0;
+        if (s.na > 0) {
+            const VX* xa = x + (int64_t)s.na * ldnt(&s.star[i]);
+            for (int j = 0; j < s.na; ++j) d += (Acc)ldnt(&val[j * m + i]) * (Acc)xa[j];
+        }
+        if (s.natt > 0) {
+            const int64_t t = ldnt(&s.att[i]);
+#pragma unroll
+            for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+                for (int qq = 0; qq < kParAxis; ++qq)
+                    d += (Acc)ldnt(&val[(s.off_att + ax * kParAxis + qq) * m + i]) *
+                         (Acc)x[s.att_base + ax * s.n_dfa + t + qq];
+        }
+        for (int j = 0; j < s.ni; ++j)
+            d += (Acc)ldnt(&val[(s.off_instr + j) * m + i]) *
+                 (Acc)x[s.instr_base + ldnt(&s.instr[j * m + i])];
+        for (int g = 0; g < s.ng; ++g)
+            d += (Acc)ldnt(&val[(s.off_glob + g) * m + i]) * (Acc)x[s.glob_base + g];
+        if (MODE == A1_ACCUM) {
+            y[i] = (VY)((Acc)y[i] + d);
+        } else {
+            const int64_t p = inv ? (int64_t)ldnt(&inv[i]) : i;
+            const VY nv = MODE == A1_LSQR ? (VY)(d - coef * (Acc)y[p]) : (VY)((Acc)b[i] - d);
+            y[p] = nv;
+            ssq += (double)nv * (double)nv;
+        }
+    }
+    if (MODE != A1_ACCUM) {
+        const double r = block_sum(ssq, red);
+        if (threadIdx.x == 0) part[blockIdx.x] = r;
+    }
+}
+
+// Eq. (3) (SQUARE: squared coefficients, the column norms) for a general
+// layout over the star-aligned wave ranges: astrometric per-star segments,
+// attitude by device atomics when ATT (else left to the bucket-order pass),
+// instrumental columns [0, hcols) in an FP64 LDS histogram (the rest to
+// k_instr_tail), global columns as per-workgroup partials
+// gpart[blockIdx.x * kGlobMax + g].
+template <typename T, typename Acc, typename VU, bool SQUARE, bool ATT>
+__global__ __launch_bounds__(kBlock) void k_gen_aprod2(SysView s, const VU* __restrict__ u,
+                                                        Acc* __restrict__ q,
+                                                        const int64_t* __restrict__ wb,
+                                                        Acc* __restrict__ gpart, int64_t hcols,
+                                                        const Scalars* __restrict__ sc,
+                                                        const int32_t* __restrict__ inv)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double* lds = reinterpret_cast<double*>(smem_raw);
+    __shared__ Acc gred[kGlobMax][kWavesPerBlock];
+    if (sc != nullptr && (sc->done || sc->beta_zero)) return;
+    const T* __restrict__ val = static_cast<const T*>(s.val);
+    const int64_t m = s.m;
+    const int na = s.na, ni = s.ni, ng = s.ng;
+    for (int64_t j = threadIdx.x; j < hcols; j += kBlock) lds[j] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t rb = wb[wave], re = wb[wave + 1];
+    Acc gsum[kGlobMax];
+#pragma unroll
+    for (int g = 0; g < kGlobMax; ++g) gsum[g] = (Acc)0;
+    SegAcc<Acc, kAstro> seg;
+    auto astro_emit = [q, na](int64_t star, const Acc (&tot)[kAstro]) {
+        for (int j = 0; j < na; ++j) q[(int64_t)na * star + j] += tot[j];
+    };
+    for (int64_t r0 = rb < re ? (rb & ~(int64_t)(kWave - 1)) : re; r0 < re; r0 += kWave) {
+        const int64_t i = r0 + lane;
+        const bool ok = i >= rb && i < re;
+        const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
+        Acc ui = (Acc)0;
+        if (!SQUARE) ui = ok ? (Acc)u[inv ? (int64_t)ldnt(&inv[ic]) : ic] : (Acc)0;
+        auto contrib = [&](T a) -> Acc {
+            return SQUARE ? (ok ? (Acc)a * (Acc)a : (Acc)0) : (Acc)a * ui;
+        };
+        if (na > 0) {  // uniform: seg_chunk is collective
+            const int64_t st = i < re ? ldnt(&s.star[ic]) : kNoStar;
+            Acc pa[kAstro];
+#pragma unroll
+            for (int j = 0; j < kAstro; ++j)
+                pa[j] = j < na ? contrib(ldnt(&val[j * m + ic])) : (Acc)0;
+            seg_chunk(seg, st, pa, lane, astro_emit);
+        }
+        if (ATT && s.natt > 0 && ok) {
+            const int64_t t = ldnt(&s.att[ic]);
+#pragma unroll
+            for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+                for (int qq = 0; qq < kParAxis; ++qq)
+                    atomicAdd(&q[s.att_base + ax * s.n_dfa + t + qq],
+                              contrib(ldnt(&val[(s.off_att + ax * kParAxis + qq) * m + ic])));
+        }
+        for (int j = 0; j < ni; ++j) {
+            const int32_t ix = ldnt(&s.instr[j * m + ic]);
+            const Acc c = contrib(ldnt(&val[(s.off_instr + j) * m + ic]));
+            if (ok && ix < hcols) atomicAdd(&lds[ix], (double)c);
+        }
+        for (int g = 0; g < ng; ++g) {
+            const Acc c = contrib(ldnt(&val[(s.off_glob + g) * m + ic]));
+            gsum[g] += ok ? c : (Acc)0;
+        }
+    }
+    if (na > 0) seg_finish(seg, lane, astro_emit);
+#pragma unroll
+    for (int g = 0; g < kGlobMax; ++g) {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) gsum[g] += __shfl_down(gsum[g], off);
+        if (lane == 0) gred[g][threadIdx.x / kWave] = gsum[g];
+    }
+    __syncthreads();
+    if (threadIdx.x < kGlobMax) {
+        Acc t = (Acc)0;
+        for (int k = 0; k < kWavesPerBlock; ++k) t += gred[threadIdx.x][k];
+        gpart[(int64_t)blockIdx.x * kGlobMax + threadIdx.x] = t;
+    }
+    Acc* __restrict__ qins = q + s.instr_base;
+    for (int64_t j = threadIdx.x; j < hcols; j += kBlock) {
+        const double v = lds[j];
+        if (v != 0.0) atomicAdd(&qins[j], (Acc)v);
+    }
+}
+
+// q[glob_base + g] += sum over workgroups of gpart[blk * kGlobMax + g], g < ng.
+template <typename Acc>
+__global__ __launch_bounds__(kBlock) void k_gen_glob_sum(const Acc* __restrict__ gpart, int nblk,
+                                                          int ng, Acc* __restrict__ qglob,
+                                                          const Scalars* __restrict__ sc)
+{
+    __shared__ double red[kWavesPerBlock];
+    if (sc != nullptr && (sc->done || sc->beta_zero)) return;
+    for (int g = 0; g < ng; ++g) {
+        double v = 0.0;
+        for (int k = threadIdx.x; k < nblk; k += kBlock) v += (double)gpart[(int64_t)k * kGlobMax + g];
+        const double r = block_sum(v, red);
+        if (threadIdx.x == 0) qglob[g] = (Acc)((double)qglob[g] + r);
     }
 }
 
@@ -1065,10 +1234,11 @@ __global__ __launch_bounds__(kBlock) void k_validate(SysView s, int32_t* __restr
         const int64_t st = s.star[i];
         if (st < 0 || st >= s.n_stars) bad |= 1;
         if (i > 0 && s.star[i - 1] > st) bad |= 2;
-        const int64_t t = s.att[i];
-        if (t < 0 || t > s.n_dfa - kParAxis) bad |= 4;
-#pragma unroll
-        for (int j = 0; j < kInstr; ++j) {
+        if (s.natt > 0) {
+            const int64_t t = s.att[i];
+            if (t < 0 || t > s.n_dfa - kParAxis) bad |= 4;
+        }
+        for (int j = 0; j < s.ni; ++j) {
             const int32_t c = s.instr[j * s.m + i];
             if (c < 0 || (int64_t)c >= s.n_instr_cols) bad |= 8;
         }
@@ -1161,13 +1331,14 @@ __global__ __launch_bounds__(kBlock) void k_gather_perm(const V* __restrict__ u,
         us[k] = u[perm[k]];
 }
 
-// att_sorted[c][k] = values[kOffAtt + c][perm[k]], c < 12 ;
+// att_sorted[c][k] = values[off_att + c][perm[k]], c < 12 ;
 // tloc[k] = t of row perm[k] minus its bucket's first start.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val,
                                                         const int64_t* __restrict__ att, int64_t m,
                                                         const int32_t* __restrict__ perm,
-                                                        int64_t width, T* __restrict__ att_sorted,
+                                                        int64_t width, int off_att,
+                                                        T* __restrict__ att_sorted,
                                                         int32_t* __restrict__ tloc)
 {
     constexpr int kAtt = kAxes * kParAxis;
@@ -1175,7 +1346,7 @@ __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val
          k += (int64_t)gridDim.x * kBlock) {
         const int64_t i = perm[k];
 #pragma unroll
-        for (int c = 0; c < kAtt; ++c) att_sorted[c * m + k] = val[(kOffAtt + c) * m + i];
+        for (int c = 0; c < kAtt; ++c) att_sorted[c * m + k] = val[(off_att + c) * m + i];
         const int64_t t = att[i];
         tloc[k] = (int32_t)(t - (t / width) * width);
     }

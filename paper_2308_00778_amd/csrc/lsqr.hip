@@ -127,6 +127,7 @@ struct Path {
 
 struct lsqr_handle {
     SysView sv{};
+    int generic = 0;  // row layout other than 5 + 3x4 + 6 + 1 (k_gen_* kernels)
     int value_type = LSQR_F64;
     int precondition = 1;
     int device = 0;
@@ -213,9 +214,11 @@ struct lsqr_handle {
 namespace {
 
 // Placement of the solver's row vector: bucket order in attitude mode 1.
+inline bool att_pass_on(const lsqr_handle* h) { return h->att_mode == 1 && h->sv.natt > 0; }
+
 inline const int32_t* row_map(const lsqr_handle* h)
 {
-    return h->att_mode == 1 ? h->invperm : nullptr;
+    return att_pass_on(h) ? h->invperm : nullptr;
 }
 
 inline int64_t att_span(const lsqr_handle* h) { return h->bwidth + kParAxis - 1; }
@@ -226,6 +229,7 @@ inline int64_t att_slices(const lsqr_handle* h) { return h->nbk * h->att_g; }
 // right-hand sides; the remaining columns go to k_instr_tail windows.
 inline int64_t instr_hcols(const lsqr_handle* h, int64_t K)
 {
+    if (h->sv.ni == 0) return 0;
     return std::min<int64_t>(h->sv.n_instr_cols, kLdsInstrBudget / (8 * K));
 }
 
@@ -235,7 +239,7 @@ template <typename T, typename Acc, int K, bool SQUARE>
 void launch_instr_tail(const lsqr_handle* h, const Acc* U, const int32_t* inv, Acc* Q,
                        int64_t hcols, const Scalars* sc, hipStream_t st)
 {
-    const int64_t ninst = h->sv.n_instr_cols;
+    const int64_t ninst = h->sv.ni > 0 ? h->sv.n_instr_cols : 0;
     const int64_t tw = std::max<int64_t>(1, kLdsInstrBudget / (8 * K));
     for (int64_t c0 = hcols; c0 < ninst; c0 += tw) {
         const int64_t c1 = std::min(ninst, c0 + tw);
@@ -254,6 +258,11 @@ void launch_aprod1(const lsqr_handle* h, const VX* x, VY* y, const double* b, co
                    double* part, hipStream_t st, const int32_t* inv = nullptr,
                    const VX* x3 = nullptr)
 {
+    if (h->generic) {  // any layout: runtime section sizes
+        hipLaunchKernelGGL((k_gen_aprod1<T, Acc, VX, VY, MODE>), dim3(h->nb1), dim3(kBlock), 0, st,
+                           h->sv, x, y, b, sc, part, inv);
+        return;
+    }
     const int64_t bytes = h->sv.n_instr_cols * (int64_t)sizeof(VX);
     const dim3 g(h->nb1), b1(kBlock1);
     if (bytes <= kLdsXBudget && x3)
@@ -328,7 +337,20 @@ void launch_aprod2(lsqr_handle* h, const Acc* u, const int32_t* inv, Acc* q, Acc
 {
     const size_t lds = (size_t)(hcols * 8);
     const dim3 g(h->nb2), bm(kBlock2), b(kBlock);
-    const bool att = h->att_mode == 0;
+    const bool att = !att_pass_on(h);
+    if (h->generic) {  // any layout: runtime section sizes, 256-thread workgroups
+        if (att)
+            hipLaunchKernelGGL((k_gen_aprod2<T, Acc, Acc, false, true>), dim3(h->nba), b, lds, st,
+                               h->sv, u, q, h->wb, gpart, hcols, sc, inv);
+        else
+            hipLaunchKernelGGL((k_gen_aprod2<T, Acc, Acc, false, false>), dim3(h->nba), b, lds, st,
+                               h->sv, u, q, h->wb, gpart, hcols, sc, inv);
+        hipLaunchKernelGGL((k_gen_glob_sum<Acc>), dim3(1), b, 0, st, gpart, h->nba, h->sv.ng,
+                           q + h->sv.glob_base, sc);
+        launch_instr_tail<T, Acc, 1, false>(h, u, inv, q, hcols, sc, st);
+        if (!att) launch_att_pass<T, Acc>(h, ub, q, sc, st);
+        return;
+    }
     if (att && h->astro_scan)
         hipLaunchKernelGGL((k_aprod2<T, Acc, Acc, false, true, true, kBlock2>), g, bm, lds, st, h->sv,
                            u, q, h->wb, gpart, hcols, sc, inv);
@@ -347,7 +369,10 @@ void launch_aprod2(lsqr_handle* h, const Acc* u, const int32_t* inv, Acc* q, Acc
 }
 
 // The fused pass serves the default attitude mode (bucket-order pass).
-inline bool use_fused(const lsqr_handle* h) { return h->fused && h->att_mode == 1; }
+inline bool use_fused(const lsqr_handle* h)
+{
+    return h->fused && att_pass_on(h) && !h->generic;
+}
 
 // One LSQR iteration; ev (optional) = 4 events bracketing aprod1 and aprod2
 // (with the fused pass: that pass, and the attitude pass).
@@ -356,7 +381,8 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
 {
     const int64_t n = h->sv.n;
     if (ev) (void)hipEventRecord(ev[0], st);
-    if (h->att_il) launch_interleave_att<Acc>(h, P.vp, P.vp3, h->sc, st);
+    const bool il = h->att_il && h->sv.natt > 0 && !h->generic;
+    if (il) launch_interleave_att<Acc>(h, P.vp, P.vp3, h->sc, st);
     if (use_fused(h)) {
         launch_fused<T, Acc>(h, P, st);
         if (ev) (void)hipEventRecord(ev[1], st);
@@ -368,7 +394,7 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
     } else {
         launch_aprod1<T, Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u, nullptr, h->sc,
                                                 h->part1, st, row_map(h),
-                                                h->att_il ? (const Acc*)P.vp3 : nullptr);
+                                                il ? (const Acc*)P.vp3 : nullptr);
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
         if (ev) (void)hipEventRecord(ev[2], st);
@@ -410,7 +436,7 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     LSQR_TRY(dalloc(&P.u, m));
     LSQR_TRY(dalloc(&P.vp, n));
     LSQR_TRY(dalloc(&P.q, n));
-    LSQR_TRY(dalloc(&P.gpart, h->nb2));
+    LSQR_TRY(dalloc(&P.gpart, std::max<int64_t>(h->nb2, (int64_t)h->nba * kGlobMax)));
     LSQR_TRY(dalloc(&P.vp3, (int64_t)kAxes * h->sv.n_dfa));
     // LDS histograms are FP64 whatever Acc is (k_att_hist); the fused pass
     // keeps the histogram and, if both fit, the instrumental slice of vp
@@ -496,7 +522,8 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
                                       bits, st);
     if (rc == LSQR_OK && e == hipSuccess) {
         hipLaunchKernelGGL((k_att_gather<T>), gm, bb, 0, st, (const T*)h->sv.val, h->sv.att, m,
-                           (const int32_t*)h->perm, h->bwidth, att_sorted, h->tloc);
+                           (const int32_t*)h->perm, h->bwidth, h->sv.off_att, att_sorted,
+                           h->tloc);
         hipLaunchKernelGGL(k_invert_perm, gm, bb, 0, st, (const int32_t*)h->perm, m, h->invperm);
         hipLaunchKernelGGL(k_bucket_starts, dim3(std::min<int64_t>(cdiv(m + 1, kBlock), 65536)), bb,
                            0, st, (const int32_t*)skeys, m, h->nbk, h->bstart);
@@ -515,7 +542,7 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
 
 lsqr_status ensure_att(lsqr_handle* h)
 {
-    if (h->att_mode == 0) return LSQR_OK;
+    if (!att_pass_on(h)) return LSQR_OK;
     return h->value_type == LSQR_F64 ? prepare_att_sorted<double>(h) : prepare_att_sorted<float>(h);
 }
 
@@ -1071,19 +1098,25 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     if (!sys) return fail(LSQR_E_INVALID, "system descriptor is null");
     if (sys->n_rows <= 0) return fail(LSQR_E_INVALID, "n_rows must be > 0");
     if (sys->n_stars <= 0) return fail(LSQR_E_INVALID, "n_stars must be > 0");
-    if (sys->n_astro != kAstro || sys->n_axes != kAxes || sys->n_par_axis != kParAxis ||
-        sys->n_instr != kInstr || sys->n_glob != 1)
-        return fail(LSQR_E_UNSUPPORTED,
-                    "only the 5 astrometric + 3x4 attitude + 6 instrumental + 1 global row "
-                    "layout is built (got %d, %dx%d, %d, %d)",
-                    sys->n_astro, sys->n_axes, sys->n_par_axis, sys->n_instr, sys->n_glob);
-    if (sys->n_dfa < sys->n_par_axis) return fail(LSQR_E_INVALID, "n_dfa must be >= n_par_axis");
-    if (sys->n_instr_cols < sys->n_instr)
-        return fail(LSQR_E_INVALID, "n_instr_cols must be >= n_instr");
+    if (sys->n_astro < 0 || sys->n_astro > kAstro || sys->n_instr < 0 || sys->n_instr > kInstr ||
+        sys->n_glob < 0 || sys->n_glob > kGlobMax || sys->n_axes < 0 || sys->n_par_axis < 0)
+        return fail(LSQR_E_INVALID, "section sizes out of range (astro 0..5, instr 0..6, "
+                                    "glob 0..5)");
+    if (sys->n_axes != 0 && (sys->n_axes != kAxes || sys->n_par_axis != kParAxis))
+        return fail(LSQR_E_UNSUPPORTED, "the attitude section is 3 axes x 4 parameters or absent "
+                                        "(got %dx%d)", sys->n_axes, sys->n_par_axis);
+    const int32_t natt = sys->n_axes ? kAxes * kParAxis : 0;
+    if (sys->n_astro + natt + sys->n_instr + sys->n_glob < 1)
+        return fail(LSQR_E_INVALID, "a row needs at least one coefficient");
+    if (natt && sys->n_dfa < sys->n_par_axis)
+        return fail(LSQR_E_INVALID, "n_dfa must be >= n_par_axis");
+    if (sys->n_dfa < 0 || sys->n_instr_cols < sys->n_instr || sys->n_instr_cols < 0)
+        return fail(LSQR_E_INVALID, "n_instr_cols must be >= n_instr and n_dfa >= 0");
     if (sys->n_instr_cols > INT32_MAX) return fail(LSQR_E_INVALID, "n_instr_cols too large");
     if (sys->value_type != LSQR_F64 && sys->value_type != LSQR_F32)
         return fail(LSQR_E_INVALID, "value_type must be LSQR_F64 or LSQR_F32");
-    if (!sys->values || !sys->star_of_row || !sys->att_start || !sys->instr_idx)
+    if (!sys->values || !sys->star_of_row || (natt && !sys->att_start) ||
+        (sys->n_instr && !sys->instr_idx))
         return fail(LSQR_E_INVALID, "matrix array pointer is null");
     if (sys->n_rows > ((int64_t)1 << 40)) return fail(LSQR_E_INVALID, "n_rows too large");
 
@@ -1111,10 +1144,19 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     s.n_stars = sys->n_stars;
     s.n_dfa = sys->n_dfa;
     s.n_instr_cols = sys->n_instr_cols;
-    s.att_base = (int64_t)kAstro * sys->n_stars;
-    s.instr_base = s.att_base + (int64_t)kAxes * sys->n_dfa;
+    // column order astro | att | instr | glob (Algorithms 2-3)
+    s.na = sys->n_astro;
+    s.natt = natt;
+    s.ni = sys->n_instr;
+    s.ng = sys->n_glob;
+    s.off_att = s.na;
+    s.off_instr = s.na + s.natt;
+    s.off_glob = s.off_instr + s.ni;
+    s.att_base = (int64_t)s.na * sys->n_stars;
+    s.instr_base = s.att_base + (int64_t)sys->n_axes * sys->n_dfa;
     s.glob_base = s.instr_base + sys->n_instr_cols;
-    s.n = s.glob_base + 1;
+    s.n = s.glob_base + s.ng;
+    h->generic = !(s.na == kAstro && s.natt == kAxes * kParAxis && s.ni == kInstr && s.ng == 1);
     h->value_type = sys->value_type;
     h->precondition = sys->precondition ? 1 : 0;
     h->user_stream = static_cast<hipStream_t>(sys->stream);
@@ -1164,7 +1206,9 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     if ((st = dalloc(&h->partc, h->nbc)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->partdd, h->nbc)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->partxx, h->nbc)) != LSQR_OK) return bail(st);
-    if ((st = dalloc(&h->gpart_raw, h->nb2)) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->gpart_raw, std::max<int64_t>(h->nb2, (int64_t)h->nba * kGlobMax))) !=
+        LSQR_OK)
+        return bail(st);
     if ((st = dalloc(&h->flag, 1)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->sc, 1)) != LSQR_OK) return bail(st);
     e = hipHostMalloc(reinterpret_cast<void**>(&h->sc_host), sizeof(Scalars), hipHostMallocDefault);
@@ -1205,7 +1249,21 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     const int64_t hc = instr_hcols(h, 1);
     const size_t lds = (size_t)(hc * 8);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st0, n, ssq, 0.0);
-    if (h->value_type == LSQR_F64) {
+    if (h->generic) {
+        if (h->value_type == LSQR_F64) {
+            hipLaunchKernelGGL((k_gen_aprod2<double, double, double, true, true>), dim3(h->nba),
+                               dim3(kBlock), lds, st0, s, (const double*)nullptr, ssq, h->wb,
+                               h->gpart_raw, hc, (const Scalars*)nullptr, (const int32_t*)nullptr);
+            launch_instr_tail<double, double, 1, true>(h, nullptr, nullptr, ssq, hc, nullptr, st0);
+        } else {
+            hipLaunchKernelGGL((k_gen_aprod2<float, double, double, true, true>), dim3(h->nba),
+                               dim3(kBlock), lds, st0, s, (const double*)nullptr, ssq, h->wb,
+                               h->gpart_raw, hc, (const Scalars*)nullptr, (const int32_t*)nullptr);
+            launch_instr_tail<float, double, 1, true>(h, nullptr, nullptr, ssq, hc, nullptr, st0);
+        }
+        hipLaunchKernelGGL((k_gen_glob_sum<double>), dim3(1), dim3(kBlock), 0, st0, h->gpart_raw,
+                           h->nba, s.ng, ssq + s.glob_base, (const Scalars*)nullptr);
+    } else if (h->value_type == LSQR_F64) {
         hipLaunchKernelGGL((k_aprod2<double, double, double, true, true, true, kBlock2>),
                            dim3(h->nb2), dim3(kBlock2), lds, st0, s, (const double*)nullptr, ssq,
                            h->wb, h->gpart_raw, hc, (const Scalars*)nullptr);
@@ -1216,8 +1274,9 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
                            h->wb, h->gpart_raw, hc, (const Scalars*)nullptr);
         launch_instr_tail<float, double, 1, true>(h, nullptr, nullptr, ssq, hc, nullptr, st0);
     }
-    hipLaunchKernelGGL((k_glob_sum<double>), dim3(1), dim3(kBlock), 0, st0, h->gpart_raw, h->nb2,
-                       ssq + s.glob_base, (const Scalars*)nullptr);
+    if (!h->generic)
+        hipLaunchKernelGGL((k_glob_sum<double>), dim3(1), dim3(kBlock), 0, st0, h->gpart_raw,
+                           h->nb2, ssq + s.glob_base, (const Scalars*)nullptr);
     hipLaunchKernelGGL(k_make_p, dim3(h->nbc), dim3(kBlock), 0, st0, n, ssq, h->p, h->precondition);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st0);
@@ -1352,7 +1411,7 @@ lsqr_status lsqr_aprod1(lsqr_handle* h, const double* x, double* y)
     LSQR_TRY(check_handle(h));
     if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
     const double* x3 = nullptr;
-    if (h->att_il) {
+    if (h->att_il && h->sv.natt > 0 && !h->generic) {
         if (!h->x3_raw) LSQR_TRY(dalloc(&h->x3_raw, (int64_t)kAxes * h->sv.n_dfa));
         launch_interleave_att<double>(h, x, h->x3_raw, nullptr, h->user_stream);
         x3 = h->x3_raw;
@@ -1375,8 +1434,9 @@ lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y)
     const int64_t hc = instr_hcols(h, 1);
     // y in row order for the star-order pass; a copy in bucket order for the
     // attitude pass
+    // (only where the bucket order exists: attitude section present, mode 1)
     const double* yb = nullptr;
-    if (h->att_mode == 1) {
+    if (att_pass_on(h)) {
         if (!h->us_raw) LSQR_TRY(dalloc(&h->us_raw, h->sv.m));
         hipLaunchKernelGGL((k_gather_perm<double>),
                            dim3(std::min<int64_t>(cdiv(h->sv.m, kBlock), 65536)), dim3(kBlock), 0,
@@ -1470,7 +1530,7 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
         LSQR_TRY(upload_controls(h, itn_limit, 0.0, 0.0, std::max(atol, 1e-300)));
         // FP64 residual of the full problem, stored as the FP32 start vector
         const double* x3 = nullptr;
-        if (h->att_il) {
+        if (h->att_il && h->sv.natt > 0 && !h->generic) {
             if (!h->x3_raw) LSQR_TRY(dalloc(&h->x3_raw, (int64_t)kAxes * h->sv.n_dfa));
             launch_interleave_att<double>(h, x, h->x3_raw, nullptr, h->stream);
             x3 = h->x3_raw;
@@ -1510,6 +1570,9 @@ lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32
     if (k < 1 || k > 4096) return fail(LSQR_E_INVALID, "k must be in [1, 4096]");
     if (itn_limit < 0) return fail(LSQR_E_INVALID, "itn_limit must be >= 0");
     if (!(atol >= 0.0) || !(btol >= 0.0)) return fail(LSQR_E_INVALID, "atol, btol must be >= 0");
+    if (h->generic)
+        return fail(LSQR_E_UNSUPPORTED,
+                    "batched solves are built for the 5 + 3x4 + 6 + 1 row layout only");
     HIP_TRY(hipStreamSynchronize(h->user_stream));
     h->var_valid = 0;
     LSQR_TRY(ensure_att(h));

@@ -134,15 +134,18 @@ def _dev_ptr(t, dtype, shape=None, name="tensor"):
 class LsqrSystem:
     """Handle over a device-resident AVU-GSR system (borrowed tensors).
 
-    values [24, m] float64/float32, star_of_row [m] int64 (non-decreasing),
-    att_start [m] int64, instr_idx [6, m] int32."""
+    values [n_par, m] float64/float32 (n_par = n_astro + 3 x 4 (if n_axes) +
+    n_instr + n_glob; 24 for the full layout), star_of_row [m] int64
+    (non-decreasing), att_start [m] int64, instr_idx [n_instr, m] int32."""
 
     def __init__(self, values, star_of_row, att_start, instr_idx, n_stars: int, n_dfa: int,
-                 n_instr_cols: int, precondition: bool = True, stream=None):
+                 n_instr_cols: int, precondition: bool = True, stream=None, n_astro: int = 5,
+                 n_axes: int = 3, n_par_axis: int = 4, n_instr: int = 6, n_glob: int = 1):
         import torch
 
         lib = load_library()
         m = int(values.shape[1])
+        n_par = n_astro + n_axes * n_par_axis + n_instr + n_glob
         if values.dtype not in (torch.float64, torch.float32):
             raise TypeError("values must be float64 or float32")
         self._keep = (values, star_of_row, att_start, instr_idx)
@@ -152,14 +155,17 @@ class LsqrSystem:
         stream = stream if stream is not None else torch.cuda.current_stream(values.device)
         self._stream = stream
         desc = _System(
-            n_rows=m, n_stars=int(n_stars), n_astro=5, n_axes=3, n_par_axis=4, n_instr=6,
-            n_dfa=int(n_dfa), n_instr_cols=int(n_instr_cols), n_glob=1,
+            n_rows=m, n_stars=int(n_stars), n_astro=int(n_astro), n_axes=int(n_axes),
+            n_par_axis=int(n_par_axis), n_instr=int(n_instr), n_dfa=int(n_dfa),
+            n_instr_cols=int(n_instr_cols), n_glob=int(n_glob),
             value_type=LSQR_F64 if values.dtype == torch.float64 else LSQR_F32,
             precondition=1 if precondition else 0, reserved=0,
-            values=_dev_ptr(values, values.dtype, (24, m), "values"),
+            values=_dev_ptr(values, values.dtype, (n_par, m), "values"),
             star_of_row=_dev_ptr(star_of_row, torch.int64, (m,), "star_of_row"),
-            att_start=_dev_ptr(att_start, torch.int64, (m,), "att_start"),
-            instr_idx=_dev_ptr(instr_idx, torch.int32, (6, m), "instr_idx"),
+            att_start=(_dev_ptr(att_start, torch.int64, (m,), "att_start") if n_axes
+                       else ctypes.c_void_p(0)),
+            instr_idx=(_dev_ptr(instr_idx, torch.int32, (n_instr, m), "instr_idx") if n_instr
+                       else ctypes.c_void_p(0)),
             stream=ctypes.c_void_p(stream.cuda_stream))
         h = ctypes.c_void_p()
         with torch.cuda.device(values.device):
@@ -181,7 +187,8 @@ class LsqrSystem:
                  instr_idx=torch.from_numpy(system.instr_idx).to(device))
         torch.cuda.synchronize(device)
         return cls(**t, n_stars=sp.n_stars, n_dfa=sp.n_dfa, n_instr_cols=sp.n_instr_cols,
-                   precondition=precondition)
+                   precondition=precondition, n_astro=sp.n_astro, n_axes=sp.n_axes,
+                   n_par_axis=sp.n_par_axis, n_instr=sp.n_instr, n_glob=sp.n_glob)
 
     # ------------------------------------------------------------------ API
     def close(self):

@@ -62,12 +62,21 @@ def test_descriptor_checks_without_gpu(lib):
     import paper_2308_00778_amd.lsqr as L
 
     L.load_library()
-    d = L._System(n_rows=100, n_stars=1, n_astro=5, n_axes=3, n_par_axis=4, n_instr=5,
+    d = L._System(n_rows=100, n_stars=1, n_astro=5, n_axes=2, n_par_axis=4, n_instr=6,
                   n_dfa=10, n_instr_cols=10, n_glob=1, value_type=0, precondition=1,
                   values=1, star_of_row=1, att_start=1, instr_idx=1, stream=None)
     h = ctypes.c_void_p()
+    # an attitude section other than 3 axes x 4 parameters is not built
     assert L._lib.lsqr_create(ctypes.byref(d), ctypes.byref(h)) == L.LSQR_E_UNSUPPORTED
-    d.n_instr = 6
+    d.n_axes = 3
+    for field, bad in (("n_instr", 7), ("n_astro", 6), ("n_glob", 6), ("n_astro", -1)):
+        good = getattr(d, field)
+        setattr(d, field, bad)
+        assert L._lib.lsqr_create(ctypes.byref(d), ctypes.byref(h)) == L.LSQR_E_INVALID
+        setattr(d, field, good)
+    d.n_astro, d.n_axes, d.n_instr, d.n_glob = 0, 0, 0, 0
+    assert L._lib.lsqr_create(ctypes.byref(d), ctypes.byref(h)) == L.LSQR_E_INVALID
+    d.n_astro, d.n_axes, d.n_instr, d.n_glob = 5, 3, 6, 1
     d.n_rows = 0
     assert L._lib.lsqr_create(ctypes.byref(d), ctypes.byref(h)) == L.LSQR_E_INVALID
     d.n_rows = 100

@@ -278,11 +278,44 @@ def check_variance_limit():
     assert np.all(prev > 0)
 
 
+# Row layouts with some sections absent or resized (the paper's subset
+# systems: astrometric-only, attitude-only, several global columns).
+SECTION_LAYOUTS = {
+    "astro_only": dict(n_axes=0, n_instr=0, n_glob=0),
+    "att_only": dict(n_astro=0, n_instr=0, n_glob=0),
+    "mixed": dict(n_astro=3, n_instr=2, n_glob=3),
+    "no_att_five_glob": dict(n_axes=0, n_glob=5),
+}
+
+
+def section_system(name, seed=41):
+    spec = synth.tiny(seed=seed, n_stars=30, obs=(10, 30), n_dfa=40, n_instr_cols=15,
+                      **SECTION_LAYOUTS[name])
+    return synth.make_system(spec)
+
+
+def check_section_layouts():
+    for name in SECTION_LAYOUTS:
+        S = section_system(name)
+        o = oracle.OracleSystem.from_synth(S)
+        A = dense_matrix(S)
+        rng = np.random.default_rng(3)
+        x = rng.standard_normal(o.n)
+        y = rng.standard_normal(o.m)
+        assert np.max(np.abs(o.aprod1(x) - A @ x)) <= 1e-12 * np.max(np.abs(A) @ np.abs(x)), name
+        assert np.max(np.abs(o.aprod2(y) - A.T @ y)) <= 1e-12 * np.max(np.abs(A.T) @ np.abs(y)), name
+        # converged solution against LAPACK (empty columns: p = 1, x = 0)
+        b = o.aprod1(synth.x_true(S.spec), synth.noise(S.spec, S.m))
+        x_orc, info = o.lsqr(b, 2000, atol=1e-14, btol=1e-14, conlim=0.0)
+        x_ls = np.linalg.lstsq(A, b, rcond=None)[0]
+        assert np.max(np.abs(x_orc - x_ls)) <= 1e-9 * np.max(np.abs(x_ls)), (name, info)
+
+
 CHECKS = [check_aprod_dense, check_adjoint_identity, check_unit_columns, check_norm_eq4,
           check_precond_dense, check_lstsq, check_scipy_iterates, check_scipy_stopping,
           check_cgls, check_first_iterate_closed_form, check_recurrence_invariants,
           check_noise_free_recovery, check_precondition_invariance, check_special_cases,
-          check_variance_limit]
+          check_variance_limit, check_section_layouts]
 
 
 @pytest.mark.parametrize("check", CHECKS, ids=[c.__name__ for c in CHECKS])
