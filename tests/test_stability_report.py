@@ -1,0 +1,87 @@
+"""Sect. 6 consistency report: hand-computed cases (CPU) and the GPU solution
+against the oracle's (GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2308_00778_amd import stability
+
+
+def test_eq6_arcsec():
+    # Eq. (6): 4.84814e-6 rad is one arcsecond
+    assert stability.sigma_arcsec(4.84814e-6) == pytest.approx(1.0, rel=1e-15)
+    assert stability.sigma_arcsec(np.array([0.0, 9.69628e-6]))[1] == pytest.approx(2.0)
+
+
+def test_sections_follow_the_column_order():
+    s = stability.sections(n_stars=10, n_dfa=7, n_instr_cols=4)
+    assert s == {"astrometric": (0, 50), "attitude": (50, 71), "instrumental": (71, 75),
+                 "global": (75, 76)}
+    s = stability.sections(n_stars=10, n_dfa=7, n_instr_cols=4, n_astro=0, n_glob=0)
+    assert s == {"attitude": (0, 21), "instrumental": (21, 25)}
+
+
+def test_standard_errors():
+    # var 4 and 9, residual norm 6 over m - n = 4 degrees of freedom: s = 3
+    np.testing.assert_allclose(stability.standard_errors([4.0, 9.0], 6.0, 10, 6), [6.0, 9.0],
+                               rtol=1e-15)
+    with pytest.raises(ValueError):
+        stability.standard_errors([1.0], 1.0, 3, 3)
+
+
+def test_compare_hand_example():
+    x_a = [1.0, 2.0, 3.0, 4.0]
+    x_b = [1.0, 2.5, 3.0, 4.0]
+    s_a = [1.0, 1.0, 2.0, 0.0]
+    s_b = [1.0, 1.0, 0.0, 0.0]
+    r = stability.compare(x_a, s_a, x_b, s_b, {"a": (0, 2), "b": (2, 4)})
+    a, b = r
+    # section a: d_x = (0, -0.5), d_sigma = 0, q = (0, 0.5 / sqrt(2))
+    assert (a.mean_dx, a.std_dx) == (-0.25, 0.25)
+    assert (a.mean_dsigma, a.std_dsigma) == (0.0, 0.0)
+    assert a.q_max == pytest.approx(0.5 / math.sqrt(2.0), rel=1e-15) and a.consistent
+    # section b: d_x = 0, d_sigma = (2, 0); q = 0 where both errors are 0 and d_x = 0
+    assert (b.mean_dx, b.std_dx) == (0.0, 0.0)
+    assert (b.mean_dsigma, b.std_dsigma) == (1.0, 1.0)
+    assert b.q_max == 0.0
+    # a difference with zero errors is inconsistent
+    r = stability.compare([0.0], [0.0], [1e-30], [0.0], {"c": (0, 1)})
+    assert r[0].q_max == math.inf and not r[0].consistent
+    with pytest.raises(ValueError):
+        stability.compare([0.0], [-1.0], [0.0], [0.0], {"c": (0, 1)})
+    assert "max q" in stability.format_table(r)
+
+
+@pytest.mark.gpu
+def test_gpu_solution_consistent_with_oracle():
+    import torch
+
+    import oracle
+    import synth
+    from paper_2308_00778_amd import LsqrSystem
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    S = synth.make_system(synth.CONFIGS[0])
+    o = oracle.OracleSystem.from_synth(S)
+    b = o.aprod1(synth.x_true(S.spec), synth.noise(S.spec, S.m))
+    x_ref, i_ref, var_ref = o.lsqr(b, 500, atol=1e-12, btol=1e-12, conlim=0.0, want_var=True)
+    print(f"stability report: c0 oracle itn={i_ref.itn}", flush=True)
+    g = LsqrSystem.from_host(S, "cuda:0")
+    g.set_option("variance", 1)
+    x, info = g.solve(torch.from_numpy(b).cuda(), 500, atol=1e-12, btol=1e-12)
+    var = g.variance().cpu().numpy()
+    xg = x.cpu().numpy()
+    g.close()
+    sp = S.spec
+    rows = stability.compare(xg, stability.standard_errors(var, info.rnorm, S.m, xg.size),
+                             x_ref, stability.standard_errors(var_ref, i_ref.rnorm, S.m, xg.size),
+                             stability.sections(sp.n_stars, sp.n_dfa, sp.n_instr_cols))
+    print(stability.format_table(rows), flush=True)
+    assert [r.section for r in rows] == ["astrometric", "attitude", "instrumental", "global"]
+    for r in rows:
+        assert r.consistent
+        # same iterate count, same precision: differences at the rounding level
+        assert r.q_max < 1e-6
+        assert abs(r.mean_dx) <= 1e-12 and r.std_dx <= 1e-12
