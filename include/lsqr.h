@@ -80,6 +80,18 @@ typedef struct lsqr_system {
     const int32_t* instr_idx;   /* [n_instr][n_rows] SoA, in [0, n_instr_cols);
                                    NULL ok when n_instr = 0                       */
     void* stream;               /* hipStream_t for all work, NULL = null stream   */
+    /* Constraint equations (Sect. 2: extra rows at the bottom of the system,
+     * defined outside the paper): n_con rows numbered n_rows .. n_rows +
+     * n_con - 1 of A, of b and of aprod1/aprod2's y. Row r holds con_val[e]
+     * at column con_col[e] for e in [con_rowptr[r], con_rowptr[r + 1])
+     * (CSR; a column repeated within a row adds). FP64 values whatever
+     * value_type is; borrowed like the matrix arrays. n_con = 0: none, the
+     * pointers are ignored. lsqr_solve_batched returns LSQR_E_UNSUPPORTED
+     * on a system with constraint rows. */
+    int64_t n_con;              /* 0..2^31                                        */
+    const int64_t* con_rowptr;  /* [n_con + 1]: 0, non-decreasing, ends at nnz   */
+    const int64_t* con_col;     /* [nnz], in [0, n)                               */
+    const double* con_val;      /* [nnz]                                          */
 } lsqr_system;
 
 /* Result of a solve. istop follows Paige & Saunders:
@@ -102,7 +114,7 @@ typedef struct lsqr_info {
 typedef struct lsqr_handle lsqr_handle;
 
 /* Create a handle: validates the descriptor and every index (a scan of the
- * index arrays on the GPU), computes the column scaling p_j = 1/||A[:,j]||
+ * index arrays and of the constraint rows' structure on the GPU), computes the column scaling p_j = 1/||A[:,j]||
  * (1 for an empty column; Sect. 2, preconditioning) and allocates the
  * workspace (owned by the handle). Synchronous. */
 lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out);
@@ -174,6 +186,9 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_FUSED 12
 #define LSQR_OPT_VARIANCE 13
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
+
+/* Below, m counts every row: n_rows observation rows plus n_con constraint
+ * rows. */
 
 /* aprod mode 1, Eq. (2): y[m] += A x[n] with the raw (unscaled) A.
  * FP64 vectors; float-stored values are widened, accumulation in FP64.

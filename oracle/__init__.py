@@ -10,7 +10,7 @@ Pinned by tests/test_oracle_pins.py against dense brute force, the adjoint
 identity, LAPACK least squares, SciPy's LSQR, CGLS, closed forms and
 invariants. Parity pinned for: aprod1, aprod2, the Eq. (4) norm, the column
 norms, the LSQR iterates and estimates, and the variance estimate (loosely, in
-its limit). The physical meaning of the attitude B-spline and instrumental
+its limit), on the full row layout, section subsets and with constraint rows. The physical meaning of the attitude B-spline and instrumental
 coefficients is not modelled (synthetic N(0,1) values): parity unpinned there
 by construction, since it does not enter the arithmetic.
 """
@@ -50,7 +50,9 @@ class _Sys(ctypes.Structure):
                 ("n_instr", ctypes.c_int32), ("n_instr_cols", ctypes.c_int64),
                 ("n_glob", ctypes.c_int32), ("value_is_f32", ctypes.c_int32),
                 ("values", ctypes.c_void_p), ("star", ctypes.c_void_p),
-                ("att", ctypes.c_void_p), ("instr", ctypes.c_void_p)]
+                ("att", ctypes.c_void_p), ("instr", ctypes.c_void_p),
+                ("n_con", ctypes.c_int64), ("con_rowptr", ctypes.c_void_p),
+                ("con_col", ctypes.c_void_p), ("con_val", ctypes.c_void_p)]
 
 
 class _Info(ctypes.Structure):
@@ -114,32 +116,50 @@ class Info:
 class OracleSystem:
     """Host view of a system in the shared SoA layout.
 
-    values [n_par, m] (float64 or float32: float32 is widened on read),
-    star_of_row [m] int64, att_start [m] int64, instr_idx [n_instr, m] int32."""
+    values [n_par, m_obs] (float64 or float32: float32 is widened on read),
+    star_of_row [m_obs] int64, att_start [m_obs] int64, instr_idx [n_instr, m_obs]
+    int32; con (optional): constraint rows (rowptr, col, val attributes, CSR)
+    appended below the observations. m = m_obs + n_con is the length of b."""
 
     def __init__(self, values, star_of_row, att_start, instr_idx, n_stars, n_dfa,
-                 n_instr_cols, n_astro=5, n_axes=3, n_par_axis=4, n_instr=6, n_glob=1):
+                 n_instr_cols, n_astro=5, n_axes=3, n_par_axis=4, n_instr=6, n_glob=1,
+                 con=None):
         self._keep = [np.ascontiguousarray(values), np.ascontiguousarray(star_of_row, np.int64),
                       np.ascontiguousarray(att_start, np.int64),
                       np.ascontiguousarray(instr_idx, np.int32)]
         vals, star, att, instr = self._keep
         assert vals.dtype in (np.float64, np.float32)
-        self.m = int(vals.shape[1])
-        self.c = _Sys(m=self.m, n_stars=n_stars, n_astro=n_astro, n_axes=n_axes,
+        self.m_obs = int(vals.shape[1])
+        n_con, rp, cc, cv = 0, None, None, None
+        if con is not None:
+            rp = np.ascontiguousarray(con.rowptr, np.int64)
+            cc = np.ascontiguousarray(con.col, np.int64)
+            cv = np.ascontiguousarray(con.val, np.float64)
+            n_con = int(rp.shape[0] - 1)
+            assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and cc.shape == cv.shape == (rp[-1],)
+            self._keep += [rp, cc, cv]
+        self.n_con = n_con
+        self.m = self.m_obs + n_con
+        self.c = _Sys(m=self.m_obs, n_stars=n_stars, n_astro=n_astro, n_axes=n_axes,
                       n_par_axis=n_par_axis, n_dfa=n_dfa, n_instr=n_instr,
                       n_instr_cols=n_instr_cols, n_glob=n_glob,
                       value_is_f32=1 if vals.dtype == np.float32 else 0,
                       values=vals.ctypes.data, star=star.ctypes.data, att=att.ctypes.data,
-                      instr=instr.ctypes.data)
+                      instr=instr.ctypes.data, n_con=n_con,
+                      con_rowptr=None if rp is None else rp.ctypes.data,
+                      con_col=None if cc is None else cc.ctypes.data,
+                      con_val=None if cv is None else cv.ctypes.data)
         self.n = int(_load().orc_ncols(ctypes.byref(self.c)))
+        if cc is not None and cc.size:
+            assert cc.min() >= 0 and cc.max() < self.n
 
     @classmethod
-    def from_synth(cls, system) -> "OracleSystem":
+    def from_synth(cls, system, con=None) -> "OracleSystem":
         sp = system.spec
         return cls(system.values, system.star_of_row, system.att_start, system.instr_idx,
                    n_stars=sp.n_stars, n_dfa=sp.n_dfa, n_instr_cols=sp.n_instr_cols,
                    n_astro=sp.n_astro, n_axes=sp.n_axes, n_par_axis=sp.n_par_axis,
-                   n_instr=sp.n_instr, n_glob=sp.n_glob)
+                   n_instr=sp.n_instr, n_glob=sp.n_glob, con=con)
 
     # -- operators -----------------------------------------------------------
     def aprod1(self, x, y=None):

@@ -14,6 +14,9 @@
  *   - Preconditioning: every column divided by its 2-norm, the normalisation
  *     factors kept in p, the solution re-multiplied by p after LSQR
  *     (Sect. 2 and Algorithm 1).
+ *   - Constraint equations (Sect. 2): extra rows placed after the observation
+ *     rows, visited after them in both aprods. Their content is defined
+ *     outside the paper; here they are general sparse rows (CSR).
  *   - Norms of the LSQR vectors by the max-scaled sum of squares of Eq. (4).
  *   - LSQR itself: Golub-Kahan bidiagonalisation + Givens QR with the
  *     estimates and stopping rules of Paige & Saunders, ACM TOMS 8 (1982),
@@ -47,6 +50,10 @@ typedef struct {
     const int64_t* star;   /* [m] */
     const int64_t* att;    /* [m] */
     const int32_t* instr;  /* [n_instr][m] */
+    int64_t n_con;         /* constraint rows m .. m + n_con - 1 */
+    const int64_t* con_rowptr; /* [n_con + 1] */
+    const int64_t* con_col;    /* [nnz] unknown index */
+    const double* con_val;     /* [nnz] */
 } orc_system;
 
 typedef struct {
@@ -91,7 +98,8 @@ static int64_t column(const orc_system* s, int32_t c, int64_t i)
     return glob_base + c;
 }
 
-/* Eq. (2): y[i] += sum_c A_d[i][c] * x[col(i,c)], rows in order. */
+/* Eq. (2): y[i] += sum_c A_d[i][c] * x[col(i,c)], rows in order, then the
+ * constraint rows. */
 void orc_aprod1(const orc_system* s, const double* x, double* y)
 {
     const int32_t np = n_par_of(s);
@@ -100,9 +108,15 @@ void orc_aprod1(const orc_system* s, const double* x, double* y)
         for (int32_t c = 0; c < np; ++c) sum += coef(s, c, i) * x[column(s, c, i)];
         y[i] += sum;
     }
+    for (int64_t r = 0; r < s->n_con; ++r) {
+        double sum = 0.0;
+        for (int64_t e = s->con_rowptr[r]; e < s->con_rowptr[r + 1]; ++e)
+            sum += s->con_val[e] * x[s->con_col[e]];
+        y[s->m + r] += sum;
+    }
 }
 
-/* Selected rows only: out[k] = (A x)[rows[k]]. */
+/* Selected observation rows only (rows[k] < m): out[k] = (A x)[rows[k]]. */
 void orc_aprod1_rows(const orc_system* s, const double* x, const int64_t* rows, int64_t nr,
                      double* out)
 {
@@ -115,12 +129,16 @@ void orc_aprod1_rows(const orc_system* s, const double* x, const int64_t* rows, 
     }
 }
 
-/* Eq. (3): x[col(i,c)] += A_d[i][c] * y[i], rows in order. */
+/* Eq. (3): x[col(i,c)] += A_d[i][c] * y[i], rows in order, then the
+ * constraint rows. */
 void orc_aprod2(const orc_system* s, double* x, const double* y)
 {
     const int32_t np = n_par_of(s);
     for (int64_t i = 0; i < s->m; ++i)
         for (int32_t c = 0; c < np; ++c) x[column(s, c, i)] += coef(s, c, i) * y[i];
+    for (int64_t r = 0; r < s->n_con; ++r)
+        for (int64_t e = s->con_rowptr[r]; e < s->con_rowptr[r + 1]; ++e)
+            x[s->con_col[e]] += s->con_val[e] * y[s->m + r];
 }
 
 /* Eq. (4): max-scaled 2-norm. */
@@ -145,6 +163,8 @@ void orc_precond(const orc_system* s, double* p)
             double a = coef(s, c, i);
             ssq[column(s, c, i)] += a * a;
         }
+    for (int64_t e = 0; e < (s->n_con ? s->con_rowptr[s->n_con] : 0); ++e)
+        ssq[s->con_col[e]] += s->con_val[e] * s->con_val[e];
     for (int64_t j = 0; j < n; ++j) p[j] = ssq[j] > 0.0 ? 1.0 / sqrt(ssq[j]) : 1.0;
     free(ssq);
 }
@@ -158,16 +178,19 @@ int orc_lsqr(const orc_system* s, const double* b, double* x, int32_t itn_limit,
              double btol, double conlim, int32_t precondition, int32_t tests, orc_info* info,
              double* var)
 {
-    const int64_t m = s->m, n = orc_ncols(s);
+    const int64_t m_obs = s->m, n = orc_ncols(s);
+    const int64_t m = m_obs + s->n_con; /* rows of u and b */
+    const int64_t nnz = s->n_con ? s->con_rowptr[s->n_con] : 0;
     const int32_t np = n_par_of(s);
     double* p = (double*)malloc((size_t)n * sizeof(double));
     double* u = (double*)malloc((size_t)m * sizeof(double));
     double* v = (double*)malloc((size_t)n * sizeof(double));
     double* w = (double*)malloc((size_t)n * sizeof(double));
     double* y = (double*)calloc((size_t)n, sizeof(double));
-    void* scaled = malloc((size_t)np * (size_t)m * sizeof(double));
-    if (!p || !u || !v || !w || !y || !scaled) {
-        free(p); free(u); free(v); free(w); free(y); free(scaled);
+    void* scaled = malloc((size_t)np * (size_t)m_obs * sizeof(double));
+    double* con_scaled = (double*)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    if (!p || !u || !v || !w || !y || !scaled || !con_scaled) {
+        free(p); free(u); free(v); free(w); free(y); free(scaled); free(con_scaled);
         return -1;
     }
 
@@ -176,10 +199,13 @@ int orc_lsqr(const orc_system* s, const double* b, double* x, int32_t itn_limit,
     else for (int64_t j = 0; j < n; ++j) p[j] = 1.0;
     double* ad = (double*)scaled;
     for (int32_t c = 0; c < np; ++c)
-        for (int64_t i = 0; i < m; ++i) ad[(int64_t)c * m + i] = coef(s, c, i) * p[column(s, c, i)];
+        for (int64_t i = 0; i < m_obs; ++i)
+            ad[(int64_t)c * m_obs + i] = coef(s, c, i) * p[column(s, c, i)];
+    for (int64_t e = 0; e < nnz; ++e) con_scaled[e] = s->con_val[e] * p[s->con_col[e]];
     orc_system sb = *s;
     sb.values = ad;
     sb.value_is_f32 = 0;
+    sb.con_val = con_scaled;
 
     if (var) memset(var, 0, (size_t)n * sizeof(double));
     const double ctol = conlim > 0.0 ? 1.0 / conlim : 0.0;
@@ -274,6 +300,6 @@ done:
         info->rnorm = rnorm; info->arnorm = arnorm; info->anorm = anorm;
         info->acond = acond; info->xnorm = xnorm; info->bnorm = bnorm;
     }
-    free(p); free(u); free(v); free(w); free(y); free(scaled);
+    free(p); free(u); free(v); free(w); free(y); free(scaled); free(con_scaled);
     return 0;
 }

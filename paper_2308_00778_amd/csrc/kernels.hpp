@@ -901,6 +901,109 @@ __global__ __launch_bounds__(kBlock) void k_gen_glob_sum(const Acc* __restrict__
     }
 }
 
+// --------------------------------------------------------- constraint rows
+// Equations appended below the observation rows (Sect. 2): a few long sparse
+// rows, in CSR form with FP64 values. One workgroup per row (grid-stride
+// over rows); their vector entries sit after the observation rows, unpermuted.
+
+// Eq. (2) on the constraint rows: dot_r = sum_e val[e] x[col[e]], then per
+// MODE (as k_aprod1) y[r] += dot, y[r] = dot - coef_u y[r] or
+// y[r] = b[r] - dot, and rowssq[r] = y[r]^2 (not in A1_ACCUM).
+template <typename Acc, typename VX, typename VY, int MODE>
+__global__ __launch_bounds__(kBlock) void k_con_aprod1(int64_t nc,
+                                                        const int64_t* __restrict__ rowptr,
+                                                        const int64_t* __restrict__ col,
+                                                        const double* __restrict__ val,
+                                                        const VX* __restrict__ x,
+                                                        VY* __restrict__ y,
+                                                        const double* __restrict__ b,
+                                                        const Scalars* __restrict__ sc,
+                                                        double* __restrict__ rowssq)
+{
+    __shared__ double red[kWavesPerBlock];
+    if (MODE == A1_LSQR && sc->done) return;
+    const Acc coef = (MODE == A1_LSQR) ? (Acc)sc->coef_u : (Acc)0;
+    for (int64_t r = blockIdx.x; r < nc; r += gridDim.x) {
+        const int64_t e1 = rowptr[r + 1];
+        Acc d = (Acc)0;
+        for (int64_t e = rowptr[r] + threadIdx.x; e < e1; e += kBlock)
+            d += (Acc)val[e] * (Acc)x[col[e]];
+        const double t = block_sum((double)d, red);
+        if (threadIdx.x == 0) {
+            const Acc dot = (Acc)t;
+            if (MODE == A1_ACCUM) {
+                y[r] = (VY)((Acc)y[r] + dot);
+            } else {
+                const VY nv = MODE == A1_LSQR ? (VY)(dot - coef * (Acc)y[r])
+                                              : (VY)((Acc)b[r] - dot);
+                y[r] = nv;
+                rowssq[r] = (double)nv * (double)nv;
+            }
+        }
+    }
+}
+
+// part[0] = sum of rowssq[0, nc) in a fixed order: the constraint rows' share
+// of ||u||^2, stored after the observation rows' partials.
+__global__ __launch_bounds__(kBlock) void k_con_ssq(int64_t nc, const double* __restrict__ rowssq,
+                                                     double* __restrict__ part)
+{
+    __shared__ double red[kWavesPerBlock];
+    double v = 0.0;
+    for (int64_t k = threadIdx.x; k < nc; k += kBlock) v += rowssq[k];
+    const double r = block_sum(v, red);
+    if (threadIdx.x == 0) part[0] = r;
+}
+
+// Eq. (3) on the constraint rows: q[col[e]] += val[e] u[r] (SQUARE: val[e]^2,
+// the column norms), device atomics (a column may appear in several rows).
+template <typename Acc, typename VU, bool SQUARE>
+__global__ __launch_bounds__(kBlock) void k_con_aprod2(int64_t nc,
+                                                        const int64_t* __restrict__ rowptr,
+                                                        const int64_t* __restrict__ col,
+                                                        const double* __restrict__ val,
+                                                        const VU* __restrict__ u,
+                                                        Acc* __restrict__ q,
+                                                        const Scalars* __restrict__ sc)
+{
+    if (sc != nullptr && (sc->done || sc->beta_zero)) return;
+    for (int64_t r = blockIdx.x; r < nc; r += gridDim.x) {
+        const Acc ur = SQUARE ? (Acc)0 : (Acc)u[r];
+        const int64_t e1 = rowptr[r + 1];
+        for (int64_t e = rowptr[r] + threadIdx.x; e < e1; e += kBlock) {
+            const Acc a = (Acc)val[e];
+            atomicAdd(&q[col[e]], SQUARE ? a * a : a * ur);
+        }
+    }
+}
+
+// Structure of the constraint rows: rowptr[0] = 0 and non-decreasing (bit 1),
+// then, in a second launch once that holds, every column in [0, n) (bit 2).
+__global__ __launch_bounds__(kBlock) void k_validate_con_rows(int64_t nc,
+                                                               const int64_t* __restrict__ rowptr,
+                                                               int32_t* __restrict__ flag)
+{
+    int32_t bad = 0;
+    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < nc;
+         r += (int64_t)gridDim.x * kBlock) {
+        if (r == 0 && rowptr[0] != 0) bad |= 1;
+        if (rowptr[r + 1] < rowptr[r]) bad |= 1;
+    }
+    if (bad) atomicOr(flag, bad);
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate_con_cols(int64_t nnz,
+                                                               const int64_t* __restrict__ col,
+                                                               int64_t n,
+                                                               int32_t* __restrict__ flag)
+{
+    int32_t bad = 0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * kBlock)
+        if (col[e] < 0 || col[e] >= n) bad |= 2;
+    if (bad) atomicOr(flag, bad);
+}
+
 // Second stage of the global-column reduction: q[glob] += sum of partials.
 template <typename Acc>
 __global__ __launch_bounds__(kBlock) void k_glob_sum(const Acc* __restrict__ gpart, int nblk,

@@ -146,12 +146,20 @@ struct lsqr_handle {
     double* v = nullptr;    // [n]
     double* w = nullptr;    // [n]
     double* y = nullptr;    // [n] iterate in the scaled space
-    double* part1 = nullptr;                    // [max(nb1, nb2)]
+    double* part1 = nullptr;                    // [max(nb1, nb2) + 1]
     double* partc = nullptr;                    // [nbc]
     double* partdd = nullptr;                   // [nbc]
     double* partxx = nullptr;                   // [nbc]
     double* gpart_raw = nullptr;                // [nb2] FP64 partials of lsqr_aprod2
     int32_t* flag = nullptr;                    // validation flags
+
+    // constraint rows (borrowed CSR, FP64 values) below the observation rows
+    int64_t nc = 0, con_nnz = 0;
+    const int64_t* con_rowptr = nullptr;
+    const int64_t* con_col = nullptr;
+    const double* con_val = nullptr;
+    double* con_ssq = nullptr;  // [nc] squares of the new row-vector entries
+    int con_grid = 0;           // workgroups of the constraint kernels
     Scalars* sc = nullptr;                      // device scalars
     Scalars* sc_host = nullptr;                 // pinned mirror
 
@@ -216,6 +224,10 @@ namespace {
 // Placement of the solver's row vector: bucket order in attitude mode 1.
 inline bool att_pass_on(const lsqr_handle* h) { return h->att_mode == 1 && h->sv.natt > 0; }
 
+// Partials of ||u||^2 that a scalar kernel sums: the row-pass partials plus,
+// with constraint rows, their share stored right after them.
+inline int n_part(const lsqr_handle* h, int nb) { return nb + (h->nc > 0 ? 1 : 0); }
+
 inline const int32_t* row_map(const lsqr_handle* h)
 {
     return att_pass_on(h) ? h->invperm : nullptr;
@@ -249,15 +261,43 @@ void launch_instr_tail(const lsqr_handle* h, const Acc* U, const int32_t* inv, A
     }
 }
 
+// Constraint rows of aprod1 (y, b: their entries, after the observation
+// rows) and, except in A1_ACCUM, their share of ||u||^2 into part[0].
+template <typename Acc, typename VX, typename VY, int MODE>
+void launch_con_aprod1(const lsqr_handle* h, const VX* x, VY* y, const double* b,
+                       const Scalars* sc, double* part, hipStream_t st)
+{
+    if (h->nc == 0) return;
+    hipLaunchKernelGGL((k_con_aprod1<Acc, VX, VY, MODE>), dim3(h->con_grid), dim3(kBlock), 0, st,
+                       h->nc, h->con_rowptr, h->con_col, h->con_val, x, y, b, sc, h->con_ssq);
+    if (MODE != A1_ACCUM)
+        hipLaunchKernelGGL(k_con_ssq, dim3(1), dim3(kBlock), 0, st, h->nc,
+                           (const double*)h->con_ssq, part);
+}
+
+// Constraint rows of aprod2: q += A_con^T u (u: their entries).
+template <typename Acc, typename VU>
+void launch_con_aprod2(const lsqr_handle* h, const VU* u, Acc* q, const Scalars* sc,
+                       hipStream_t st)
+{
+    if (h->nc == 0) return;
+    hipLaunchKernelGGL((k_con_aprod2<Acc, VU, false>), dim3(h->con_grid), dim3(kBlock), 0, st,
+                       h->nc, h->con_rowptr, h->con_col, h->con_val, u, q, sc);
+}
+
 // aprod1 with the instrumental slice of x staged in LDS when it fits.
 // x3 (optional): interleaved attitude section of x, already written
 // (k_interleave_att).
-// inv (optional): placement of y (row i at y[inv[i]]).
+// inv (optional): placement of y (row i at y[inv[i]]). Constraint rows follow
+// at y[m..] (b[m..]), their ||u||^2 share at part[nb1].
 template <typename T, typename Acc, typename VX, typename VY, int MODE>
 void launch_aprod1(const lsqr_handle* h, const VX* x, VY* y, const double* b, const Scalars* sc,
                    double* part, hipStream_t st, const int32_t* inv = nullptr,
                    const VX* x3 = nullptr)
 {
+    const int64_t m = h->sv.m;
+    launch_con_aprod1<Acc, VX, VY, MODE>(h, x, y + m, b ? b + m : nullptr, sc,
+                                         part ? part + h->nb1 : nullptr, st);
     if (h->generic) {  // any layout: runtime section sizes
         hipLaunchKernelGGL((k_gen_aprod1<T, Acc, VX, VY, MODE>), dim3(h->nb1), dim3(kBlock), 0, st,
                            h->sv, x, y, b, sc, part, inv);
@@ -327,8 +367,9 @@ void launch_att_pass(lsqr_handle* h, const Acc* ub, Acc* q, const Scalars* sc, h
                        q + h->sv.att_base, sc);
 }
 
-// q += A^T u for the LSQR loop (and lsqr_aprod2): the main pass over the rows
-// in star order (row i of u at u[inv[i]], or u[i] without inv), the
+// q += A^T u for the LSQR loop (and lsqr_aprod2): the constraint rows (u[m..]),
+// the main pass over the rows in star order (row i of u at u[inv[i]], or u[i]
+// without inv), the
 // global-column second stage and, in attitude mode 1, the attitude pass over
 // ub, the same vector in bucket order.
 template <typename T, typename Acc>
@@ -338,6 +379,7 @@ void launch_aprod2(lsqr_handle* h, const Acc* u, const int32_t* inv, Acc* q, Acc
     const size_t lds = (size_t)(hcols * 8);
     const dim3 g(h->nb2), bm(kBlock2), b(kBlock);
     const bool att = !att_pass_on(h);
+    launch_con_aprod2<Acc, Acc>(h, u + h->sv.m, q, sc, st);
     if (h->generic) {  // any layout: runtime section sizes, 256-thread workgroups
         if (att)
             hipLaunchKernelGGL((k_gen_aprod2<T, Acc, Acc, false, true>), dim3(h->nba), b, lds, st,
@@ -385,18 +427,23 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
     if (il) launch_interleave_att<Acc>(h, P.vp, P.vp3, h->sc, st);
     if (use_fused(h)) {
         launch_fused<T, Acc>(h, P, st);
+        launch_con_aprod1<Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u + h->sv.m, nullptr,
+                                                  h->sc, h->part1 + h->nb2, st);
         if (ev) (void)hipEventRecord(ev[1], st);
-        hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb2, h->sc);
+        hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1,
+                           n_part(h, h->nb2), h->sc);
         if (ev) (void)hipEventRecord(ev[2], st);
         hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), dim3(kBlock), 0, st, P.gpart, h->nb2,
                            P.q + h->sv.glob_base, h->sc);
         launch_att_pass<T, Acc>(h, P.u, P.q, h->sc, st);
+        launch_con_aprod2<Acc, Acc>(h, P.u + h->sv.m, P.q, h->sc, st);
     } else {
         launch_aprod1<T, Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u, nullptr, h->sc,
                                                 h->part1, st, row_map(h),
                                                 il ? (const Acc*)P.vp3 : nullptr);
         if (ev) (void)hipEventRecord(ev[1], st);
-        hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
+        hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1,
+                           n_part(h, h->nb1), h->sc);
         if (ev) (void)hipEventRecord(ev[2], st);
         launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.hcols, h->sc, st, P.u);
     }
@@ -417,7 +464,8 @@ template <typename T, typename Acc>
 void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st)
 {
     const int64_t n = h->sv.n;
-    hipLaunchKernelGGL(k_scalar_init_beta, dim3(1), dim3(kBlock), 0, st, h->part1, h->nb1, h->sc);
+    hipLaunchKernelGGL(k_scalar_init_beta, dim3(1), dim3(kBlock), 0, st, h->part1,
+                       n_part(h, h->nb1), h->sc);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, P.q, (Acc)0);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->v, 0.0);
     launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.hcols, h->sc, st, P.u);
@@ -433,7 +481,7 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
 {
     if (P.ready) return LSQR_OK;
     const int64_t m = h->sv.m, n = h->sv.n;
-    LSQR_TRY(dalloc(&P.u, m));
+    LSQR_TRY(dalloc(&P.u, m + h->nc));  // observation rows, then constraint rows
     LSQR_TRY(dalloc(&P.vp, n));
     LSQR_TRY(dalloc(&P.q, n));
     LSQR_TRY(dalloc(&P.gpart, std::max<int64_t>(h->nb2, (int64_t)h->nba * kGlobMax)));
@@ -682,6 +730,9 @@ lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_l
     }
     hipLaunchKernelGGL((k_copy_ssq<double>), dim3(h->nb1), dim3(kBlock), 0, h->stream, m, b, P.u,
                        h->part1, row_map(h));
+    if (h->nc > 0)  // constraint rows: after the observation rows, one partial
+        hipLaunchKernelGGL((k_copy_ssq<double>), dim3(1), dim3(kBlock), 0, h->stream, h->nc, b + m,
+                           P.u + m, h->part1 + h->nb1, (const int32_t*)nullptr);
     launch_init<T, double>(h, P, h->stream);
     HIP_TRY(hipGetLastError());
     LSQR_TRY(read_scalars(h));
@@ -1119,6 +1170,10 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
         (sys->n_instr && !sys->instr_idx))
         return fail(LSQR_E_INVALID, "matrix array pointer is null");
     if (sys->n_rows > ((int64_t)1 << 40)) return fail(LSQR_E_INVALID, "n_rows too large");
+    if (sys->n_con < 0 || sys->n_con > ((int64_t)1 << 31))
+        return fail(LSQR_E_INVALID, "n_con must be in [0, 2^31]");
+    if (sys->n_con > 0 && (!sys->con_rowptr || !sys->con_col || !sys->con_val))
+        return fail(LSQR_E_INVALID, "constraint array pointer is null");
 
     lsqr_handle* h = new (std::nothrow) lsqr_handle();
     if (!h) return fail(LSQR_E_NOMEM, "host allocation failed");
@@ -1157,6 +1212,12 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     s.glob_base = s.instr_base + sys->n_instr_cols;
     s.n = s.glob_base + s.ng;
     h->generic = !(s.na == kAstro && s.natt == kAxes * kParAxis && s.ni == kInstr && s.ng == 1);
+    h->nc = sys->n_con;
+    if (h->nc > 0) {
+        h->con_rowptr = sys->con_rowptr;
+        h->con_col = sys->con_col;
+        h->con_val = sys->con_val;
+    }
     h->value_type = sys->value_type;
     h->precondition = sys->precondition ? 1 : 0;
     h->user_stream = static_cast<hipStream_t>(sys->stream);
@@ -1202,7 +1263,7 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     if ((st = dalloc(&h->v, n)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->w, n)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->y, n)) != LSQR_OK) return bail(st);
-    if ((st = dalloc(&h->part1, std::max(h->nb1, h->nb2))) != LSQR_OK) return bail(st);
+    if ((st = dalloc(&h->part1, std::max(h->nb1, h->nb2) + 1)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->partc, h->nbc)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->partdd, h->nbc)) != LSQR_OK) return bail(st);
     if ((st = dalloc(&h->partxx, h->nbc)) != LSQR_OK) return bail(st);
@@ -1237,6 +1298,32 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
                          (bad & 2) ? " star_of_row not non-decreasing" : "",
                          (bad & 4) ? " att_start out of [0,n_dfa-4]" : "",
                          (bad & 8) ? " instr_idx out of [0,n_instr_cols)" : ""));
+    }
+    if (h->nc > 0) {
+        // row pointers first (they bound every later read), then the columns
+        if ((st = dalloc(&h->con_ssq, h->nc)) != LSQR_OK) return bail(st);
+        h->con_grid = (int)std::min<int64_t>(h->nc, 1024);
+        hipLaunchKernelGGL(k_validate_con_rows, dim3(std::min<int64_t>(cdiv(h->nc, kBlock), 1024)),
+                           dim3(kBlock), 0, st0, h->nc, h->con_rowptr, h->flag);
+        int64_t nnz = 0;
+        e = hipMemcpyAsync(&bad, h->flag, sizeof bad, hipMemcpyDeviceToHost, st0);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&nnz, h->con_rowptr + h->nc, sizeof nnz, hipMemcpyDeviceToHost, st0);
+        if (e == hipSuccess) e = hipStreamSynchronize(st0);
+        if (e != hipSuccess)
+            return bail(fail(LSQR_E_HIP, "constraint validation: %s", hipGetErrorString(e)));
+        if (bad)
+            return bail(fail(LSQR_E_INVALID,
+                             "constraint rows: con_rowptr must start at 0 and be non-decreasing"));
+        h->con_nnz = nnz;
+        hipLaunchKernelGGL(k_validate_con_cols,
+                           dim3(std::max<int64_t>(1, std::min<int64_t>(cdiv(nnz, kBlock), 8192))),
+                           dim3(kBlock), 0, st0, nnz, h->con_col, n, h->flag);
+        e = hipMemcpyAsync(&bad, h->flag, sizeof bad, hipMemcpyDeviceToHost, st0);
+        if (e == hipSuccess) e = hipStreamSynchronize(st0);
+        if (e != hipSuccess)
+            return bail(fail(LSQR_E_HIP, "constraint validation: %s", hipGetErrorString(e)));
+        if (bad) return bail(fail(LSQR_E_INVALID, "constraint rows: con_col out of [0, n)"));
     }
 
     // 2. star-aligned row ranges of the aprod2 waves
@@ -1277,6 +1364,10 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     if (!h->generic)
         hipLaunchKernelGGL((k_glob_sum<double>), dim3(1), dim3(kBlock), 0, st0, h->gpart_raw,
                            h->nb2, ssq + s.glob_base, (const Scalars*)nullptr);
+    if (h->nc > 0)
+        hipLaunchKernelGGL((k_con_aprod2<double, double, true>), dim3(h->con_grid), dim3(kBlock), 0,
+                           st0, h->nc, h->con_rowptr, h->con_col, h->con_val,
+                           (const double*)nullptr, ssq, (const Scalars*)nullptr);
     hipLaunchKernelGGL(k_make_p, dim3(h->nbc), dim3(kBlock), 0, st0, n, ssq, h->p, h->precondition);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st0);
@@ -1316,6 +1407,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h)
     dfree(h->partxx);
     dfree(h->gpart_raw);
     dfree(h->flag);
+    dfree(h->con_ssq);
     dfree(h->sc);
     if (h->sc_host) (void)hipHostFree(h->sc_host);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
@@ -1573,6 +1665,8 @@ lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32
     if (h->generic)
         return fail(LSQR_E_UNSUPPORTED,
                     "batched solves are built for the 5 + 3x4 + 6 + 1 row layout only");
+    if (h->nc > 0)
+        return fail(LSQR_E_UNSUPPORTED, "batched solves are built without constraint rows");
     HIP_TRY(hipStreamSynchronize(h->user_stream));
     h->var_valid = 0;
     LSQR_TRY(ensure_att(h));

@@ -47,7 +47,9 @@ class _System(ctypes.Structure):
                 ("precondition", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("values", ctypes.c_void_p), ("star_of_row", ctypes.c_void_p),
                 ("att_start", ctypes.c_void_p), ("instr_idx", ctypes.c_void_p),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("n_con", ctypes.c_int64),
+                ("con_rowptr", ctypes.c_void_p), ("con_col", ctypes.c_void_p),
+                ("con_val", ctypes.c_void_p)]
 
 
 class _Info(ctypes.Structure):
@@ -136,11 +138,15 @@ class LsqrSystem:
 
     values [n_par, m] float64/float32 (n_par = n_astro + 3 x 4 (if n_axes) +
     n_instr + n_glob; 24 for the full layout), star_of_row [m] int64
-    (non-decreasing), att_start [m] int64, instr_idx [n_instr, m] int32."""
+    (non-decreasing), att_start [m] int64, instr_idx [n_instr, m] int32;
+    optional constraint rows below the observations, CSR on the device:
+    con_rowptr [n_con + 1] int64, con_col [nnz] int64, con_val [nnz] float64.
+    Row vectors (b, y) then have m_obs + n_con entries (self.m)."""
 
     def __init__(self, values, star_of_row, att_start, instr_idx, n_stars: int, n_dfa: int,
                  n_instr_cols: int, precondition: bool = True, stream=None, n_astro: int = 5,
-                 n_axes: int = 3, n_par_axis: int = 4, n_instr: int = 6, n_glob: int = 1):
+                 n_axes: int = 3, n_par_axis: int = 4, n_instr: int = 6, n_glob: int = 1,
+                 con_rowptr=None, con_col=None, con_val=None):
         import torch
 
         lib = load_library()
@@ -148,8 +154,17 @@ class LsqrSystem:
         n_par = n_astro + n_axes * n_par_axis + n_instr + n_glob
         if values.dtype not in (torch.float64, torch.float32):
             raise TypeError("values must be float64 or float32")
-        self._keep = (values, star_of_row, att_start, instr_idx)
-        self.m = m
+        n_con = 0 if con_rowptr is None else int(con_rowptr.shape[0]) - 1
+        con_ptrs = (ctypes.c_void_p(0),) * 3
+        if n_con > 0:
+            nnz = int(con_col.shape[0])
+            con_ptrs = (_dev_ptr(con_rowptr, torch.int64, (n_con + 1,), "con_rowptr"),
+                        _dev_ptr(con_col, torch.int64, (nnz,), "con_col"),
+                        _dev_ptr(con_val, torch.float64, (nnz,), "con_val"))
+        self._keep = (values, star_of_row, att_start, instr_idx, con_rowptr, con_col, con_val)
+        self.m_obs = m
+        self.n_con = n_con
+        self.m = m + n_con
         self.dtype = values.dtype
         self.device = values.device
         stream = stream if stream is not None else torch.cuda.current_stream(values.device)
@@ -166,7 +181,8 @@ class LsqrSystem:
                        else ctypes.c_void_p(0)),
             instr_idx=(_dev_ptr(instr_idx, torch.int32, (n_instr, m), "instr_idx") if n_instr
                        else ctypes.c_void_p(0)),
-            stream=ctypes.c_void_p(stream.cuda_stream))
+            stream=ctypes.c_void_p(stream.cuda_stream), n_con=n_con, con_rowptr=con_ptrs[0],
+            con_col=con_ptrs[1], con_val=con_ptrs[2])
         h = ctypes.c_void_p()
         with torch.cuda.device(values.device):
             _check(lib.lsqr_create(ctypes.byref(desc), ctypes.byref(h)))
@@ -176,8 +192,9 @@ class LsqrSystem:
         self.n = int(n.value)
 
     @classmethod
-    def from_host(cls, system, device="cuda:0", precondition=True):
-        """Upload a synth.System to the GPU and create a handle."""
+    def from_host(cls, system, device="cuda:0", precondition=True, con=None):
+        """Upload a synth.System (and optional constraint rows with rowptr, col,
+        val host arrays) to the GPU and create a handle."""
         import torch
 
         sp = system.spec
@@ -185,6 +202,10 @@ class LsqrSystem:
                  star_of_row=torch.from_numpy(system.star_of_row).to(device),
                  att_start=torch.from_numpy(system.att_start).to(device),
                  instr_idx=torch.from_numpy(system.instr_idx).to(device))
+        if con is not None:
+            t.update(con_rowptr=torch.from_numpy(con.rowptr).to(device),
+                     con_col=torch.from_numpy(con.col).to(device),
+                     con_val=torch.from_numpy(con.val).to(device))
         torch.cuda.synchronize(device)
         return cls(**t, n_stars=sp.n_stars, n_dfa=sp.n_dfa, n_instr_cols=sp.n_instr_cols,
                    precondition=precondition, n_astro=sp.n_astro, n_axes=sp.n_axes,

@@ -70,7 +70,7 @@ def _load_gpu():
                                ctypes.c_uint32, ctypes.c_double)
     lib.synth_gpu_star_of_row.argtypes = [P, i64, i64, P, P]
     lib.synth_gpu_rows.argtypes = [u64, i64, i64, i64, P, i32, i32, i32, i64, i32, i64, i32,
-                                   f64, f64, i32, P, P, P, P]
+                                   f64, f64, f64, i32, P, P, P, P]
     lib.synth_gpu_normals.argtypes = [u64, u32, i64, i64, f64, P, P]
     for f in (lib.synth_gpu_star_of_row, lib.synth_gpu_rows, lib.synth_gpu_normals):
         f.restype = ctypes.c_int
@@ -95,7 +95,7 @@ def _load():
     lib.synth_star_of_row.argtypes = [P, i64, i64, i64, P]
     lib.synth_star_of_row.restype = None
     lib.synth_rows.argtypes = [u64, i64, i64, i64, P, i32, i32, i32, i64, i32, i64, i32,
-                               f64, f64, i32, P, P, P]
+                               f64, f64, f64, i32, P, P, P]
     lib.synth_rows.restype = None
     lib.synth_normals.argtypes = [u64, u32, i64, i64, f64, P]
     lib.synth_normals.restype = None
@@ -143,8 +143,15 @@ class Spec:
     n_instr: int = 6
     n_glob: int = 1
     astro_scale: tuple | None = None  # (lo, hi) exponent range of 10^U(lo,hi)
+    # correlation rho in [0, 1) of astrometric coefficients 1.. with the first
+    # (harder conditioning: kappa of the scaled per-star blocks ~ 1/sqrt(1-rho))
+    astro_corr: float = 0.0
     noise_sigma: float = 1e-6
     n_rhs: int = 1
+
+    def __post_init__(self):
+        if not 0.0 <= self.astro_corr < 1.0:
+            raise ValueError("astro_corr must be in [0, 1)")
 
     @property
     def n_par(self) -> int:
@@ -221,7 +228,7 @@ def rows(spec: Spec, first_row: np.ndarray, r0: int, r1: int, values_out=None,
     lo, hi = spec.astro_scale if spec.astro_scale else (0.0, 0.0)
     lib.synth_rows(spec.seed, r0, r1, nr, _ptr(star), spec.n_astro, spec.n_axes,
                    spec.n_par_axis, spec.n_dfa, spec.n_instr, spec.n_instr_cols, spec.n_glob,
-                   float(lo), float(hi), 0 if vdt is np.float64 else 1,
+                   float(lo), float(hi), float(spec.astro_corr), 0 if vdt is np.float64 else 1,
                    _ptr(values), _ptr(att), _ptr(instr))
     return values, star, att, instr
 
@@ -232,6 +239,54 @@ def make_system(spec: Spec) -> System:
     values, star, att, instr = rows(spec, first, 0, m)
     return System(spec=spec, first_row=first, values=values, star_of_row=star,
                   att_start=att, instr_idx=instr)
+
+
+@dataclass
+class Constraints:
+    """Extra equations appended below the observation rows, in CSR form:
+    row r has the coefficients val[rowptr[r]:rowptr[r+1]] at the unknowns
+    col[rowptr[r]:rowptr[r+1]]."""
+    rowptr: np.ndarray  # [n_con + 1] int64
+    col: np.ndarray     # [nnz] int64
+    val: np.ndarray     # [nnz] float64
+
+    @property
+    def n_con(self) -> int:
+        return int(self.rowptr.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.rowptr[-1])
+
+
+def constraints(spec: Spec, n_con: int, nnz=(0, 200), seed: int = 0,
+                cols: tuple | None = None, row_norm: float | None = None) -> Constraints:
+    """n_con constraint rows: each row draws its length uniformly in
+    [nnz[0], nnz[1]] (at most the number of candidate columns), distinct
+    columns uniformly from [cols[0], cols[1]) (default: every unknown) in
+    ascending order, and N(0, 1) coefficients, rescaled so that every
+    non-empty row has 2-norm row_norm when given (sqrt(n_par) weighs a
+    constraint like an observation). The paper leaves the content of its
+    constraint equations to another work; these rows have its structure (few
+    rows at the bottom of the system, long and sparse)."""
+    lo_c, hi_c = cols if cols is not None else (0, spec.n_cols)
+    span = hi_c - lo_c
+    rng = np.random.default_rng([spec.seed, 7, seed])
+    lens = rng.integers(nnz[0], nnz[1] + 1, size=n_con)
+    lens = np.minimum(lens, span)
+    rowptr = np.zeros(n_con + 1, dtype=np.int64)
+    np.cumsum(lens, out=rowptr[1:])
+    col = np.empty(int(rowptr[-1]), dtype=np.int64)
+    for r in range(n_con):
+        pick = rng.choice(span, size=int(lens[r]), replace=False)
+        col[rowptr[r]:rowptr[r + 1]] = np.sort(pick) + lo_c
+    val = rng.standard_normal(int(rowptr[-1]))
+    if row_norm is not None:
+        for r in range(n_con):
+            sl = slice(int(rowptr[r]), int(rowptr[r + 1]))
+            if sl.stop > sl.start:
+                val[sl] *= row_norm / np.linalg.norm(val[sl])
+    return Constraints(rowptr=rowptr, col=col, val=val)
 
 
 def x_true(spec: Spec) -> np.ndarray:
@@ -280,7 +335,8 @@ def device_system(spec: Spec, device="cuda:0"):
     lo, hi = spec.astro_scale if spec.astro_scale else (0.0, 0.0)
     rc = lib.synth_gpu_rows(spec.seed, 0, m, m, star.data_ptr(), spec.n_astro, spec.n_axes,
                             spec.n_par_axis, spec.n_dfa, spec.n_instr, spec.n_instr_cols,
-                            spec.n_glob, float(lo), float(hi), 0 if vdt == torch.float64 else 1,
+                            spec.n_glob, float(lo), float(hi), float(spec.astro_corr),
+                            0 if vdt == torch.float64 else 1,
                             values.data_ptr(), att.data_ptr(), instr.data_ptr(), stream)
     if rc != 0:
         raise RuntimeError(f"synth_gpu_rows failed ({rc})")

@@ -159,6 +159,7 @@ typedef struct synth_params {
     int32_t n_astro, n_axes, n_par_axis, n_instr, n_glob, value_kind;
     int64_t n_dfa, n_instr_cols;
     double scale_lo, scale_hi; /* astrometric column scale 10^U(lo,hi) when lo < hi */
+    double corr;               /* correlation rho in [0, 1) of astrometric coefficients 1.. with 0 */
 } synth_params;
 
 #define SYNTH_MAX_PAR 32
@@ -202,6 +203,13 @@ SYNTH_FN void synth_row(uint64_t seed, int64_t i, int64_t s, const synth_params*
         synth_normal2(seed, 1u, (uint64_t)i, (uint32_t)g, &a, &b);
         z[2 * g] = a;
         if (2 * g + 1 < n_par) z[2 * g + 1] = b;
+    }
+    if (P->corr > 0.0) {
+        /* z_j <- rho z_0 + sqrt(1 - rho^2) z_j for the astrometric j >= 1: unit
+           variance, correlation rho with z_0 (rho^2 between the others), so the
+           per-star blocks become ill-conditioned whatever the column scaling */
+        const double c = sqrt((1.0 - P->corr) * (1.0 + P->corr));
+        for (int32_t j = 1; j < P->n_astro; ++j) z[j] = P->corr * z[0] + c * z[j];
     }
     if (P->scale_lo < P->scale_hi) {
         for (int32_t j = 0; j < P->n_astro; ++j) {

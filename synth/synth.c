@@ -48,13 +48,13 @@ void synth_star_of_row(const int64_t* first_row, int64_t n_stars, int64_t r0, in
 void synth_rows(uint64_t seed, int64_t r0, int64_t r1, int64_t ld, const int64_t* star_of_row,
                 int32_t n_astro, int32_t n_axes, int32_t n_par_axis, int64_t n_dfa,
                 int32_t n_instr, int64_t n_instr_cols, int32_t n_glob, double scale_lo,
-                double scale_hi, int32_t value_kind, void* values, int64_t* att_start,
-                int32_t* instr_idx)
+                double scale_hi, double corr, int32_t value_kind, void* values,
+                int64_t* att_start, int32_t* instr_idx)
 {
     synth_params P;
     P.n_astro = n_astro; P.n_axes = n_axes; P.n_par_axis = n_par_axis; P.n_instr = n_instr;
     P.n_glob = n_glob; P.value_kind = value_kind; P.n_dfa = n_dfa; P.n_instr_cols = n_instr_cols;
-    P.scale_lo = scale_lo; P.scale_hi = scale_hi;
+    P.scale_lo = scale_lo; P.scale_hi = scale_hi; P.corr = corr;
     const int32_t n_par = n_astro + n_axes * n_par_axis + n_instr + n_glob;
     #pragma omp parallel for schedule(static)
     for (int64_t i = r0; i < r1; ++i) {

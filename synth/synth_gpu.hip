@@ -84,7 +84,7 @@ int synth_gpu_star_of_row(const int64_t* first_row, int64_t n_stars, int64_t m, 
 int synth_gpu_rows(uint64_t seed, int64_t r0, int64_t r1, int64_t ld, const int64_t* star,
                    int32_t n_astro, int32_t n_axes, int32_t n_par_axis, int64_t n_dfa,
                    int32_t n_instr, int64_t n_instr_cols, int32_t n_glob, double scale_lo,
-                   double scale_hi, int32_t value_kind, void* values, int64_t* att,
+                   double scale_hi, double corr, int32_t value_kind, void* values, int64_t* att,
                    int32_t* instr, void* stream)
 {
     synth_params P;
@@ -98,6 +98,7 @@ int synth_gpu_rows(uint64_t seed, int64_t r0, int64_t r1, int64_t ld, const int6
     P.n_instr_cols = n_instr_cols;
     P.scale_lo = scale_lo;
     P.scale_hi = scale_hi;
+    P.corr = corr;
     if (n_astro + n_axes * n_par_axis + n_instr + n_glob > SYNTH_MAX_PAR || n_instr > SYNTH_MAX_INSTR)
         return -1;
     const int g = grid_for(r1 - r0);

@@ -38,6 +38,15 @@ def dense_matrix(S):
     return np.hstack([astro, att, instr, glob])
 
 
+def with_constraints(A, con):
+    """A with the constraint rows (CSR rowptr/col/val) appended below it."""
+    extra = np.zeros((con.rowptr.shape[0] - 1, A.shape[1]))
+    for r in range(extra.shape[0]):
+        sl = slice(int(con.rowptr[r]), int(con.rowptr[r + 1]))
+        np.add.at(extra[r], con.col[sl], con.val[sl])
+    return np.vstack([A, extra])
+
+
 def cgls(A, b, iters):
     """Conjugate gradients on the normal equations (Hestenes-Stiefel form of
     CGLS, Bjorck 1996, Alg. 7.4.1); iterates equal LSQR's in exact arithmetic."""

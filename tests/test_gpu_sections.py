@@ -28,8 +28,11 @@ LAYOUTS = {
     "mixed_f32": dict(n_astro=4, n_instr=5, n_glob=2, value_dtype="f32"),
 }
 
-# fixed iteration counts well below the unknown count (25 on instr_glob_only)
-ITN = {"instr_glob_only": 10, "mixed_huge_instr": 30}
+# Fixed iteration counts: well below the unknown count (25 on
+# instr_glob_only), and past the window in which mixed_f32's iterates are
+# sensitive to rounding while LSQR converges (oracle vs SciPy's LSQR: 1.9e-11
+# at 20 iterations, 8.6e-9 at 30, 1.1e-12 at 40, 1e-15 at 50).
+ITN = {"instr_glob_only": 10, "mixed_huge_instr": 30, "mixed_f32": 60}
 
 _SYS = {}
 

@@ -17,7 +17,7 @@ import scipy.sparse.linalg
 
 import oracle
 import synth
-from dense_ref import cgls, dense_matrix
+from dense_ref import cgls, dense_matrix, with_constraints
 
 ORACLE_SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                           "oracle", "oracle.c")
@@ -311,11 +311,61 @@ def check_section_layouts():
         assert np.max(np.abs(x_orc - x_ls)) <= 1e-9 * np.max(np.abs(x_ls)), (name, info)
 
 
+def _with_empty_row(con, at):
+    rp = np.insert(con.rowptr, at + 1, con.rowptr[at])
+    return synth.Constraints(rowptr=rp, col=con.col, val=con.val)
+
+
+def constraint_cases():
+    """(system, constraints, name): a full-layout system with long sparse
+    constraint rows (one empty), and an astrometric-only system whose stars
+    have 2..4 observations (rank-deficient blocks) that the constraint rows
+    over the astrometric columns make full rank."""
+    if "con" not in _CACHE:
+        S1 = synth.make_system(synth.tiny(seed=5))
+        C1 = _with_empty_row(synth.constraints(S1.spec, 6, nnz=(1, 90), seed=1), 2)
+        sp2 = synth.tiny(seed=17, n_stars=6, obs=(2, 4), n_axes=0, n_instr=0, n_glob=0)
+        S2 = synth.make_system(sp2)
+        C2 = synth.constraints(sp2, 24, nnz=(6, 14), seed=2)
+        _CACHE["con"] = [(S1, C1, "full_layout"), (S2, C2, "rank_deficient")]
+    return _CACHE["con"]
+
+
+def check_constraints():
+    rng = np.random.default_rng(8)
+    for S, C, name in constraint_cases():
+        o = oracle.OracleSystem.from_synth(S, con=C)
+        A0 = dense_matrix(S)
+        A = with_constraints(A0, C)
+        assert A.shape == (o.m, o.n) and o.m == S.m + C.n_con
+        x = rng.standard_normal(o.n)
+        y = rng.standard_normal(o.m)
+        assert rel(o.aprod1(x, y), y + A @ x) < 1e-13, name
+        assert rel(o.aprod2(y, x), x + A.T @ y) < 1e-13, name
+        cn = np.linalg.norm(A, axis=0)
+        p = np.where(cn > 0, 1.0 / np.where(cn > 0, cn, 1.0), 1.0)
+        assert rel(o.precond(), p) < 1e-13, name
+        b = A @ rng.standard_normal(o.n) + 1e-3 * rng.standard_normal(o.m)
+        for k in (2, 5, 12):  # iterates and estimates: SciPy's LSQR on the scaled matrix
+            xo, info = o.lsqr(b, k, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+            res = scipy.sparse.linalg.lsqr(A * p[None, :], b, atol=0.0, btol=0.0, conlim=0.0,
+                                           iter_lim=k)
+            assert rel(xo, p * res[0]) < 1e-11, (name, k)
+            assert abs(info.rnorm - res[3]) <= 1e-11 * res[3], (name, k)
+        # the constraints complete the rank; converged solution = LAPACK's
+        assert np.linalg.matrix_rank(A) == o.n, name
+        if name == "rank_deficient":
+            assert np.linalg.matrix_rank(A0) < o.n
+        xo, info = o.lsqr(b, 5000, atol=1e-14, btol=1e-14, conlim=0.0)
+        x_ls = np.linalg.lstsq(A, b, rcond=None)[0]
+        assert rel(xo, x_ls) < 1e-9, (name, info)
+
+
 CHECKS = [check_aprod_dense, check_adjoint_identity, check_unit_columns, check_norm_eq4,
           check_precond_dense, check_lstsq, check_scipy_iterates, check_scipy_stopping,
           check_cgls, check_first_iterate_closed_form, check_recurrence_invariants,
           check_noise_free_recovery, check_precondition_invariance, check_special_cases,
-          check_variance_limit, check_section_layouts]
+          check_variance_limit, check_section_layouts, check_constraints]
 
 
 @pytest.mark.parametrize("check", CHECKS, ids=[c.__name__ for c in CHECKS])
@@ -341,6 +391,13 @@ MUTANTS = {
     "precond_no_sqrt": ("1.0 / sqrt(ssq[j])", "1.0 / ssq[j]"),
     "anorm_drop_beta": ("anorm * anorm + alpha * alpha + beta * beta",
                         "anorm * anorm + alpha * alpha"),
+    "con_aprod1_overwrite": ("y[s->m + r] += sum;", "y[s->m + r] = sum;"),
+    "con_aprod2_row": ("x[s->con_col[e]] += s->con_val[e] * y[s->m + r];",
+                       "x[s->con_col[e]] += s->con_val[e] * y[s->m];"),
+    "con_norm_unsquared": ("ssq[s->con_col[e]] += s->con_val[e] * s->con_val[e];",
+                           "ssq[s->con_col[e]] += fabs(s->con_val[e]);"),
+    "con_unscaled": ("con_scaled[e] = s->con_val[e] * p[s->con_col[e]];",
+                     "con_scaled[e] = s->con_val[e];"),
 }
 
 

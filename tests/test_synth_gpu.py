@@ -21,7 +21,9 @@ def torch_cuda():
     synth.tiny(seed=41, n_stars=500, obs=(50, 150), n_dfa=700, n_instr_cols=300),
     synth.tiny(seed=42, n_stars=300, obs=(90, 110), n_dfa=900, n_instr_cols=2000,
                value_dtype="f32", astro_scale=(-2.0, 2.0)),
-], ids=["c0", "uneven", "f32_scaled"])
+    synth.tiny(seed=43, n_stars=300, obs=(20, 60), n_dfa=150, n_instr_cols=23,
+               astro_corr=0.999, n_glob=3, n_instr=4),
+], ids=["c0", "uneven", "f32_scaled", "correlated_sections"])
 def test_device_generator_is_bit_identical(torch_cuda, spec):
     torch = torch_cuda
     print(f"generator twin: seed={spec.seed} dtype={spec.value_dtype}", flush=True)
