@@ -25,29 +25,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
-# Algorithmic bytes per row and launch (FP64 values, configured index layout:
-# int64 star, int64 attitude start, 6 int32 instrumental indices = 40 B).
-#   aprod1: 24 values + indices + u read and written
-#   aprod2: 24 values + indices + u read
-#   fused pass: as aprod1 (A is read once for both products)
-#   attitude pass: 12 attitude values in bucket order + int32 local start + u
-#   (read in bucket order)
-BYTES_PER_ROW = {"aprod1": 24 * 8 + 40 + 16, "aprod2": 24 * 8 + 40 + 8,
-                 "fused": 24 * 8 + 40 + 16, "attitude": 12 * 8 + 4 + 8}
-# FP32 values with FP32 work vectors (the inner solve of the refinement)
-BYTES_PER_ROW_F32 = {"aprod1": 24 * 4 + 40 + 8, "aprod2": 24 * 4 + 40 + 4,
-                     "fused": 24 * 4 + 40 + 8, "attitude": 12 * 4 + 4 + 4}
 
 
-def pass_names(fused: bool):
-    """Names of the two timed row passes of an iteration."""
-    return ("fused", "attitude") if fused else ("aprod1", "aprod2")
+def bytes_per_row(vb: int, ub: int):
+    """Algorithmic bytes per row and launch of each row pass, for values of vb
+    bytes and a row vector u of ub bytes (index layout: int64 star, int64
+    attitude start, 6 int32 instrumental indices = 40 B; in bucket order an
+    int32 local attitude start):
+      aprod1: 24 values + indices + u read and written
+      aprod2: 24 values + indices + u read
+      fused (fused mode 1): as aprod1, A read once for both products
+      attitude_dot (mode 2): 12 attitude values + local start + u read and
+        written, in bucket order
+      fused_rest (mode 2): the 12 other values + star and instrumental
+        indices + u read and written
+      attitude: 12 attitude values + local start + u read, in bucket order"""
+    return {"aprod1": 24 * vb + 40 + 2 * ub, "aprod2": 24 * vb + 40 + ub,
+            "fused": 24 * vb + 40 + 2 * ub, "attitude_dot": 12 * vb + 4 + 2 * ub,
+            "fused_rest": 12 * vb + 32 + 2 * ub, "attitude": 12 * vb + 4 + ub}
 
 
-def pass_times(kt, fused: bool):
-    a, b = pass_names(fused)
-    return {a: kt["aprod1_ms"] / max(1, kt["aprod1_n"]),
-            b: kt["aprod2_ms"] / max(1, kt["aprod2_n"])}
+BYTES_PER_ROW = bytes_per_row(8, 8)      # FP64 values and vectors
+BYTES_PER_ROW_F32 = bytes_per_row(4, 4)  # the FP32 inner solve of the refinement
+
+
+def pass_times(g, mode: int):
+    """Per-iteration milliseconds of the row passes of the last profiled solve
+    (fused mode 2: attitude pre-pass, rest of the fused pass, attitude pass;
+    1: fused pass, attitude pass; 0: aprod1, aprod2)."""
+    pt = g.pass_times()
+    per = {k: ms / max(1, n) for k, (ms, n) in pt.items()}
+    if mode == 2:
+        return {"attitude_dot": per["pre"], "fused_rest": per["fused"],
+                "attitude": per["attitude"]}
+    a, b = ("fused", "attitude") if mode == 1 else ("aprod1", "aprod2")
+    return {a: per["pre"] + per["fused"], b: per["attitude"]}
 
 
 def log(*a):
@@ -151,9 +163,8 @@ def refine_leg(cfg: int, dev):
     # per-iteration kernel times of the FP32 inner loop
     g.set_option("profile", 1)
     g.solve_refined(b, 20, atol=0.0, btol=0.0, outer_limit=1)
-    kt = g.kernel_times()
     g.set_option("profile", 0)
-    ms = pass_times(kt, True)
+    ms = pass_times(g, 2)
     out.update({
         "fp64_seconds": t_fp64, "fp64_itn": i64.itn, "fp64_istop": i64.istop,
         "refined_seconds": t_ref, "refined_inner_itn": i32.itn,
@@ -189,8 +200,8 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
     b = synth.device_noise(spec, m, 0, dev)
     g.aprod1(synth.device_x_true(spec, dev), b)
     out = {}
-    for fused, att, scan, il in ((1, 1, 0, 1), (1, 1, 0, 0), (0, 1, 0, 1), (0, 1, 0, 0),
-                                 (0, 1, 1, 1), (0, 0, 0, 1)):
+    for fused, att, scan, il in ((2, 1, 0, 1), (1, 1, 0, 1), (1, 1, 0, 0), (0, 1, 0, 1),
+                                 (0, 1, 0, 0), (0, 1, 1, 1), (0, 0, 0, 1)):
         g.set_option("fused", fused)
         g.set_option("att_mode", att)
         g.set_option("astro_scan", scan)
@@ -199,8 +210,8 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
         g.set_option("profile", 1)
         g.solve(b, 2, atol=0.0, btol=0.0)
         x, info = g.solve(b, itn, atol=0.0, btol=0.0)
-        ms = pass_times(g.kernel_times(), bool(fused and att == 1))
-        key = ("fused_" if fused else "") + ("atomics", "bucket_pass")[att] + \
+        ms = pass_times(g, fused if att == 1 else 0)
+        key = ("", "fused_", "fused_att_dot_")[fused] + ("atomics", "bucket_pass")[att] + \
             ("_scan" if scan else "_flush") + ("" if il else "_plain_att_gathers")
         out[key] = {**{f"{k}_ms": v for k, v in ms.items()},
                     "iteration_rows_ms": sum(ms.values()), "rnorm": info.rnorm}
@@ -216,8 +227,8 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
         g.set_option("profile", 1)
         g.solve(b, 2, atol=0.0, btol=0.0)
         x, info = g.solve(b, itn, atol=0.0, btol=0.0)
-        ms = pass_times(g.kernel_times(), True)
-        key = f"fused_att_buckets_{nbk}"
+        ms = pass_times(g, 2)
+        key = f"fused_att_dot_buckets_{nbk}"
         out[key] = {**{f"{k}_ms": v for k, v in ms.items()},
                     "iteration_rows_ms": sum(ms.values()), "rnorm": info.rnorm}
         log(f"{key}: " + ", ".join(f"{k} {v:.3f} ms" for k, v in ms.items()))
@@ -335,14 +346,14 @@ def largest_leg(cfg: int, dev):
     g.set_option("profile", 1)
     g.set_option("tests", 0)
     g.solve(b, 16, atol=0.0, btol=0.0)
-    ms64 = pass_times(g.kernel_times(), True)
+    ms64 = pass_times(g, 2)
     g.solve_refined(b, 16, atol=0.0, btol=0.0, outer_limit=1)
-    ms32 = pass_times(g.kernel_times(), True)
+    ms32 = pass_times(g, 2)
     g.set_option("profile", 0)
     g.set_option("tests", 1)
-    # FP64 arithmetic on FP32 values: 24 x 4 + 40 + u 16 per fused row, 12 x 4 + 4 + 8
-    # per attitude row; the FP32 inner solve: BYTES_PER_ROW_F32
-    bpr64 = {"fused": 24 * 4 + 40 + 16, "attitude": 12 * 4 + 4 + 8}
+    # FP64 arithmetic on FP32 values (FP64 row vector); the FP32 inner solve:
+    # BYTES_PER_ROW_F32
+    bpr64 = bytes_per_row(4, 8)
     out.update({
         "fp64_seconds": t_fp64, "fp64_itn": i64.itn, "fp64_istop": i64.istop,
         "refined_seconds": t_ref, "refined_inner_itn": i32.itn,
@@ -464,7 +475,7 @@ def main():
     wall = time.perf_counter() - t1
     kt = g.kernel_times()
     assert info.itn == args.steps and kt["aprod1_n"] == args.steps == kt["aprod2_n"]
-    ms = pass_times(kt, True)
+    ms = pass_times(g, 2)
     gbps = {k: BYTES_PER_ROW[k] * m / (ms[k] * 1e-3) / 1e9 for k in ms}
     dom = max(ms, key=ms.get)
     # counter-measured HBM bytes per launch (committed profile of this workload)
@@ -480,19 +491,26 @@ def main():
     torch.cuda.synchronize()
     wall_graph = time.perf_counter() - t2
 
-    # the same iterations with separate aprod1 / aprod2 launches
-    g.set_option("fused", 0)
-    g.set_option("profile", 1)
-    g.solve(b, 2, atol=0.0, btol=0.0)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    g.solve(b, args.steps, atol=0.0, btol=0.0)
-    torch.cuda.synchronize()
-    wall_unfused = time.perf_counter() - t3
-    ms_u = pass_times(g.kernel_times(), False)
-    g.set_option("fused", 1)
-    log(f"unfused: {args.steps / wall_unfused:.1f} iter/s; " +
-        ", ".join(f"{k} {v:.3f} ms" for k, v in ms_u.items()))
+    # the same iterations with the attitude dot product inside the fused pass
+    # (fused mode 1) and with separate aprod1 / aprod2 launches (mode 0)
+    other = {}
+    for mode in (1, 0):
+        g.set_option("fused", mode)
+        g.set_option("profile", 1)
+        g.solve(b, 2, atol=0.0, btol=0.0)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        g.solve(b, args.steps, atol=0.0, btol=0.0)
+        torch.cuda.synchronize()
+        wall_m = time.perf_counter() - t3
+        ms_m = pass_times(g, mode)
+        other[mode] = {"iter_per_s": args.steps / wall_m,
+                       "kernels": {k: {"ms": v, "GBps": BYTES_PER_ROW[k] * m / (v * 1e-3) / 1e9,
+                                       "bytes_per_row": BYTES_PER_ROW[k]}
+                                   for k, v in ms_m.items()}}
+        log(f"fused mode {mode}: {args.steps / wall_m:.1f} iter/s; " +
+            ", ".join(f"{k} {v:.3f} ms" for k, v in ms_m.items()))
+    g.set_option("fused", 2)
 
     result = {
         "metric": "LSQR iter/s + aprod HBM GB/s, FP64 vs FP32+refine & batched RHS at 1e-10 err",
@@ -519,10 +537,8 @@ def main():
                         "frac_of_peak": gbps[k] / HBM_PEAK_GBPS,
                         "counter_bytes_per_launch": traffic[k]} for k in ms},
         "graph_iter_per_s": args.steps / wall_graph,
-        "unfused": {"iter_per_s": args.steps / wall_unfused,
-                    "kernels": {k: {"ms": v, "GBps": BYTES_PER_ROW[k] * m / (v * 1e-3) / 1e9,
-                                    "bytes_per_row": BYTES_PER_ROW[k]}
-                                for k, v in ms_u.items()}},
+        "fused_att_in_pass": other[1],
+        "unfused": other[0],
         "solve_info": {"itn": info.itn, "istop": info.istop, "rnorm": info.rnorm},
     }
     g.close()

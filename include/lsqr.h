@@ -156,12 +156,18 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         (x3[3 c + axis], rebuilt before every aprod1; the
  *                         values are then consecutive): 1 (default) or 0
  *                         (three 4-value windows straight from the vector)
- *   LSQR_OPT_FUSED        1 (default): with LSQR_OPT_ATT_MODE 1, each LSQR
- *                         iteration reads A once for aprod1 and the
- *                         astrometric, instrumental and global part of aprod2
- *                         (u~ = Abar v - alpha u is row-local, so every row's new
- *                         value is scattered as soon as it is computed), then
- *                         runs the attitude pass; 0: separate aprod1 and aprod2
+ *   LSQR_OPT_FUSED        with LSQR_OPT_ATT_MODE 1 on the full row layout:
+ *                         1: each LSQR iteration reads A once for aprod1 and
+ *                         the astrometric, instrumental and global part of
+ *                         aprod2 (u~ = Abar v - alpha u is row-local, so every
+ *                         row's new value is scattered as soon as it is
+ *                         computed), then runs the attitude pass;
+ *                         2 (default): the same, with the attitude part of
+ *                         aprod1 computed first by a pass over the rows in
+ *                         bucket order (the bucket's attitude columns of v in
+ *                         LDS, no gathers from global memory) and folded into
+ *                         u~, so the fused pass skips the attitude section;
+ *                         0: separate aprod1 and aprod2
  *   LSQR_OPT_VARIANCE     1: lsqr_solve also accumulates the variance estimate of
  *                         the unknowns, sum over iterations of (w/rho)^2 (Algorithm
  *                         1, variances at the end of each iteration; Paige &
@@ -259,6 +265,13 @@ lsqr_status lsqr_batch_tuning(lsqr_handle* h, int32_t* k_tile, double* ms_per_rh
  * be NULL. */
 lsqr_status lsqr_kernel_times(lsqr_handle* h, double* ms_aprod1, int64_t* n_aprod1,
                               double* ms_aprod2, int64_t* n_aprod2);
+
+/* Per-pass timing of the last solve run with LSQR_OPT_PROFILE = 1 (FP64 or
+ * refined, not batched): ms[0] the attitude pre-pass of fused mode 2 (with the
+ * attitude-interleave copy; 0 in other modes), ms[1] the rest of the aprod1
+ * window (the fused pass, or aprod1), ms[2] the aprod2 window (the attitude
+ * pass, or aprod2); n[i] the iterations timed. Host arrays of 3. */
+lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n);
 
 /* Number of columns n of the handle's system. Host pointer out. */
 lsqr_status lsqr_num_cols(lsqr_handle* h, int64_t* n_out);

@@ -546,7 +546,7 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
 // is applied afterwards by the column kernel (v~ = p .* A^T u~ / beta - beta v),
 // so A is read once per iteration for these sections; the attitude columns
 // are left to the row-reordered pass, which reads u~_{i+1}.
-//   x: vp = p .* v (Acc), x3: its interleaved attitude section (ATTI),
+//   x: vp = p .* v (Acc), x3: its interleaved attitude section (kAttX3),
 //   u: u~ [m], overwritten (row i at u[inv[i]], or u[i] without inv),
 //   part[blockIdx.x]: FP64 sum of squares of the
 //   stored u~, q: A^T u~ accumulator (astro, instr, glob sections),
@@ -554,7 +554,11 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
 // Dynamic LDS: the FP64 histogram of instrumental columns [0, hcols) (see
 // k_att_hist; columns from hcols on are left to k_instr_tail) and, after it,
 // the instrumental slice of x (LDSX, n_instr_cols Acc).
-template <typename T, typename Acc, int NT, bool LDSX, bool ATTI>
+// AM, the attitude part of the dot product: kAttX reads three 4-value windows
+// of x, kAttX3 one 12-value window of x3, kAttPre none: k_att_dot has already
+// replaced u~ by (attitude part of A vp) - coef u~, so the row adds that.
+enum { kAttX = 0, kAttX3 = 1, kAttPre = 2 };
+template <typename T, typename Acc, int NT, bool LDSX, int AM>
 __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ x,
                                                const Acc* __restrict__ x3, Acc* __restrict__ u,
                                                Acc* __restrict__ q, const int64_t* __restrict__ wb,
@@ -604,10 +608,11 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
         const int64_t stc = ldnt(&s.star[ic]);
         const int64_t st = i < re ? stc : kNoStar;
-        const int64_t t = ldnt(&s.att[ic]);
+        const int64_t t = AM == kAttPre ? 0 : ldnt(&s.att[ic]);
         T a[kPar];
 #pragma unroll
-        for (int c = 0; c < kPar; ++c) a[c] = ldnt(&val[c * m + ic]);
+        for (int c = 0; c < kPar; ++c)
+            if (AM != kAttPre || c < kOffAtt || c >= kOffInstr) a[c] = ldnt(&val[c * m + ic]);
         int32_t ix[kInstr];
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
@@ -619,19 +624,24 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         const Acc* xa = x + kAstro * stc;
 #pragma unroll
         for (int j = 0; j < kAstro; ++j) d += (Acc)a[j] * xa[j];
+        if (AM != kAttPre) {
 #pragma unroll
-        for (int ax = 0; ax < kAxes; ++ax) {
+            for (int ax = 0; ax < kAxes; ++ax) {
 #pragma unroll
-            for (int qq = 0; qq < kParAxis; ++qq) {
-                const Acc xv = ATTI ? x3[kAxes * (t + qq) + ax]
-                                    : x[s.att_base + ax * s.n_dfa + t + qq];
-                d += (Acc)a[kOffAtt + ax * kParAxis + qq] * xv;
+                for (int qq = 0; qq < kParAxis; ++qq) {
+                    const Acc xv = AM == kAttX3 ? x3[kAxes * (t + qq) + ax]
+                                                : x[s.att_base + ax * s.n_dfa + t + qq];
+                    d += (Acc)a[kOffAtt + ax * kParAxis + qq] * xv;
+                }
             }
         }
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) d += (Acc)a[kOffInstr + j] * xi[ix[j]];
         d += (Acc)a[kOffGlob] * xg;
-        d -= coef * uo;
+        if (AM == kAttPre)
+            d += uo;
+        else
+            d -= coef * uo;
         if (ok) u[pu] = d;
         if (!ok) d = (Acc)0;
         ssq += (double)d * (double)d;
@@ -1455,11 +1465,56 @@ __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val
     }
 }
 
-// Attitude part of Eq. (3) over the rows in bucket order. Workgroup w covers
-// the g-th of G equal slices of bucket b = w / G (g = w % G): an LDS
-// histogram hist[axis][W + 3] gets a * u for the 12 coefficients of each of
-// its rows, then is stored as S2[w][r][axis][W + 3]; k_att_reduce adds the
-// slices. The histogram and S2 are FP64 whatever Acc is: gfx950's LDS FP64
+// Attitude part of Eq. (2) over the rows in bucket order, folded into the
+// row vector: u~[k] <- sum_c a_c x[col_c] - coef_u u~[k] for the 12 attitude
+// coefficients of row k (u~ in bucket order, coalesced). The G workgroups of
+// a bucket share its rows as in k_att_hist; the bucket's
+// attitude columns [b W, b W + W + 3) of the interleaved copy x3 are staged
+// in LDS first (win[3 c + axis], 3 (W + 3) Acc), so no row gathers from
+// global memory. The fused pass (kAttPre) then adds the other sections.
+template <typename T, typename Acc, int NT>
+__global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__ att_sorted,
+                                                 const int32_t* __restrict__ tloc,
+                                                 const int64_t* __restrict__ bstart,
+                                                 int64_t width, int G, int64_t n_dfa,
+                                                 const Acc* __restrict__ x3, Acc* __restrict__ u,
+                                                 const Scalars* __restrict__ sc)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Acc* win = reinterpret_cast<Acc*>(smem_raw);
+    if (sc->done) return;
+    const int64_t span = width + kParAxis - 1;
+    const int64_t bk = blockIdx.x / G, g = blockIdx.x - bk * G;
+    const int64_t c0 = bk * width;
+    // columns past n_dfa - 1 are never referenced (t + 3 <= n_dfa - 1)
+    const int64_t ncol = span < n_dfa - c0 ? span : n_dfa - c0;
+    for (int64_t e = threadIdx.x; e < kAxes * ncol; e += NT) win[e] = x3[kAxes * c0 + e];
+    __syncthreads();
+    const int64_t b0 = bstart[bk], len = bstart[bk + 1] - b0;
+    const int64_t r1 = b0 + len;
+    const Acc coef = (Acc)sc->coef_u;
+    for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += (int64_t)G * NT) {
+        const int64_t tl = ldnt(&tloc[k]);
+        T a[kAxes * kParAxis];
+#pragma unroll
+        for (int c = 0; c < kAxes * kParAxis; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
+        const Acc uo = u[k];
+        Acc d = (Acc)0;
+#pragma unroll
+        for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+            for (int qq = 0; qq < kParAxis; ++qq)
+                d += (Acc)a[ax * kParAxis + qq] * win[kAxes * (tl + qq) + ax];
+        u[k] = d - coef * uo;
+    }
+}
+
+// Attitude part of Eq. (3) over the rows in bucket order. The G workgroups
+// of bucket b share its rows in interleaved blocks of NT (workgroup w = b G +
+// g takes blocks g, g + G, ..., so the G streams advance through memory
+// together): an LDS histogram hist[axis][W + 3] gets a * u for the 12
+// coefficients of each of its rows, then is stored as S2[w][r][axis][W + 3];
+// k_att_reduce adds the slices. The histogram and S2 are FP64 whatever Acc is: gfx950's LDS FP64
 // atomic add runs at 7.6x the rate of the FP32 one (measured, random
 // addresses over 150 KB: 1550 vs 204 G/s), and the sums are more accurate.
 // U is in bucket order ([m][K], K right-hand sides swept one after another).
@@ -1477,12 +1532,12 @@ __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict_
     const int64_t span = width + kParAxis - 1;
     const int64_t bk = blockIdx.x / G, g = blockIdx.x - bk * G;
     const int64_t b0 = bstart[bk], len = bstart[bk + 1] - b0;
-    const int64_t r0 = b0 + g * len / G, r1 = b0 + (g + 1) * len / G;
+    const int64_t r1 = b0 + len;
     for (int r = 0; r < K; ++r) {
         if (sc != nullptr && (sc[r].done || sc[r].beta_zero)) continue;  // uniform
         for (int64_t e = threadIdx.x; e < kAxes * span; e += NT) hist[e] = 0.0;
         __syncthreads();
-        for (int64_t k = r0 + threadIdx.x; k < r1; k += NT) {
+        for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += (int64_t)G * NT) {
             const int64_t tl = ldnt(&tloc[k]);
             const double uk = (double)U[k * K + r];
             T a[kAxes * kParAxis];  // all loads issued before the first atomic

@@ -209,7 +209,9 @@ struct lsqr_handle {
     int att_mode = 1;    // 0: attitude scatter with device atomics, 1: bucket-order pass
     int astro_scan = 0;  // 1: segmented scan per chunk, 0: accumulate-and-flush segments
     int att_il = 1;      // aprod1 gathers attitude values from the interleaved copy
-    int fused = 1;       // one pass for aprod1 and the non-attitude part of aprod2
+    int fused = 2;       // 1: one pass for aprod1 and the non-attitude part of aprod2;
+                         // 2: the same with the attitude part of aprod1 in a bucket-order
+                         // pre-pass (k_att_dot); 0: separate aprod1 and aprod2
     double outer_tol = 1e-10;
     int ktile = 0;       // batched k-tile: 0 autotune, else 1, 2, 4 or 8
 
@@ -217,6 +219,7 @@ struct lsqr_handle {
     std::vector<hipEvent_t> events;
     double ms1 = 0.0, ms2 = 0.0;
     int64_t n1 = 0, n2 = 0;
+    double ms_pre = 0.0;  // profile: attitude pre-pass share of ms1 (fused mode 2)
 };
 
 namespace {
@@ -234,6 +237,7 @@ inline const int32_t* row_map(const lsqr_handle* h)
 }
 
 inline int64_t att_span(const lsqr_handle* h) { return h->bwidth + kParAxis - 1; }
+constexpr int kEvIter = 5;  // profile events per single-RHS iteration
 inline int64_t att_slices(const lsqr_handle* h) { return h->nbk * h->att_g; }
 
 // ------------------------------------------------------------ launch helpers
@@ -329,27 +333,41 @@ void launch_interleave_att(const lsqr_handle* h, const V* x, V* x3, const Scalar
 
 // The fused pass (aprod1 and the astrometric, instrumental and global part of
 // aprod2 in one sweep) over the main-pass grid.
-template <typename T, typename Acc>
-void launch_fused(const lsqr_handle* h, Path<Acc>& P, hipStream_t st)
+template <typename T, typename Acc, bool LDSX, int AM>
+void launch_fused_as(const lsqr_handle* h, Path<Acc>& P, const Acc* x3, hipStream_t st)
 {
-    const dim3 g(h->nb2), bm(kBlock2);
+    hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, LDSX, AM>), dim3(h->nb2), dim3(kBlock2), P.lds_f,
+                       st, h->sv, (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1,
+                       P.hcols, h->sc, row_map(h));
+}
+
+// Attitude part of aprod1 in bucket order, folded into u~ (fused mode 2):
+// x3 must hold the interleaved attitude section of vp.
+template <typename T, typename Acc>
+void launch_att_dot(const lsqr_handle* h, Path<Acc>& P, hipStream_t st)
+{
+    const size_t lds = (size_t)(kAxes * att_span(h)) * sizeof(Acc);
+    hipLaunchKernelGGL((k_att_dot<T, Acc, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock), lds,
+                       st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
+                       (const int64_t*)h->bstart, h->bwidth, h->att_g, h->sv.n_dfa,
+                       (const Acc*)P.vp3, P.u, h->sc);
+}
+
+// pre: the attitude part of the row products is already in u~ (fused mode 2)
+template <typename T, typename Acc>
+void launch_fused(const lsqr_handle* h, Path<Acc>& P, hipStream_t st, bool pre)
+{
     const Acc* x3 = h->att_il ? (const Acc*)P.vp3 : nullptr;
-    if (P.f_ldsx && x3)
-        hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, true, true>), g, bm, P.lds_f, st, h->sv,
-                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.hcols,
-                           h->sc, row_map(h));
-    else if (P.f_ldsx)
-        hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, true, false>), g, bm, P.lds_f, st, h->sv,
-                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.hcols,
-                           h->sc, row_map(h));
-    else if (x3)
-        hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, false, true>), g, bm, P.lds_f, st, h->sv,
-                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.hcols,
-                           h->sc, row_map(h));
-    else
-        hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, false, false>), g, bm, P.lds_f, st, h->sv,
-                           (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1, P.hcols,
-                           h->sc, row_map(h));
+    if (pre) {
+        if (P.f_ldsx) launch_fused_as<T, Acc, true, kAttPre>(h, P, nullptr, st);
+        else launch_fused_as<T, Acc, false, kAttPre>(h, P, nullptr, st);
+    } else if (P.f_ldsx) {
+        if (x3) launch_fused_as<T, Acc, true, kAttX3>(h, P, x3, st);
+        else launch_fused_as<T, Acc, true, kAttX>(h, P, x3, st);
+    } else {
+        if (x3) launch_fused_as<T, Acc, false, kAttX3>(h, P, x3, st);
+        else launch_fused_as<T, Acc, false, kAttX>(h, P, x3, st);
+    }
     launch_instr_tail<T, Acc, 1, false>(h, P.u, row_map(h), P.q, P.hcols, h->sc, st);
 }
 
@@ -416,17 +434,21 @@ inline bool use_fused(const lsqr_handle* h)
     return h->fused && att_pass_on(h) && !h->generic;
 }
 
-// One LSQR iteration; ev (optional) = 4 events bracketing aprod1 and aprod2
-// (with the fused pass: that pass, and the attitude pass).
+// One LSQR iteration; ev (optional) = kEvIter events: [0, 1] around aprod1
+// (with the fused pass: the attitude pre-pass, if any, and that pass), [2, 3]
+// around aprod2 (the attitude pass), [4] after the pre-pass.
 template <typename T, typename Acc>
 void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* ev)
 {
     const int64_t n = h->sv.n;
     if (ev) (void)hipEventRecord(ev[0], st);
-    const bool il = h->att_il && h->sv.natt > 0 && !h->generic;
+    const bool pre = use_fused(h) && h->fused == 2;
+    const bool il = (h->att_il || pre) && h->sv.natt > 0 && !h->generic;
     if (il) launch_interleave_att<Acc>(h, P.vp, P.vp3, h->sc, st);
+    if (pre) launch_att_dot<T, Acc>(h, P, st);
+    if (ev) (void)hipEventRecord(ev[4], st);
     if (use_fused(h)) {
-        launch_fused<T, Acc>(h, P, st);
+        launch_fused<T, Acc>(h, P, st, pre);
         launch_con_aprod1<Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u + h->sv.m, nullptr,
                                                   h->sc, h->part1 + h->nb2, st);
         if (ev) (void)hipEventRecord(ev[1], st);
@@ -654,8 +676,8 @@ lsqr_status run_iterations(lsqr_handle* h, Path<Acc>& P)
         }
         P.graph_chunk = chunk;
     }
-    if (h->profile && h->events.size() < (size_t)4 * chunk) {
-        while (h->events.size() < (size_t)4 * chunk) {
+    if (h->profile && h->events.size() < (size_t)kEvIter * chunk) {
+        while (h->events.size() < (size_t)kEvIter * chunk) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e));
             h->events.push_back(e);
@@ -668,18 +690,21 @@ lsqr_status run_iterations(lsqr_handle* h, Path<Acc>& P)
         } else {
             for (int k = 0; k < chunk; ++k)
                 launch_iteration<T, Acc>(h, P, h->stream,
-                                         h->profile ? &h->events[4 * k] : nullptr);
+                                         h->profile ? &h->events[kEvIter * k] : nullptr);
             HIP_TRY(hipGetLastError());
         }
         LSQR_TRY(read_scalars(h));
         if (h->profile) {
             const int ran = std::min(chunk, h->sc_host->itn - itn_before);
             for (int k = 0; k < ran; ++k) {
-                float a = 0.f, b = 0.f;
-                HIP_TRY(hipEventElapsedTime(&a, h->events[4 * k], h->events[4 * k + 1]));
-                HIP_TRY(hipEventElapsedTime(&b, h->events[4 * k + 2], h->events[4 * k + 3]));
+                hipEvent_t* ev = &h->events[kEvIter * k];
+                float a = 0.f, b = 0.f, c = 0.f;
+                HIP_TRY(hipEventElapsedTime(&a, ev[0], ev[1]));
+                HIP_TRY(hipEventElapsedTime(&b, ev[2], ev[3]));
+                HIP_TRY(hipEventElapsedTime(&c, ev[0], ev[4]));
                 h->ms1 += a;
                 h->ms2 += b;
+                h->ms_pre += c;
                 h->n1 += 1;
                 h->n2 += 1;
             }
@@ -718,7 +743,7 @@ lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_l
     Path<double>& P = h->p64;
     const int64_t m = h->sv.m, n = h->sv.n;
     if (h->profile) {
-        h->ms1 = h->ms2 = 0.0;
+        h->ms1 = h->ms2 = h->ms_pre = 0.0;
         h->n1 = h->n2 = 0;
     }
     LSQR_TRY(upload_controls(h, itn_limit, atol, btol));
@@ -1067,7 +1092,7 @@ lsqr_status batch_autotune(lsqr_handle* h, const double* Bm, int64_t ldb, int32_
 {
     auto& B = h->batch;
     const int saved_profile = h->profile, saved_chunk = h->chunk, saved_tests = h->tests;
-    const double saved[4] = {h->ms1, h->ms2, (double)h->n1, (double)h->n2};
+    const double saved[5] = {h->ms1, h->ms2, (double)h->n1, (double)h->n2, h->ms_pre};
     double* Xs = nullptr;
     LSQR_TRY(dalloc(&Xs, h->sv.n * 8));
     int best = 1;
@@ -1077,7 +1102,7 @@ lsqr_status batch_autotune(lsqr_handle* h, const double* Bm, int64_t ldb, int32_
         h->profile = 1;
         h->tests = 0;
         h->chunk = 3;
-        h->ms1 = h->ms2 = 0.0;
+        h->ms1 = h->ms2 = h->ms_pre = 0.0;
         h->n1 = h->n2 = 0;
         rc = batch_tile_k<T>(h, K, Bm, ldb, Xs, K, 1 << 20, 0.0, 0.0, nullptr, 1);
         if (rc != LSQR_OK) break;
@@ -1096,6 +1121,7 @@ lsqr_status batch_autotune(lsqr_handle* h, const double* Bm, int64_t ldb, int32_
     h->ms2 = saved[1];
     h->n1 = (int64_t)saved[2];
     h->n2 = (int64_t)saved[3];
+    h->ms_pre = saved[4];
     if (rc != LSQR_OK) return rc;
     B.tuned_k = best;
     return LSQR_OK;
@@ -1113,7 +1139,7 @@ lsqr_status solve_batched(lsqr_handle* h, const double* Bm, double* X, int32_t k
     }
     LSQR_TRY(batch_alloc(h, K));
     if (h->profile) {
-        h->ms1 = h->ms2 = 0.0;
+        h->ms1 = h->ms2 = h->ms_pre = 0.0;
         h->n1 = h->n2 = 0;
     }
     int32_t j0 = 0;
@@ -1454,7 +1480,9 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
     }
     case LSQR_OPT_ATT_INTERLEAVE:
     case LSQR_OPT_FUSED: {
-        const int v = value != 0.0 ? 1 : 0;
+        if (option == LSQR_OPT_FUSED && !(value == 0.0 || value == 1.0 || value == 2.0))
+            return fail(LSQR_E_INVALID, "fused mode must be 0, 1 or 2");
+        const int v = option == LSQR_OPT_FUSED ? (int)value : (value != 0.0 ? 1 : 0);
         int& slot = option == LSQR_OPT_FUSED ? h->fused : h->att_il;
         if (slot != v) {
             if (h->p64.graph) (void)hipGraphExecDestroy(h->p64.graph);
@@ -1606,7 +1634,7 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
     Path<float>& P = h->p32;
     const int64_t n = h->sv.n;
     if (h->profile) {
-        h->ms1 = h->ms2 = 0.0;
+        h->ms1 = h->ms2 = h->ms_pre = 0.0;
         h->n1 = h->n2 = 0;
     }
     double* part_d = h->partdd;  // reused: not live between outer steps
@@ -1683,6 +1711,18 @@ lsqr_status lsqr_batch_tuning(lsqr_handle* h, int32_t* k_tile, double* ms_per_rh
     if (k_tile) *k_tile = h->batch.tuned_k;
     if (ms_per_rhs_iter)
         for (int K = 1, i = 0; K <= 8; K *= 2, ++i) ms_per_rhs_iter[i] = h->batch.tuned_ms[K];
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n)
+{
+    if (!h) return fail(LSQR_E_INVALID, "null handle");
+    if (!ms || !n) return fail(LSQR_E_INVALID, "null output");
+    ms[0] = h->ms_pre;
+    ms[1] = h->ms1 - h->ms_pre;
+    ms[2] = h->ms2;
+    n[0] = n[1] = h->n1;
+    n[2] = h->n2;
     return LSQR_OK;
 }
 

@@ -29,7 +29,8 @@ OPTIONS = {"conlim": 1, "tests": 2, "chunk": 3, "graph": 4, "profile": 5, "outer
 SYMBOLS = ("lsqr_create", "lsqr_destroy", "lsqr_set_option", "lsqr_aprod1", "lsqr_aprod2",
            "lsqr_get_precond", "lsqr_get_variance", "lsqr_num_cols", "lsqr_solve",
            "lsqr_solve_refined",
-           "lsqr_solve_batched", "lsqr_batch_tuning", "lsqr_kernel_times", "lsqr_last_error")
+           "lsqr_solve_batched", "lsqr_batch_tuning", "lsqr_kernel_times", "lsqr_pass_times",
+           "lsqr_last_error")
 
 
 class LsqrError(RuntimeError):
@@ -101,6 +102,7 @@ def load_library(path: str = LIB_PATH):
         "lsqr_batch_tuning": ([H, ctypes.POINTER(I32), ctypes.POINTER(F64)], I32),
         "lsqr_kernel_times": ([H, ctypes.POINTER(F64), ctypes.POINTER(I64),
                                ctypes.POINTER(F64), ctypes.POINTER(I64)], I32),
+        "lsqr_pass_times": ([H, ctypes.POINTER(F64), ctypes.POINTER(I64)], I32),
         "lsqr_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -310,3 +312,11 @@ class LsqrSystem:
                                       ctypes.byref(b), ctypes.byref(nb)))
         return {"aprod1_ms": a.value, "aprod1_n": na.value, "aprod2_ms": b.value,
                 "aprod2_n": nb.value}
+
+    def pass_times(self):
+        """Profiled milliseconds and iteration counts of the attitude pre-pass,
+        the fused (aprod1) pass and the attitude (aprod2) pass."""
+        ms = (ctypes.c_double * 3)()
+        n = (ctypes.c_int64 * 3)()
+        _check(_lib.lsqr_pass_times(self._h, ms, n))
+        return {name: (ms[i], n[i]) for i, name in enumerate(("pre", "fused", "attitude"))}

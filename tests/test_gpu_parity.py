@@ -175,12 +175,15 @@ def test_solve_without_interleaved_attitude(torch_cuda, name, itn):
     _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], interleave=0)
 
 
-# The fused pass (default) against separate aprod1/aprod2 launches of the same
-# attitude mode: both must match the oracle.
+# The default iteration (fused mode 2: attitude pre-pass in bucket order, then
+# the fused pass) against fused mode 1 (attitude dot product inside the fused
+# pass) and separate aprod1/aprod2 launches (0): all must match the oracle.
+@pytest.mark.parametrize("fused", [1, 0])
 @pytest.mark.parametrize("name,itn", [("c0", 60), ("ragged", 60), ("one_star", 15),
-                                       ("few_rows", 15), ("wide_instr", 40)])
-def test_solve_unfused(torch_cuda, name, itn):
-    _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], fused=0)
+                                       ("few_rows", 15), ("wide_instr", 40),
+                                       ("wide_att_f32", 30)])
+def test_solve_other_fused_modes(torch_cuda, name, itn, fused):
+    _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], fused=fused)
 
 
 def _solve_fixed(torch_cuda, name, itn, graph, variant, interleave=1, fused=1):
@@ -304,7 +307,8 @@ def test_option_errors(torch_cuda):
     S, o = system("few_rows")
     say("option validation: few_rows")
     g = gpu_system(torch, S)
-    bad = [("att_mode", 2), ("ktile", 3), ("chunk", 0), ("att_buckets", -1), ("outer_tol", -1.0)]
+    bad = [("att_mode", 2), ("ktile", 3), ("chunk", 0), ("att_buckets", -1), ("outer_tol", -1.0),
+           ("fused", 3)]
     for name, value in bad:
         with pytest.raises(LsqrError) as ei:
             g.set_option(name, value)
@@ -450,6 +454,27 @@ def test_harder_conditioning_fp64_and_refined(torch_cuda):
         f"inner itn={info.itn} err={e_ref:.3e}")
     assert e_fix <= 1e-10
     assert e_ref <= 1e-10
+
+
+def test_profile_pass_times(torch_cuda):
+    torch = torch_cuda
+    S, o = system("c0")
+    b = _b(S, o)
+    say("profile pass times: c0 itn=12, fused modes 2 and 1")
+    g = gpu_system(torch, S)
+    g.set_option("tests", 0)
+    g.set_option("profile", 1)
+    g.solve(torch.from_numpy(b).cuda(), 12, atol=0.0, btol=0.0)
+    pt = g.pass_times()
+    assert all(n == 12 for _, n in pt.values()) and all(ms > 0 for ms, _ in pt.values())
+    g.set_option("fused", 1)
+    g.solve(torch.from_numpy(b).cuda(), 12, atol=0.0, btol=0.0)
+    pt1 = g.pass_times()
+    kt = g.kernel_times()
+    g.close()
+    # mode 1 has no pre-pass: the first window holds only the interleave copy
+    assert pt1["pre"][0] < pt1["fused"][0]
+    assert abs(pt1["pre"][0] + pt1["fused"][0] - kt["aprod1_ms"]) <= 1e-6 * kt["aprod1_ms"]
 
 
 def test_profile_counts_launches(torch_cuda):
