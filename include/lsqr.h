@@ -268,10 +268,12 @@ lsqr_status lsqr_kernel_times(lsqr_handle* h, double* ms_aprod1, int64_t* n_apro
 
 /* Per-pass timing of the last solve run with LSQR_OPT_PROFILE = 1 (FP64 or
  * refined, not batched): ms[0] the attitude pre-pass of fused mode 2 (with the
- * attitude-interleave copy; 0 in other modes), ms[1] the rest of the aprod1
- * window (the fused pass, or aprod1), ms[2] the aprod2 window (the attitude
- * pass, or aprod2); n[i] the iterations timed. Host arrays of 3. */
-lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n);
+ * attitude-interleave copy; only that copy in other modes), ms[1] the rest of
+ * the aprod1 window (the fused pass, or aprod1), ms[2] the aprod2 window (the
+ * attitude pass, or aprod2); n[i] the iterations timed. Host arrays of 3.
+ * mode (may be NULL): the fused mode the last FP64 or refined solve ran
+ * (0, 1 or 2, see LSQR_OPT_FUSED). */
+lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n, int32_t* mode);
 
 /* Number of columns n of the handle's system. Host pointer out. */
 lsqr_status lsqr_num_cols(lsqr_handle* h, int64_t* n_out);

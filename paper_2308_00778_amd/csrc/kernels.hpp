@@ -694,13 +694,15 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
 // window, then flushes it with one device atomic per column. U holds K
 // values per row, row i at U[inv[i] K + r] (U[i K + r] without inv); frozen
 // RHS (done or beta_zero) are skipped.
-template <typename T, typename Acc, int K, bool SQUARE, int NT>
+// GEN: section sizes from the system view (general layouts); otherwise the
+// full layout's constants.
+template <typename T, typename Acc, int K, bool SQUARE, int NT, bool GEN>
 __global__ __launch_bounds__(NT) void k_instr_tail(SysView s, const Acc* __restrict__ U,
                                                     const int32_t* __restrict__ inv,
                                                     Acc* __restrict__ Q, int64_t c0, int64_t c1,
                                                     const Scalars* __restrict__ sc)
 {
-    const int ni = s.ni, oins = s.off_instr;
+    const int ni = GEN ? s.ni : kInstr, oins = GEN ? s.off_instr : kOffInstr;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* hist = reinterpret_cast<double*>(smem_raw);
     uint32_t live = 0;

@@ -212,6 +212,7 @@ struct lsqr_handle {
     int fused = 2;       // 1: one pass for aprod1 and the non-attitude part of aprod2;
                          // 2: the same with the attitude part of aprod1 in a bucket-order
                          // pre-pass (k_att_dot); 0: separate aprod1 and aprod2
+    int last_mode = 0;   // fused mode of the last single-RHS solve
     double outer_tol = 1e-10;
     int ktile = 0;       // batched k-tile: 0 autotune, else 1, 2, 4 or 8
 
@@ -259,9 +260,14 @@ void launch_instr_tail(const lsqr_handle* h, const Acc* U, const int32_t* inv, A
     const int64_t tw = std::max<int64_t>(1, kLdsInstrBudget / (8 * K));
     for (int64_t c0 = hcols; c0 < ninst; c0 += tw) {
         const int64_t c1 = std::min(ninst, c0 + tw);
-        hipLaunchKernelGGL((k_instr_tail<T, Acc, K, SQUARE, kAttBlock>), dim3(h->num_cu),
-                           dim3(kAttBlock), (size_t)((c1 - c0) * K * 8), st, h->sv, U, inv, Q, c0,
-                           c1, sc);
+        if (h->generic)
+            hipLaunchKernelGGL((k_instr_tail<T, Acc, K, SQUARE, kAttBlock, true>), dim3(h->num_cu),
+                               dim3(kAttBlock), (size_t)((c1 - c0) * K * 8), st, h->sv, U, inv, Q,
+                               c0, c1, sc);
+        else
+            hipLaunchKernelGGL((k_instr_tail<T, Acc, K, SQUARE, kAttBlock, false>),
+                               dim3(h->num_cu), dim3(kAttBlock), (size_t)((c1 - c0) * K * 8), st,
+                               h->sv, U, inv, Q, c0, c1, sc);
     }
 }
 
@@ -434,6 +440,10 @@ inline bool use_fused(const lsqr_handle* h)
     return h->fused && att_pass_on(h) && !h->generic;
 }
 
+// Effective fused mode of an iteration: 0 separate passes, 1 fused pass with
+// the attitude dot product, 2 attitude pre-pass + fused pass.
+inline int fused_mode(const lsqr_handle* h) { return use_fused(h) ? h->fused : 0; }
+
 // One LSQR iteration; ev (optional) = kEvIter events: [0, 1] around aprod1
 // (with the fused pass: the attitude pre-pass, if any, and that pass), [2, 3]
 // around aprod2 (the attitude pass), [4] after the pre-pass.
@@ -442,7 +452,7 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
 {
     const int64_t n = h->sv.n;
     if (ev) (void)hipEventRecord(ev[0], st);
-    const bool pre = use_fused(h) && h->fused == 2;
+    const bool pre = fused_mode(h) == 2;
     const bool il = (h->att_il || pre) && h->sv.natt > 0 && !h->generic;
     if (il) launch_interleave_att<Acc>(h, P.vp, P.vp3, h->sc, st);
     if (pre) launch_att_dot<T, Acc>(h, P, st);
@@ -658,6 +668,7 @@ lsqr_status read_scalars(lsqr_handle* h)
 template <typename T, typename Acc>
 lsqr_status run_iterations(lsqr_handle* h, Path<Acc>& P)
 {
+    h->last_mode = fused_mode(h);
     const int chunk = std::max(1, h->chunk);
     const bool graph = h->use_graph && !h->profile;
     if (graph && (P.graph == nullptr || P.graph_chunk != chunk)) {
@@ -1714,10 +1725,11 @@ lsqr_status lsqr_batch_tuning(lsqr_handle* h, int32_t* k_tile, double* ms_per_rh
     return LSQR_OK;
 }
 
-lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n)
+lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n, int32_t* mode)
 {
     if (!h) return fail(LSQR_E_INVALID, "null handle");
     if (!ms || !n) return fail(LSQR_E_INVALID, "null output");
+    if (mode) *mode = h->last_mode;
     ms[0] = h->ms_pre;
     ms[1] = h->ms1 - h->ms_pre;
     ms[2] = h->ms2;

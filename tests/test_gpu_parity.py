@@ -466,6 +466,7 @@ def test_profile_pass_times(torch_cuda):
     g.set_option("profile", 1)
     g.solve(torch.from_numpy(b).cuda(), 12, atol=0.0, btol=0.0)
     pt = g.pass_times()
+    assert pt.pop("mode") == 2  # default: few buckets, attitude pre-pass
     assert all(n == 12 for _, n in pt.values()) and all(ms > 0 for ms, _ in pt.values())
     g.set_option("fused", 1)
     g.solve(torch.from_numpy(b).cuda(), 12, atol=0.0, btol=0.0)
@@ -473,8 +474,19 @@ def test_profile_pass_times(torch_cuda):
     kt = g.kernel_times()
     g.close()
     # mode 1 has no pre-pass: the first window holds only the interleave copy
-    assert pt1["pre"][0] < pt1["fused"][0]
+    assert pt1["mode"] == 1 and pt1["pre"][0] < pt1["fused"][0]
     assert abs(pt1["pre"][0] + pt1["fused"][0] - kt["aprod1_ms"]) <= 1e-6 * kt["aprod1_ms"]
+    # many attitude buckets (84 windows of 12 starts): pre-pass windows at
+    # every bucket boundary, same iterates
+    g = gpu_system(torch, S)
+    g.set_option("att_buckets", 90)
+    g.set_option("tests", 0)
+    g.set_option("profile", 1)
+    x, _ = g.solve(torch.from_numpy(b).cuda(), 12, atol=0.0, btol=0.0)
+    assert g.pass_times()["mode"] == 2
+    g.close()
+    x_ref, _ = o.lsqr(b, 12, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+    assert rel_inf(x.cpu().numpy(), x_ref) <= 1e-10
 
 
 def test_profile_counts_launches(torch_cuda):
