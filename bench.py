@@ -99,7 +99,7 @@ def counter_traffic(kernel: str):
     return rec.get(kernel)
 
 
-def cpu_baseline(spec, sample_stars=20_000, itn=(1, 6)):
+def cpu_baseline(spec, sample_stars=40_000, itn=(1, 11)):
     """The oracle as it stands, single thread, on the first `sample_stars`
     stars of the workload (same N_DFA and instrumental columns), per-iteration
     time from two runs of different length, scaled to the full row count."""
@@ -129,6 +129,31 @@ def cpu_baseline(spec, sample_stars=20_000, itn=(1, 6)):
 
 def rel_inf(a, b):
     return float((a - b).abs().max() / b.abs().max())
+
+
+def stream_ceiling(dev, gib: float = 20.0, reps: int = 5):
+    """Practical HBM ceilings on this GPU: a plain reduction (read) and fill
+    (write) over a `gib` GiB FP64 buffer with PyTorch's own kernels, median of
+    `reps` runs each."""
+    import torch
+
+    buf = torch.empty(int(gib * 2**30) // 8, dtype=torch.float64, device=dev)
+    buf.fill_(1.0)
+    out = {}
+    for name, fn in (("read", lambda: buf.sum()), ("write", lambda: buf.fill_(2.0))):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        out[f"{name}_GBps"] = buf.numel() * 8 / sorted(ts)[reps // 2] / 1e9
+    out["kernels"] = f"torch sum / fill over {gib:.0f} GiB FP64, median of {reps}"
+    del buf
+    torch.cuda.empty_cache()
+    return out
 
 
 def refine_leg(cfg: int, dev):
@@ -548,6 +573,10 @@ def main():
     g.close()
     del arrays, b, xt, x
     torch.cuda.empty_cache()
+    sc = stream_ceiling(dev)
+    sc["dominant_kernel_frac_of_read"] = gbps[dom] / sc["read_GBps"]
+    result["stream_ceiling"] = sc
+    log(f"stream ceiling: read {sc['read_GBps']:.0f} GB/s, write {sc['write_GBps']:.0f} GB/s")
     forms = [f for f in args.forms.split(",") if f and f != "none"]
     if "refine" in forms:
         result["fp32_refine"] = refine_leg(2, dev)
