@@ -99,7 +99,7 @@ def counter_traffic(kernel: str):
     return rec.get(kernel)
 
 
-def cpu_baseline(spec, sample_stars=40_000, itn=(1, 11)):
+def cpu_baseline(spec, sample_stars=40_000, itn=(1, 21)):
     """The oracle as it stands, single thread, on the first `sample_stars`
     stars of the workload (same N_DFA and instrumental columns), per-iteration
     time from two runs of different length, scaled to the full row count."""

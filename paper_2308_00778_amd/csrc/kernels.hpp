@@ -1861,8 +1861,9 @@ __global__ __launch_bounds__(kBlock) void k_interleave_att(const double* __restr
 // FP64 histogram [hcols][K] of instrumental columns [0, hcols) (the others
 // are left to k_instr_tail), then the instrumental slice of VP (LDSX). In 1024-thread workgroups (128 registers
 // per lane) a multi-RHS tile reduces its star segments chunk by chunk instead
-// of carrying 5K running sums.
-template <typename T, typename Acc, int K, int NT, bool LDSX, bool ATTI>
+// of carrying 5K running sums. AM as in the single-RHS pass (kAttPre with
+// K = 1 only: k_att_dot's window holds one RHS).
+template <typename T, typename Acc, int K, int NT, bool LDSX, int AM>
 __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ VP,
                                                const Acc* __restrict__ X3, Acc* __restrict__ U,
                                                Acc* __restrict__ Q, const int64_t* __restrict__ wb,
@@ -1919,10 +1920,11 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
         const int64_t stc = ldnt(&s.star[ic]);
         const int64_t st = i < re ? stc : kNoStar;
-        const int64_t t = ldnt(&s.att[ic]);
+        const int64_t t = AM == kAttPre ? 0 : ldnt(&s.att[ic]);
         T a[kPar];
 #pragma unroll
-        for (int c = 0; c < kPar; ++c) a[c] = ldnt(&val[c * m + ic]);
+        for (int c = 0; c < kPar; ++c)
+            if (AM != kAttPre || c < kOffAtt || c >= kOffInstr) a[c] = ldnt(&val[c * m + ic]);
         int32_t ix[kInstr];
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
@@ -1936,16 +1938,18 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         for (int j = 0; j < kAstro; ++j)
 #pragma unroll
             for (int r = 0; r < K; ++r) d[r] += (Acc)a[j] * xa[j * K + r];
+        if (AM != kAttPre) {
 #pragma unroll
-        for (int ax = 0; ax < kAxes; ++ax)
+            for (int ax = 0; ax < kAxes; ++ax)
 #pragma unroll
-            for (int qq = 0; qq < kParAxis; ++qq) {
-                const Acc* xv = ATTI ? X3 + (kAxes * (t + qq) + ax) * K
-                                     : VP + (s.att_base + ax * s.n_dfa + t + qq) * K;
-                const Acc av = (Acc)a[kOffAtt + ax * kParAxis + qq];
+                for (int qq = 0; qq < kParAxis; ++qq) {
+                    const Acc* xv = AM == kAttX3 ? X3 + (kAxes * (t + qq) + ax) * K
+                                                 : VP + (s.att_base + ax * s.n_dfa + t + qq) * K;
+                    const Acc av = (Acc)a[kOffAtt + ax * kParAxis + qq];
 #pragma unroll
-                for (int r = 0; r < K; ++r) d[r] += av * xv[r];
-            }
+                    for (int r = 0; r < K; ++r) d[r] += av * xv[r];
+                }
+        }
 #pragma unroll
         for (int j = 0; j < kInstr; ++j)
 #pragma unroll
@@ -1954,7 +1958,8 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         for (int r = 0; r < K; ++r) {
             d[r] += (Acc)a[kOffGlob] * xg[r];
             const bool on = ok && ((live >> r) & 1u);
-            const Acc nu = d[r] - coef[r] * U[pu * K + r];
+            // kAttPre (K = 1): U already holds the attitude part minus coef U
+            const Acc nu = AM == kAttPre ? d[r] + U[pu * K + r] : d[r] - coef[r] * U[pu * K + r];
             if (on) U[pu * K + r] = nu;
             d[r] = on ? nu : (Acc)0;
             ssq[r] += (double)d[r] * (double)d[r];

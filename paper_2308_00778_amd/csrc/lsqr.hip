@@ -895,6 +895,18 @@ size_t batch_fused_lds(const lsqr_handle* h, int64_t* hc, int* ldsx)
     return (size_t)(*ldsx ? hist + xbytes : *hc * K * 8);
 }
 
+template <typename T, int K, bool LDSX, int AM>
+void batch_fused_as(lsqr_handle* h, const double* X3, int64_t hc, size_t lds, hipStream_t st)
+{
+    auto& B = h->batch;
+    constexpr int NT = fused_nt<K>();
+    hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, LDSX, AM>), dim3(fused_grid<K>(h)),
+                       dim3(NT), lds, st, h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb,
+                       B.gpart, B.part1, hc, B.sc, row_map(h));
+}
+
+// The fused pass of a k-tile; a one-RHS tile in fused mode 2 first runs the
+// attitude pre-pass (k_att_dot on the tile's U, X3 and Scalars).
 template <typename T, int K>
 void batch_fused(lsqr_handle* h, hipStream_t st)
 {
@@ -902,30 +914,28 @@ void batch_fused(lsqr_handle* h, hipStream_t st)
     int64_t hc = 0;
     int ldsx = 0;
     const size_t lds = batch_fused_lds<K>(h, &hc, &ldsx);
-    constexpr int NT = fused_nt<K>();
-    const dim3 g(fused_grid<K>(h)), bm(NT);
+    const bool pre = K == 1 && h->fused == 2;
     const double* X3 = nullptr;
-    if (h->att_il) {
+    if (h->att_il || pre) {
         hipLaunchKernelGGL((batched::k_interleave_att<K>), dim3(h->nbc), dim3(kBlock), 0, st,
                            (const double*)B.VP, h->sv.att_base, h->sv.n_dfa, B.X3);
         X3 = B.X3;
     }
-    if (ldsx && X3)
-        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, true, true>), g, bm, lds, st, h->sv,
-                           (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc, B.sc,
-                           row_map(h));
-    else if (ldsx)
-        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, true, false>), g, bm, lds, st,
-                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc,
-                           B.sc, row_map(h));
-    else if (X3)
-        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, false, true>), g, bm, lds, st,
-                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc,
-                           B.sc, row_map(h));
-    else
-        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, false, false>), g, bm, lds, st,
-                           h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc,
-                           B.sc, row_map(h));
+    if (pre) {
+        hipLaunchKernelGGL((k_att_dot<T, double, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock),
+                           (size_t)(kAxes * att_span(h) * 8), st, h->sv.m,
+                           (const T*)h->att_sorted, (const int32_t*)h->tloc,
+                           (const int64_t*)h->bstart, h->bwidth, h->att_g, h->sv.n_dfa, X3, B.U,
+                           (const Scalars*)B.sc);
+        if (ldsx) batch_fused_as<T, K, true, kAttPre>(h, nullptr, hc, lds, st);
+        else batch_fused_as<T, K, false, kAttPre>(h, nullptr, hc, lds, st);
+    } else if (ldsx) {
+        if (X3) batch_fused_as<T, K, true, kAttX3>(h, X3, hc, lds, st);
+        else batch_fused_as<T, K, true, kAttX>(h, X3, hc, lds, st);
+    } else {
+        if (X3) batch_fused_as<T, K, false, kAttX3>(h, X3, hc, lds, st);
+        else batch_fused_as<T, K, false, kAttX>(h, X3, hc, lds, st);
+    }
     launch_instr_tail<T, double, K, false>(h, (const double*)B.U, row_map(h), B.Q, hc, B.sc, st);
 }
 

@@ -34,8 +34,9 @@ def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-# (attitude mode, fused pass): the fused pass serves attitude mode 1
-@pytest.mark.parametrize("att_mode,fused", [(1, 1), (1, 0), (0, 1)])
+# (attitude mode, fused mode): the fused pass serves attitude mode 1; fused
+# mode 2 runs the attitude pre-pass in one-RHS tiles
+@pytest.mark.parametrize("att_mode,fused", [(1, 2), (1, 1), (1, 0), (0, 1)])
 @pytest.mark.parametrize("ktile", [1, 2, 4, 8])
 def test_batched_fixed_iterations(torch_cuda, c0, ktile, att_mode, fused):
     torch = torch_cuda
