@@ -1184,6 +1184,21 @@ lsqr_status check_handle(lsqr_handle* h)
 }  // namespace
 
 // ================================================================== C ABI
+// Captured iteration graphs bake in the kernel choices: drop them all (single
+// solves and every batched k-tile) when an option that selects kernels
+// changes.
+void drop_graphs(lsqr_handle* h)
+{
+    for (hipGraphExec_t* g : {&h->p64.graph, &h->p32.graph}) {
+        if (*g) (void)hipGraphExecDestroy(*g);
+        *g = nullptr;
+    }
+    for (auto& g : h->batch.graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
 extern "C" {
 
 const char* lsqr_last_error(void) { return g_last_error.c_str(); }
@@ -1491,10 +1506,7 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         const int v = option == LSQR_OPT_ATT_MODE ? (int)value : (value != 0.0 ? 1 : 0);
         int& slot = option == LSQR_OPT_ATT_MODE ? h->att_mode : h->astro_scan;
         if (slot != v) {  // captured graphs bake in the kernel choice
-            if (h->p64.graph) (void)hipGraphExecDestroy(h->p64.graph);
-            if (h->p32.graph) (void)hipGraphExecDestroy(h->p32.graph);
-            h->p64.graph = nullptr;
-            h->p32.graph = nullptr;
+            drop_graphs(h);
         }
         slot = v;
         return LSQR_OK;
@@ -1506,10 +1518,7 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         const int v = option == LSQR_OPT_FUSED ? (int)value : (value != 0.0 ? 1 : 0);
         int& slot = option == LSQR_OPT_FUSED ? h->fused : h->att_il;
         if (slot != v) {
-            if (h->p64.graph) (void)hipGraphExecDestroy(h->p64.graph);
-            if (h->p32.graph) (void)hipGraphExecDestroy(h->p32.graph);
-            h->p64.graph = nullptr;
-            h->p32.graph = nullptr;
+            drop_graphs(h);
         }
         slot = v;
         return LSQR_OK;
@@ -1530,10 +1539,7 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
     case LSQR_OPT_VARIANCE: {
         const int v = value != 0.0 ? 1 : 0;
         if (h->var_on != v) {  // captured graphs bake in the variance pointer
-            if (h->p64.graph) (void)hipGraphExecDestroy(h->p64.graph);
-            if (h->p32.graph) (void)hipGraphExecDestroy(h->p32.graph);
-            h->p64.graph = nullptr;
-            h->p32.graph = nullptr;
+            drop_graphs(h);
         }
         h->var_on = v;
         return LSQR_OK;
