@@ -174,6 +174,13 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         Saunders' diagonal estimate of (Abar^T Abar)^-1), read
  *                         back re-multiplied by p^2 with lsqr_get_variance;
  *                         0 (default) off. One FP64 update per column per iteration
+ *   LSQR_OPT_COMPACT_INDEX 1 (default): on the first solve, build int32 copies of
+ *                         star_of_row and uint16 copies of instr_idx for the
+ *                         fused passes (16 instead of 32 index bytes per row;
+ *                         full row layout, n_instr_cols <= 65536, n_stars <
+ *                         2^31) when they take at most 1/32 of the device
+ *                         memory; the caller's arrays are used otherwise and
+ *                         by every other pass; 0: never (frees the copies)
  *   LSQR_OPT_KTILE        batched solves: right-hand sides advanced together per
  *                         pass over A (1, 2, 4, 8), 0 (default) = autotune once
  *                         per handle
@@ -191,6 +198,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_ATT_INTERLEAVE 11
 #define LSQR_OPT_FUSED 12
 #define LSQR_OPT_VARIANCE 13
+#define LSQR_OPT_COMPACT_INDEX 14
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
 
 /* Below, m counts every row: n_rows observation rows plus n_con constraint

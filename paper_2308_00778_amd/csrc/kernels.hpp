@@ -64,7 +64,25 @@ struct SysView {
     // is 5, 12, 6, 1 at offsets 5, 17, 23)
     int32_t na, natt, ni, ng;
     int32_t off_att, off_instr, off_glob;
+    // compact copies of the star and instrumental indices read by the fused
+    // passes (CIDX), or null
+    const int32_t* star32;    // [m]
+    const uint16_t* instr16;  // [kInstr][m]
 };
+
+// Star and instrumental index of row ic, from the compact copies when CIDX.
+template <bool CIDX>
+__device__ __forceinline__ int64_t star_of(const SysView& s, int64_t ic)
+{
+    return CIDX ? (int64_t)__builtin_nontemporal_load(&s.star32[ic])
+                : __builtin_nontemporal_load(&s.star[ic]);
+}
+template <bool CIDX>
+__device__ __forceinline__ int32_t instr_of(const SysView& s, int j, int64_t ic)
+{
+    return CIDX ? (int32_t)__builtin_nontemporal_load(&s.instr16[j * s.m + ic])
+                : __builtin_nontemporal_load(&s.instr[j * s.m + ic]);
+}
 
 // LSQR state kept on the device so that a whole iteration runs without a
 // host round trip (and can be captured into a graph).
@@ -558,7 +576,7 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
 // of x, kAttX3 one 12-value window of x3, kAttPre none: k_att_dot has already
 // replaced u~ by (attitude part of A vp) - coef u~, so the row adds that.
 enum { kAttX = 0, kAttX3 = 1, kAttPre = 2 };
-template <typename T, typename Acc, int NT, bool LDSX, int AM>
+template <typename T, typename Acc, int NT, bool LDSX, int AM, bool CIDX>
 __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ x,
                                                const Acc* __restrict__ x3, Acc* __restrict__ u,
                                                Acc* __restrict__ q, const int64_t* __restrict__ wb,
@@ -606,7 +624,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         const int64_t i = r0 + lane;
         const bool ok = i >= rb && i < re;
         const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
-        const int64_t stc = ldnt(&s.star[ic]);
+        const int64_t stc = star_of<CIDX>(s, ic);
         const int64_t st = i < re ? stc : kNoStar;
         const int64_t t = AM == kAttPre ? 0 : ldnt(&s.att[ic]);
         T a[kPar];
@@ -615,7 +633,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
             if (AM != kAttPre || c < kOffAtt || c >= kOffInstr) a[c] = ldnt(&val[c * m + ic]);
         int32_t ix[kInstr];
 #pragma unroll
-        for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
+        for (int j = 0; j < kInstr; ++j) ix[j] = instr_of<CIDX>(s, j, ic);
         const int64_t pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
         const Acc uo = u[pu];
 
@@ -1361,6 +1379,19 @@ __global__ __launch_bounds__(kBlock) void k_validate(SysView s, int32_t* __restr
     if (bad) atomicOr(flag, bad);
 }
 
+// Compact index copies for the fused passes: star as int32, instrumental
+// indices as uint16 (the caller checks that they fit).
+__global__ __launch_bounds__(kBlock) void k_compact_idx(SysView s, int32_t* __restrict__ star32,
+                                                         uint16_t* __restrict__ instr16)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < s.m;
+         i += (int64_t)gridDim.x * kBlock) {
+        star32[i] = (int32_t)s.star[i];
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) instr16[j * s.m + i] = (uint16_t)s.instr[j * s.m + i];
+    }
+}
+
 // Star-aligned row boundaries: range g starts at the first star boundary at
 // or after g*m/nw, so that no star is split between two waves.
 template <typename K>
@@ -1863,7 +1894,7 @@ __global__ __launch_bounds__(kBlock) void k_interleave_att(const double* __restr
 // per lane) a multi-RHS tile reduces its star segments chunk by chunk instead
 // of carrying 5K running sums. AM as in the single-RHS pass (kAttPre with
 // K = 1 only: k_att_dot's window holds one RHS).
-template <typename T, typename Acc, int K, int NT, bool LDSX, int AM>
+template <typename T, typename Acc, int K, int NT, bool LDSX, int AM, bool CIDX>
 __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ VP,
                                                const Acc* __restrict__ X3, Acc* __restrict__ U,
                                                Acc* __restrict__ Q, const int64_t* __restrict__ wb,
@@ -1918,7 +1949,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         const int64_t i = r0 + lane;
         const bool ok = i >= rb && i < re;
         const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
-        const int64_t stc = ldnt(&s.star[ic]);
+        const int64_t stc = star_of<CIDX>(s, ic);
         const int64_t st = i < re ? stc : kNoStar;
         const int64_t t = AM == kAttPre ? 0 : ldnt(&s.att[ic]);
         T a[kPar];
@@ -1927,7 +1958,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
             if (AM != kAttPre || c < kOffAtt || c >= kOffInstr) a[c] = ldnt(&val[c * m + ic]);
         int32_t ix[kInstr];
 #pragma unroll
-        for (int j = 0; j < kInstr; ++j) ix[j] = ldnt(&s.instr[j * m + ic]);
+        for (int j = 0; j < kInstr; ++j) ix[j] = instr_of<CIDX>(s, j, ic);
 
         const int64_t pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
         Acc d[K];

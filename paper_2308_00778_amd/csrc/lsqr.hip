@@ -213,6 +213,10 @@ struct lsqr_handle {
                          // 2: the same with the attitude part of aprod1 in a bucket-order
                          // pre-pass (k_att_dot); 0: separate aprod1 and aprod2
     int last_mode = 0;   // fused mode of the last single-RHS solve
+    int compact = 1;     // compact index copies for the fused passes when they fit
+    int compact_tried = 0;
+    int32_t* star32 = nullptr;    // [m] compact star index (or null)
+    uint16_t* instr16 = nullptr;  // [6][m] compact instrumental indices (or null)
     double outer_tol = 1e-10;
     int ktile = 0;       // batched k-tile: 0 autotune, else 1, 2, 4 or 8
 
@@ -342,9 +346,14 @@ void launch_interleave_att(const lsqr_handle* h, const V* x, V* x3, const Scalar
 template <typename T, typename Acc, bool LDSX, int AM>
 void launch_fused_as(const lsqr_handle* h, Path<Acc>& P, const Acc* x3, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, LDSX, AM>), dim3(h->nb2), dim3(kBlock2), P.lds_f,
-                       st, h->sv, (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart, h->part1,
-                       P.hcols, h->sc, row_map(h));
+    if (h->sv.star32)
+        hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, LDSX, AM, true>), dim3(h->nb2), dim3(kBlock2),
+                           P.lds_f, st, h->sv, (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart,
+                           h->part1, P.hcols, h->sc, row_map(h));
+    else
+        hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, LDSX, AM, false>), dim3(h->nb2),
+                           dim3(kBlock2), P.lds_f, st, h->sv, (const Acc*)P.vp, x3, P.u, P.q,
+                           h->wb, P.gpart, h->part1, P.hcols, h->sc, row_map(h));
 }
 
 // Attitude part of aprod1 in bucket order, folded into u~ (fused mode 2):
@@ -626,6 +635,53 @@ lsqr_status ensure_att(lsqr_handle* h)
     return h->value_type == LSQR_F64 ? prepare_att_sorted<double>(h) : prepare_att_sorted<float>(h);
 }
 
+// Captured iteration graphs bake in the kernel choices: drop them all (single
+// solves and every batched k-tile) when an option that selects kernels
+// changes.
+void drop_graphs(lsqr_handle* h)
+{
+    for (hipGraphExec_t* g : {&h->p64.graph, &h->p32.graph}) {
+        if (*g) (void)hipGraphExecDestroy(*g);
+        *g = nullptr;
+    }
+    for (auto& g : h->batch.graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// Compact index copies for the fused passes (int32 star, uint16 instrumental
+// index: 16 instead of 32 bytes per row), built once per handle on the first
+// solve when the layout allows them and they take at most 1/32 of the
+// device's memory; otherwise (or if the allocation fails) the fused passes
+// read the caller's arrays.
+constexpr int64_t kCompactMemFraction = 32;
+
+lsqr_status ensure_compact(lsqr_handle* h)
+{
+    if (!h->compact || h->compact_tried || h->generic) return LSQR_OK;
+    h->compact_tried = 1;
+    const int64_t m = h->sv.m;
+    if (h->sv.n_stars > INT32_MAX || h->sv.n_instr_cols > 65536) return LSQR_OK;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return LSQR_OK;
+    const int64_t need = m * (int64_t)(sizeof(int32_t) + kInstr * sizeof(uint16_t));
+    if (need > (int64_t)(total_b / kCompactMemFraction) || need >= (int64_t)free_b) return LSQR_OK;
+    if (dalloc(&h->star32, m) != LSQR_OK || dalloc(&h->instr16, (int64_t)kInstr * m) != LSQR_OK) {
+        dfree(h->star32);
+        dfree(h->instr16);
+        g_last_error.clear();  // not an error: the fused passes use the caller's arrays
+        return LSQR_OK;
+    }
+    hipLaunchKernelGGL(k_compact_idx, dim3(std::min<int64_t>(cdiv(m, kBlock), 8192)), dim3(kBlock),
+                       0, h->stream, h->sv, h->star32, h->instr16);
+    HIP_TRY(hipGetLastError());
+    h->sv.star32 = h->star32;
+    h->sv.instr16 = h->instr16;
+    drop_graphs(h);
+    return LSQR_OK;
+}
+
 template <typename Acc>
 void release_path(Path<Acc>& P)
 {
@@ -750,6 +806,7 @@ lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_l
                        double btol, lsqr_info* info)
 {
     LSQR_TRY(ensure_att(h));
+    LSQR_TRY(ensure_compact(h));
     LSQR_TRY((prepare_path<T, double>(h, h->p64)));
     Path<double>& P = h->p64;
     const int64_t m = h->sv.m, n = h->sv.n;
@@ -900,9 +957,14 @@ void batch_fused_as(lsqr_handle* h, const double* X3, int64_t hc, size_t lds, hi
 {
     auto& B = h->batch;
     constexpr int NT = fused_nt<K>();
-    hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, LDSX, AM>), dim3(fused_grid<K>(h)),
-                       dim3(NT), lds, st, h->sv, (const double*)B.VP, X3, B.U, B.Q, h->wb,
-                       B.gpart, B.part1, hc, B.sc, row_map(h));
+    if (h->sv.star32)
+        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, LDSX, AM, true>),
+                           dim3(fused_grid<K>(h)), dim3(NT), lds, st, h->sv, (const double*)B.VP,
+                           X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc, B.sc, row_map(h));
+    else
+        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, LDSX, AM, false>),
+                           dim3(fused_grid<K>(h)), dim3(NT), lds, st, h->sv, (const double*)B.VP,
+                           X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc, B.sc, row_map(h));
 }
 
 // The fused pass of a k-tile; a one-RHS tile in fused mode 2 first runs the
@@ -1184,20 +1246,6 @@ lsqr_status check_handle(lsqr_handle* h)
 }  // namespace
 
 // ================================================================== C ABI
-// Captured iteration graphs bake in the kernel choices: drop them all (single
-// solves and every batched k-tile) when an option that selects kernels
-// changes.
-void drop_graphs(lsqr_handle* h)
-{
-    for (hipGraphExec_t* g : {&h->p64.graph, &h->p32.graph}) {
-        if (*g) (void)hipGraphExecDestroy(*g);
-        *g = nullptr;
-    }
-    for (auto& g : h->batch.graph) {
-        if (g) (void)hipGraphExecDestroy(g);
-        g = nullptr;
-    }
-}
 
 extern "C" {
 
@@ -1470,6 +1518,8 @@ lsqr_status lsqr_destroy(lsqr_handle* h)
     dfree(h->gpart_raw);
     dfree(h->flag);
     dfree(h->con_ssq);
+    dfree(h->star32);
+    dfree(h->instr16);
     dfree(h->sc);
     if (h->sc_host) (void)hipHostFree(h->sc_host);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
@@ -1542,6 +1592,19 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
             drop_graphs(h);
         }
         h->var_on = v;
+        return LSQR_OK;
+    }
+    case LSQR_OPT_COMPACT_INDEX: {
+        const int v = value != 0.0 ? 1 : 0;
+        if (!v && h->star32) {  // back to the caller's arrays
+            drop_graphs(h);
+            dfree(h->star32);
+            dfree(h->instr16);
+            h->sv.star32 = nullptr;
+            h->sv.instr16 = nullptr;
+        }
+        if (v && !h->compact) h->compact_tried = 0;
+        h->compact = v;
         return LSQR_OK;
     }
     case LSQR_OPT_OUTER_TOL:
@@ -1657,6 +1720,7 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
     HIP_TRY(hipStreamSynchronize(h->user_stream));
     h->var_valid = 0;
     LSQR_TRY(ensure_att(h));
+    LSQR_TRY(ensure_compact(h));
     LSQR_TRY((prepare_path<float, float>(h, h->p32)));
     Path<float>& P = h->p32;
     const int64_t n = h->sv.n;
@@ -1725,6 +1789,7 @@ lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32
     HIP_TRY(hipStreamSynchronize(h->user_stream));
     h->var_valid = 0;
     LSQR_TRY(ensure_att(h));
+    LSQR_TRY(ensure_compact(h));
     if (h->value_type == LSQR_F64)
         LSQR_TRY(solve_batched<double>(h, B, X, k, itn_limit, atol, btol, infos));
     else

@@ -34,11 +34,12 @@ def rel_inf(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-# (attitude mode, fused mode): the fused pass serves attitude mode 1; fused
-# mode 2 runs the attitude pre-pass in one-RHS tiles
-@pytest.mark.parametrize("att_mode,fused", [(1, 2), (1, 1), (1, 0), (0, 1)])
+# (attitude mode, fused mode, compact indices): the fused pass serves
+# attitude mode 1; fused mode 2 runs the attitude pre-pass in one-RHS tiles
+@pytest.mark.parametrize("att_mode,fused,compact", [(1, 2, 1), (1, 2, 0), (1, 1, 1), (1, 0, 1),
+                                                    (0, 1, 1)])
 @pytest.mark.parametrize("ktile", [1, 2, 4, 8])
-def test_batched_fixed_iterations(torch_cuda, c0, ktile, att_mode, fused):
+def test_batched_fixed_iterations(torch_cuda, c0, ktile, att_mode, fused, compact):
     torch = torch_cuda
     from paper_2308_00778_amd import LsqrSystem
 
@@ -48,6 +49,7 @@ def test_batched_fixed_iterations(torch_cuda, c0, ktile, att_mode, fused):
     g = LsqrSystem.from_host(S, "cuda:0")
     g.set_option("att_mode", att_mode)
     g.set_option("fused", fused)
+    g.set_option("compact_index", compact)
     g.set_option("att_buckets", 4)
     g.set_option("tests", 0)
     g.set_option("ktile", ktile)

@@ -186,7 +186,15 @@ def test_solve_other_fused_modes(torch_cuda, name, itn, fused):
     _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], fused=fused)
 
 
-def _solve_fixed(torch_cuda, name, itn, graph, variant, interleave=1, fused=1):
+# The fused passes read compact copies of the star and instrumental indices
+# by default; the caller's int64/int32 arrays without them.
+@pytest.mark.parametrize("fused", [2, 1])
+@pytest.mark.parametrize("name,itn", [("c0", 60), ("huge_instr", 30), ("wide_att_f32", 30)])
+def test_solve_without_compact_index(torch_cuda, name, itn, fused):
+    _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], fused=fused, compact=0)
+
+
+def _solve_fixed(torch_cuda, name, itn, graph, variant, interleave=1, fused=2, compact=1):
     torch = torch_cuda
     S, o = system(name)
     b = _b(S, o)
@@ -198,6 +206,7 @@ def _solve_fixed(torch_cuda, name, itn, graph, variant, interleave=1, fused=1):
     g.set_option("astro_scan", variant[1])
     g.set_option("att_interleave", interleave)
     g.set_option("fused", fused)
+    g.set_option("compact_index", compact)
     if graph:
         g.set_option("att_buckets", BUCKETS.get(name, 3))
     g.set_option("tests", 0)
