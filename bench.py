@@ -46,6 +46,11 @@ def bytes_per_row(vb: int, ub: int):
 
 
 BYTES_PER_ROW = bytes_per_row(8, 8)      # FP64 values and vectors
+# Named variant: with compact index copies (LSQR_OPT_COMPACT_INDEX) the fused
+# pass reads an int32 star and six uint16 instrumental indices, 16 bytes less
+# per row than the configured layout; the canonical figures keep the
+# configured bytes.
+COMPACT_SAVING = 16
 BYTES_PER_ROW_F32 = bytes_per_row(4, 4)  # the FP32 inner solve of the refinement
 
 
@@ -57,6 +62,7 @@ def pass_times(g, mode=None):
     pt = g.pass_times()
     mode = pt.pop("mode") if mode is None else mode
     pt.pop("mode", None)
+    pt.pop("compact", None)
     per = {k: ms / max(1, n) for k, (ms, n) in pt.items()}
     if mode == 2:
         return {"attitude_dot": per["pre"], "fused_rest": per["fused"],
@@ -503,6 +509,7 @@ def main():
     wall = time.perf_counter() - t1
     kt = g.kernel_times()
     assert info.itn == args.steps and kt["aprod1_n"] == args.steps == kt["aprod2_n"]
+    compact = g.pass_times()["compact"]
     ms = pass_times(g)
     gbps = {k: BYTES_PER_ROW[k] * m / (ms[k] * 1e-3) / 1e9 for k in ms}
     dom = max(ms, key=ms.get)
@@ -564,7 +571,12 @@ def main():
                                  if traffic.get(dom) is not None else None)},
         "kernels": {k: {"ms": ms[k], "GBps": gbps[k], "bytes_per_row": BYTES_PER_ROW[k],
                         "frac_of_peak": gbps[k] / HBM_PEAK_GBPS,
-                        "counter_bytes_per_launch": traffic[k]} for k in ms},
+                        "counter_bytes_per_launch": traffic[k],
+                        **({"compact_index_bytes_per_row": BYTES_PER_ROW[k] - COMPACT_SAVING,
+                            "compact_index_GBps": (BYTES_PER_ROW[k] - COMPACT_SAVING) * m
+                            / (ms[k] * 1e-3) / 1e9}
+                           if compact and k in ("fused", "fused_rest") else {})}
+                    for k in ms},
         "graph_iter_per_s": args.steps / wall_graph,
         "fused_att_in_pass": other[1],
         "unfused": other[0],

@@ -280,8 +280,10 @@ lsqr_status lsqr_kernel_times(lsqr_handle* h, double* ms_aprod1, int64_t* n_apro
  * the aprod1 window (the fused pass, or aprod1), ms[2] the aprod2 window (the
  * attitude pass, or aprod2); n[i] the iterations timed. Host arrays of 3.
  * mode (may be NULL): the fused mode the last FP64 or refined solve ran
- * (0, 1 or 2, see LSQR_OPT_FUSED). */
-lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n, int32_t* mode);
+ * (0, 1 or 2, see LSQR_OPT_FUSED); compact (may be NULL): 1 when the fused
+ * passes read the compact index copies (LSQR_OPT_COMPACT_INDEX). */
+lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n, int32_t* mode,
+                            int32_t* compact);
 
 /* Number of columns n of the handle's system. Host pointer out. */
 lsqr_status lsqr_num_cols(lsqr_handle* h, int64_t* n_out);

@@ -1806,11 +1806,13 @@ lsqr_status lsqr_batch_tuning(lsqr_handle* h, int32_t* k_tile, double* ms_per_rh
     return LSQR_OK;
 }
 
-lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n, int32_t* mode)
+lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n, int32_t* mode,
+                            int32_t* compact)
 {
     if (!h) return fail(LSQR_E_INVALID, "null handle");
     if (!ms || !n) return fail(LSQR_E_INVALID, "null output");
     if (mode) *mode = h->last_mode;
+    if (compact) *compact = h->sv.star32 != nullptr ? 1 : 0;
     ms[0] = h->ms_pre;
     ms[1] = h->ms1 - h->ms_pre;
     ms[2] = h->ms2;

@@ -103,7 +103,7 @@ def load_library(path: str = LIB_PATH):
         "lsqr_kernel_times": ([H, ctypes.POINTER(F64), ctypes.POINTER(I64),
                                ctypes.POINTER(F64), ctypes.POINTER(I64)], I32),
         "lsqr_pass_times": ([H, ctypes.POINTER(F64), ctypes.POINTER(I64),
-                             ctypes.POINTER(I32)], I32),
+                             ctypes.POINTER(I32), ctypes.POINTER(I32)], I32),
         "lsqr_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -316,12 +316,14 @@ class LsqrSystem:
 
     def pass_times(self):
         """Profiled milliseconds and iteration counts of the attitude pre-pass,
-        the fused (aprod1) pass and the attitude (aprod2) pass, and the fused
-        mode of the last solve ("mode")."""
+        the fused (aprod1) pass and the attitude (aprod2) pass, the fused mode
+        of the last solve ("mode") and whether its fused passes read the
+        compact index copies ("compact")."""
         ms = (ctypes.c_double * 3)()
         n = (ctypes.c_int64 * 3)()
-        mode = ctypes.c_int32()
-        _check(_lib.lsqr_pass_times(self._h, ms, n, ctypes.byref(mode)))
+        mode, compact = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.lsqr_pass_times(self._h, ms, n, ctypes.byref(mode), ctypes.byref(compact)))
         out = {name: (ms[i], n[i]) for i, name in enumerate(("pre", "fused", "attitude"))}
         out["mode"] = mode.value
+        out["compact"] = compact.value
         return out

@@ -475,7 +475,8 @@ def test_profile_pass_times(torch_cuda):
     g.set_option("profile", 1)
     g.solve(torch.from_numpy(b).cuda(), 12, atol=0.0, btol=0.0)
     pt = g.pass_times()
-    assert pt.pop("mode") == 2  # default: few buckets, attitude pre-pass
+    assert pt.pop("mode") == 2  # default: attitude pre-pass
+    assert pt.pop("compact") == 1  # default: compact index copies (small system)
     assert all(n == 12 for _, n in pt.values()) and all(ms > 0 for ms, _ in pt.values())
     g.set_option("fused", 1)
     g.solve(torch.from_numpy(b).cuda(), 12, atol=0.0, btol=0.0)
