@@ -49,6 +49,10 @@ SPECS = {
     # rest in a tail window
     "huge_instr": synth.tiny(seed=27, n_stars=300, obs=(30, 60), n_dfa=200,
                              n_instr_cols=25000),
+    # 70,000 instrumental columns: beyond a uint16 index (no compact index
+    # copies) and four LDS windows (one histogram, three tail windows)
+    "instr_70k": synth.tiny(seed=28, n_stars=300, obs=(30, 60), n_dfa=150,
+                            n_instr_cols=70000),
     # FP32 values, 8,997 attitude starts: the default layout has two buckets
     # of FP64 histograms (exact operators and fixed-iteration solves only:
     # more attitude columns than rows)
@@ -158,7 +162,8 @@ def _b(S, o, rhs=0):
 # differ by 2e-9 at k = 30 on the 36-unknown "one_star" system, 1e-15 at 15).
 @pytest.mark.parametrize("name,itn", [("c0", 50), ("c0", 200), ("ragged", 120),
                                        ("one_star", 15), ("few_rows", 15), ("wide_instr", 60),
-                                       ("huge_instr", 30), ("wide_att_f32", 30)])
+                                       ("huge_instr", 30), ("instr_70k", 30),
+                                       ("wide_att_f32", 30)])
 @pytest.mark.parametrize("graph", [1, 0])
 def test_solve_fixed_iterations(torch_cuda, name, itn, graph):
     _solve_fixed(torch_cuda, name, itn, graph, VARIANTS[0])
