@@ -170,7 +170,7 @@ def refine_leg(cfg: int, dev):
     import synth
     from paper_2308_00778_amd import LsqrSystem
 
-    spec = synth.CONFIGS[cfg]
+    spec = synth.WORKLOADS[cfg]
     t0 = time.perf_counter()
     arrays, first = synth.device_system(spec, dev)
     m = int(first[-1])
@@ -226,7 +226,7 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
     import synth
     from paper_2308_00778_amd import LsqrSystem
 
-    spec = synth.CONFIGS[cfg]
+    spec = synth.WORKLOADS[cfg]
     arrays, first = synth.device_system(spec, dev)
     m = int(first[-1])
     g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
@@ -278,7 +278,7 @@ def batched_leg(cfg: int, dev, singles: int = 2):
     import synth
     from paper_2308_00778_amd import LsqrSystem
 
-    spec = synth.CONFIGS[cfg]
+    spec = synth.WORKLOADS[cfg]
     k = spec.n_rhs
     t0 = time.perf_counter()
     arrays, first = synth.device_system(spec, dev)
@@ -350,7 +350,7 @@ def largest_leg(cfg: int, dev):
     def free_gb():
         return torch.cuda.mem_get_info(dev)[0] / 1e9
 
-    spec = synth.CONFIGS[cfg]
+    spec = synth.WORKLOADS[cfg]
     k = spec.n_rhs
     t0 = time.perf_counter()
     arrays, first = synth.device_system(spec, dev)
@@ -454,7 +454,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)  # the workload's timed iteration count
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="refine,batched",
                     help="comma list of extra legs: refine (FP32 + FP64 refinement), "
@@ -465,8 +465,8 @@ def main():
                     help="only time the attitude variants of aprod2")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding "
-              "is a design, not a build, here", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solver's "
+              "multi-GPU sharding is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -479,9 +479,9 @@ def main():
         copy_calibration(dev)
         return
     if args.attitude_ab:
-        attitude_ab(dev, args.config)
+        attitude_ab(dev, args.workload)
         return
-    spec = synth.CONFIGS[args.config]
+    spec = synth.WORKLOADS[args.workload]
     assert spec.value_dtype == "f64", "the FP64 bench runs on an FP64 workload"
     t0 = time.perf_counter()
     arrays, first = synth.device_system(spec, dev)
@@ -514,7 +514,7 @@ def main():
     gbps = {k: BYTES_PER_ROW[k] * m / (ms[k] * 1e-3) / 1e9 for k in ms}
     dom = max(ms, key=ms.get)
     # counter-measured HBM bytes per launch (committed profile of this workload)
-    traffic = {k: counter_traffic(k) if args.config == 1 else None for k in ms}
+    traffic = {k: counter_traffic(k) if args.workload == 1 else None for k in ms}
     log(f"timed {args.steps} iterations in {wall:.3f} s; " +
         ", ".join(f"{k} {ms[k]:.3f} ms ({gbps[k]:.0f} GB/s)" for k in ms))
 

@@ -170,7 +170,7 @@ BASE_SEED = 20230801
 
 # The five workloads: a parity-sized system, the single-GPU production share,
 # the mixed-precision system, the batched system and the largest system.
-CONFIGS = {
+WORKLOADS = {
     0: Spec(n_stars=1_000, obs_lo=100, obs_hi=100, n_dfa=1_000, n_instr_cols=120,
             seed=BASE_SEED + 0),
     1: Spec(n_stars=1_000_000, obs_lo=100, obs_hi=100, n_dfa=100_000, n_instr_cols=6_000,

@@ -23,7 +23,7 @@ def torch_cuda():
 
 @pytest.fixture(scope="module")
 def c0():
-    S = synth.make_system(synth.CONFIGS[0])
+    S = synth.make_system(synth.WORKLOADS[0])
     o = oracle.OracleSystem.from_synth(S)
     xt = synth.x_true(S.spec)
     B = np.stack([o.aprod1(xt, synth.noise(S.spec, S.m, rhs=j)) for j in range(5)], axis=1)

@@ -49,7 +49,7 @@ def _handle(spec):
 @pytest.fixture(scope="module")
 def c1(torch_cuda):
     torch = torch_cuda
-    spec = synth.CONFIGS[1]
+    spec = synth.WORKLOADS[1]
     say(f"full size: generating the 1e8-row system on the GPU (seed {spec.seed})")
     g, first, arrays = _handle(spec)
     yield spec, g, first
@@ -176,7 +176,7 @@ def test_fullsize_converged_normal_equations(torch_cuda, c1):
 
 def test_fullsize_fp32_system_and_refinement(torch_cuda, c1):
     torch = torch_cuda
-    spec = synth.CONFIGS[2]
+    spec = synth.WORKLOADS[2]
     say(f"full size: generating the 4e8-row FP32 system on the GPU (seed {spec.seed})")
     g, first, arrays = _handle(spec)
     try:

@@ -38,7 +38,7 @@ def torch_cuda():
 # 1..6 observations (rank-deficient astrometric blocks) appear in the exact
 # operator checks only.
 SPECS = {
-    "c0": synth.CONFIGS[0],
+    "c0": synth.WORKLOADS[0],
     "ragged": synth.tiny(seed=21, n_stars=37, obs=(10, 140), n_dfa=50, n_instr_cols=17),
     "short_stars": synth.tiny(seed=25, n_stars=300, obs=(1, 6), n_dfa=40, n_instr_cols=11),
     "one_star": synth.tiny(seed=22, n_stars=1, obs=(70, 70), n_dfa=8, n_instr_cols=6),

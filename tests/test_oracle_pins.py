@@ -72,7 +72,7 @@ def check_aprod_dense():
 
 def check_adjoint_identity():
     rng = np.random.default_rng(2)
-    S = synth.make_system(synth.CONFIGS[0])
+    S = synth.make_system(synth.WORKLOADS[0])
     o = oracle.OracleSystem.from_synth(S)
     x = rng.standard_normal(o.n)
     y = rng.standard_normal(o.m)
@@ -230,7 +230,7 @@ def check_recurrence_invariants():
 
 
 def check_noise_free_recovery():
-    S = synth.make_system(synth.CONFIGS[0])
+    S = synth.make_system(synth.WORKLOADS[0])
     o = oracle.OracleSystem.from_synth(S)
     xt = synth.x_true(S.spec)
     b = o.aprod1(xt)

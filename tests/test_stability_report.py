@@ -63,7 +63,7 @@ def test_gpu_solution_consistent_with_oracle():
 
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    S = synth.make_system(synth.CONFIGS[0])
+    S = synth.make_system(synth.WORKLOADS[0])
     o = oracle.OracleSystem.from_synth(S)
     b = o.aprod1(synth.x_true(S.spec), synth.noise(S.spec, S.m))
     x_ref, i_ref, var_ref = o.lsqr(b, 500, atol=1e-12, btol=1e-12, conlim=0.0, want_var=True)

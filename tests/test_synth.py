@@ -23,7 +23,7 @@ def test_philox_known_answers():
 
 @pytest.mark.parametrize("cfg", [0])
 def test_structure_invariants(cfg):
-    sp = synth.CONFIGS[cfg]
+    sp = synth.WORKLOADS[cfg]
     S = synth.make_system(sp)
     assert S.m == 100_000 and S.n == 8_121
     assert np.all(np.diff(S.star_of_row) >= 0)
@@ -67,7 +67,7 @@ def test_reproducible_and_range_independent():
     n1 = synth.noise(sp, m, rhs=0)
     assert np.array_equal(n1[r0:r1], synth.noise(sp, m, rhs=0, i0=r0, i1=r1))
     assert not np.array_equal(n1, synth.noise(sp, m, rhs=1))
-    assert abs(np.std(synth.noise(synth.CONFIGS[0], 100_000)) - 1e-6) < 2e-8
+    assert abs(np.std(synth.noise(synth.WORKLOADS[0], 100_000)) - 1e-6) < 2e-8
 
 
 def test_generator_ln_exp_accuracy():

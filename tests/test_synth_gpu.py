@@ -17,7 +17,7 @@ def torch_cuda():
 
 
 @pytest.mark.parametrize("spec", [
-    synth.CONFIGS[0],
+    synth.WORKLOADS[0],
     synth.tiny(seed=41, n_stars=500, obs=(50, 150), n_dfa=700, n_instr_cols=300),
     synth.tiny(seed=42, n_stars=300, obs=(90, 110), n_dfa=900, n_instr_cols=2000,
                value_dtype="f32", astro_scale=(-2.0, 2.0)),
@@ -45,7 +45,7 @@ def test_device_generator_is_bit_identical(torch_cuda, spec):
 def test_device_generator_full_size_prefix(torch_cuda):
     # the 1e8-row workload: sampled row ranges against the host generator
     torch = torch_cuda
-    spec = synth.CONFIGS[1]
+    spec = synth.WORKLOADS[1]
     print("generator twin: 1e8-row workload, sampled rows", flush=True)
     dev, first = synth.device_system(spec, "cuda:0")
     m = int(first[-1])
