@@ -199,6 +199,29 @@ def test_solve_without_compact_index(torch_cuda, name, itn, fused):
     _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], fused=fused, compact=0)
 
 
+def test_compact_index_toggle(torch_cuda):
+    # copies built on the first solve, freed (graphs dropped) when the option
+    # is switched off, rebuilt when it is switched on again: same iterates
+    torch = torch_cuda
+    S, o = system("c0")
+    b = torch.from_numpy(_b(S, o)).cuda()
+    say("compact index copies toggled between solves: c0")
+    g = gpu_system(torch, S)
+    g.set_option("tests", 0)  # graph replay: the captured graphs must follow
+    xs, flags = [], []
+    for compact in (1, 0, 1):
+        g.set_option("compact_index", compact)
+        x, _ = g.solve(b, 30, atol=0.0, btol=0.0)
+        xs.append(x.cpu().numpy())
+        flags.append(g.pass_times()["compact"])
+    g.close()
+    assert flags == [1, 0, 1]
+    x_ref, _ = o.lsqr(_b(S, o), 30, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+    for xg in xs:
+        assert rel_inf(xg, x_ref) <= 1e-10
+    assert rel_inf(xs[1], xs[0]) <= 1e-13 and rel_inf(xs[2], xs[0]) <= 1e-13
+
+
 def _solve_fixed(torch_cuda, name, itn, graph, variant, interleave=1, fused=2, compact=1):
     torch = torch_cuda
     S, o = system(name)
