@@ -184,6 +184,14 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *   LSQR_OPT_KTILE        batched solves: right-hand sides advanced together per
  *                         pass over A (1, 2, 4, 8), 0 (default) = autotune once
  *                         per handle
+ *   LSQR_OPT_ATT_RHS      right-hand sides one sweep of the bucket-order
+ *                         attitude passes holds (1 default, 2, 4, 8): the
+ *                         buckets narrow until that many LDS windows /
+ *                         histograms fit, so a batched k-tile of up to that
+ *                         many RHS reads the attitude coefficients once per
+ *                         pass instead of once per RHS (single-RHS passes pay
+ *                         a few percent for the extra buckets); settable only
+ *                         before the first solve or aprod2
  */
 #define LSQR_OPT_CONLIM 1
 #define LSQR_OPT_TESTS 2
@@ -199,6 +207,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_FUSED 12
 #define LSQR_OPT_VARIANCE 13
 #define LSQR_OPT_COMPACT_INDEX 14
+#define LSQR_OPT_ATT_RHS 15
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
 
 /* Below, m counts every row: n_rows observation rows plus n_con constraint

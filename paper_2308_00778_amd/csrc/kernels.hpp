@@ -1500,12 +1500,15 @@ __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val
 
 // Attitude part of Eq. (2) over the rows in bucket order, folded into the
 // row vector: u~[k] <- sum_c a_c x[col_c] - coef_u u~[k] for the 12 attitude
-// coefficients of row k (u~ in bucket order, coalesced). The G workgroups of
-// a bucket share its rows as in k_att_hist; the bucket's
-// attitude columns [b W, b W + W + 3) of the interleaved copy x3 are staged
-// in LDS first (win[3 c + axis], 3 (W + 3) Acc), so no row gathers from
-// global memory. The fused pass (kAttPre) then adds the other sections.
-template <typename T, typename Acc, int NT>
+// coefficients of row k (u~ in bucket order, coalesced), for K right-hand
+// sides (u~ [m][K] row-interleaved, x3 [3 n_dfa][K]). The G workgroups of a
+// bucket share its rows as in k_att_hist; the bucket's attitude columns
+// [b W, b W + W + 3) of the interleaved copy x3 are staged in LDS first
+// (win[(3 c + axis) KS + j], 3 (W + 3) KS Acc), so no row gathers from global
+// memory. KS right-hand sides share one sweep over the rows (one window each);
+// K / KS sweeps cover the tile. Frozen RHS (done) keep u~. The fused pass
+// (kAttPre) then adds the other sections.
+template <typename T, typename Acc, int K, int KS, int NT>
 __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__ att_sorted,
                                                  const int32_t* __restrict__ tloc,
                                                  const int64_t* __restrict__ bstart,
@@ -1513,46 +1516,74 @@ __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__
                                                  const Acc* __restrict__ x3, Acc* __restrict__ u,
                                                  const Scalars* __restrict__ sc)
 {
+    static_assert(K % KS == 0, "sweeps of KS right-hand sides cover the tile");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Acc* win = reinterpret_cast<Acc*>(smem_raw);
-    if (sc->done) return;
     const int64_t span = width + kParAxis - 1;
     const int64_t bk = blockIdx.x / G, g = blockIdx.x - bk * G;
     const int64_t c0 = bk * width;
     // columns past n_dfa - 1 are never referenced (t + 3 <= n_dfa - 1)
     const int64_t ncol = span < n_dfa - c0 ? span : n_dfa - c0;
-    for (int64_t e = threadIdx.x; e < kAxes * ncol; e += NT) win[e] = x3[kAxes * c0 + e];
-    __syncthreads();
-    const int64_t b0 = bstart[bk], len = bstart[bk + 1] - b0;
-    const int64_t r1 = b0 + len;
-    const Acc coef = (Acc)sc->coef_u;
-    for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += (int64_t)G * NT) {
-        const int64_t tl = ldnt(&tloc[k]);
-        T a[kAxes * kParAxis];
+    const int64_t b0 = bstart[bk], r1 = bstart[bk + 1];
+    for (int s0 = 0; s0 < K; s0 += KS) {
+        uint32_t live = 0;
+        Acc coef[KS];
 #pragma unroll
-        for (int c = 0; c < kAxes * kParAxis; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
-        const Acc uo = u[k];
-        Acc d = (Acc)0;
+        for (int j = 0; j < KS; ++j) {
+            live |= (sc[s0 + j].done ? 0u : 1u) << j;
+            coef[j] = (Acc)sc[s0 + j].coef_u;
+        }
+        if (live == 0) continue;  // uniform over the grid
+        if (KS == K) {
+            for (int64_t e = threadIdx.x; e < kAxes * ncol * K; e += NT)
+                win[e] = x3[kAxes * c0 * K + e];
+        } else {
+            for (int64_t e = threadIdx.x; e < kAxes * ncol * KS; e += NT) {
+                const int64_t col = e / KS;
+                win[e] = x3[(kAxes * c0 + col) * K + s0 + (e - col * KS)];
+            }
+        }
+        __syncthreads();
+        for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += (int64_t)G * NT) {
+            const int64_t tl = ldnt(&tloc[k]);
+            T a[kAxes * kParAxis];
 #pragma unroll
-        for (int ax = 0; ax < kAxes; ++ax)
+            for (int c = 0; c < kAxes * kParAxis; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
+            Acc d[KS];
 #pragma unroll
-            for (int qq = 0; qq < kParAxis; ++qq)
-                d += (Acc)a[ax * kParAxis + qq] * win[kAxes * (tl + qq) + ax];
-        u[k] = d - coef * uo;
+            for (int j = 0; j < KS; ++j) d[j] = (Acc)0;
+#pragma unroll
+            for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+                for (int qq = 0; qq < kParAxis; ++qq) {
+                    const Acc av = (Acc)a[ax * kParAxis + qq];
+                    const Acc* w = win + (kAxes * (tl + qq) + ax) * KS;
+#pragma unroll
+                    for (int j = 0; j < KS; ++j) d[j] += av * w[j];
+                }
+#pragma unroll
+            for (int j = 0; j < KS; ++j) {
+                if (!((live >> j) & 1u)) continue;
+                Acc* up = u + k * K + s0 + j;
+                *up = d[j] - coef[j] * *up;
+            }
+        }
+        __syncthreads();  // the next sweep restages the window
     }
 }
 
 // Attitude part of Eq. (3) over the rows in bucket order. The G workgroups
 // of bucket b share its rows in interleaved blocks of NT (workgroup w = b G +
 // g takes blocks g, g + G, ..., so the G streams advance through memory
-// together): an LDS histogram hist[axis][W + 3] gets a * u for the 12
-// coefficients of each of its rows, then is stored as S2[w][r][axis][W + 3];
-// k_att_reduce adds the slices. The histogram and S2 are FP64 whatever Acc is: gfx950's LDS FP64
-// atomic add runs at 7.6x the rate of the FP32 one (measured, random
-// addresses over 150 KB: 1550 vs 204 G/s), and the sums are more accurate.
-// U is in bucket order ([m][K], K right-hand sides swept one after another).
-// Frozen RHS (done or beta_zero) are skipped.
-template <typename T, typename Acc, int K, int NT>
+// together): an LDS histogram hist[axis][W + 3][KS] gets a * u for the 12
+// coefficients of each of its rows and the KS right-hand sides of one sweep,
+// then is stored as S2[w][r][axis][W + 3]; k_att_reduce adds the slices. The
+// histogram and S2 are FP64 whatever Acc is: gfx950's LDS FP64 atomic add
+// runs at 7.6x the rate of the FP32 one (measured, random addresses over
+// 150 KB: 1550 vs 204 G/s), and the sums are more accurate. U is in bucket
+// order ([m][K]); K / KS sweeps cover the tile. Frozen RHS (done or
+// beta_zero) are skipped.
+template <typename T, typename Acc, int K, int KS, int NT>
 __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict__ att_sorted,
                                                   const int32_t* __restrict__ tloc,
                                                   const int64_t* __restrict__ bstart,
@@ -1560,19 +1591,25 @@ __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict_
                                                   double* __restrict__ S2,
                                                   const Scalars* __restrict__ sc)
 {
+    static_assert(K % KS == 0, "sweeps of KS right-hand sides cover the tile");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double* hist = reinterpret_cast<double*>(smem_raw);
     const int64_t span = width + kParAxis - 1;
     const int64_t bk = blockIdx.x / G, g = blockIdx.x - bk * G;
-    const int64_t b0 = bstart[bk], len = bstart[bk + 1] - b0;
-    const int64_t r1 = b0 + len;
-    for (int r = 0; r < K; ++r) {
-        if (sc != nullptr && (sc[r].done || sc[r].beta_zero)) continue;  // uniform
-        for (int64_t e = threadIdx.x; e < kAxes * span; e += NT) hist[e] = 0.0;
+    const int64_t b0 = bstart[bk], r1 = bstart[bk + 1];
+    for (int s0 = 0; s0 < K; s0 += KS) {
+        uint32_t live = 0;
+#pragma unroll
+        for (int j = 0; j < KS; ++j)
+            live |= (sc != nullptr && (sc[s0 + j].done || sc[s0 + j].beta_zero) ? 0u : 1u) << j;
+        if (live == 0) continue;  // uniform over the grid
+        for (int64_t e = threadIdx.x; e < kAxes * span * KS; e += NT) hist[e] = 0.0;
         __syncthreads();
         for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += (int64_t)G * NT) {
             const int64_t tl = ldnt(&tloc[k]);
-            const double uk = (double)U[k * K + r];
+            double uk[KS];
+#pragma unroll
+            for (int j = 0; j < KS; ++j) uk[j] = (double)U[k * K + s0 + j];
             T a[kAxes * kParAxis];  // all loads issued before the first atomic
 #pragma unroll
             for (int c = 0; c < kAxes * kParAxis; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
@@ -1580,11 +1617,18 @@ __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict_
             for (int ax = 0; ax < kAxes; ++ax)
 #pragma unroll
                 for (int qq = 0; qq < kParAxis; ++qq)
-                    atomicAdd(&hist[ax * span + tl + qq], (double)a[ax * kParAxis + qq] * uk);
+#pragma unroll
+                    for (int j = 0; j < KS; ++j)
+                        if ((live >> j) & 1u)
+                            atomicAdd(&hist[(ax * span + tl + qq) * KS + j],
+                                      (double)a[ax * kParAxis + qq] * uk[j]);
         }
         __syncthreads();
-        double* out = S2 + ((int64_t)blockIdx.x * K + r) * kAxes * span;
-        for (int64_t e = threadIdx.x; e < kAxes * span; e += NT) out[e] = hist[e];
+        for (int j = 0; j < KS; ++j) {
+            if (!((live >> j) & 1u)) continue;
+            double* out = S2 + ((int64_t)blockIdx.x * K + s0 + j) * kAxes * span;
+            for (int64_t e = threadIdx.x; e < kAxes * span; e += NT) out[e] = hist[e * KS + j];
+        }
         __syncthreads();
     }
 }
@@ -1890,10 +1934,11 @@ __global__ __launch_bounds__(kBlock) void k_interleave_att(const double* __restr
 // registers scattered into Q += A^T U~ for the astrometric, instrumental and
 // global columns. Frozen RHS keep U and contribute nothing. Dynamic LDS: the
 // FP64 histogram [hcols][K] of instrumental columns [0, hcols) (the others
-// are left to k_instr_tail), then the instrumental slice of VP (LDSX). In 1024-thread workgroups (128 registers
-// per lane) a multi-RHS tile reduces its star segments chunk by chunk instead
-// of carrying 5K running sums. AM as in the single-RHS pass (kAttPre with
-// K = 1 only: k_att_dot's window holds one RHS).
+// are left to k_instr_tail), then the instrumental slice of VP (LDSX). In
+// 1024-thread workgroups (128 registers per lane) a multi-RHS tile would
+// reduce its star segments chunk by chunk instead of carrying 5K running sums;
+// the tiles run in 512 or 256 threads, which have the registers. AM as in the single-RHS pass (kAttPre after
+// k_att_dot over the tile's K right-hand sides).
 template <typename T, typename Acc, int K, int NT, bool LDSX, int AM, bool CIDX>
 __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ VP,
                                                const Acc* __restrict__ X3, Acc* __restrict__ U,
@@ -1938,7 +1983,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         ssq[r] = 0.0;
         gsum[r] = (Acc)0;
     }
-    constexpr bool kChunkFlush = NT > kBlock && K > 1;
+    constexpr bool kChunkFlush = NT > 512 && K > 1;
     SegAcc<Acc, kChunkFlush ? 1 : kAstro * K> seg;
     auto astro_emit = [Q](int64_t star, const Acc (&tot)[kAstro * K]) {
         Acc* dst = Q + kAstro * star * K;
@@ -1989,7 +2034,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         for (int r = 0; r < K; ++r) {
             d[r] += (Acc)a[kOffGlob] * xg[r];
             const bool on = ok && ((live >> r) & 1u);
-            // kAttPre (K = 1): U already holds the attitude part minus coef U
+            // kAttPre: U already holds the attitude part minus coef U
             const Acc nu = AM == kAttPre ? d[r] + U[pu * K + r] : d[r] - coef[r] * U[pu * K + r];
             if (on) U[pu * K + r] = nu;
             d[r] = on ? nu : (Acc)0;

@@ -103,7 +103,6 @@ constexpr int kWavesPerCU = 16;                 // row ranges per compute unit i
 // accesses of the star-order passes through inv cost more the more runs they
 // split into (measured on 1e8 rows: +0.17 ms at 16 buckets, +0.65 ms at 25,
 // +1.6 ms at 100).
-constexpr int64_t kAttWidthMax = kLdsInstrBudget / (kAxes * 8) - (kParAxis - 1);
 constexpr int kAttBlock = 1024;  // attitude-pass workgroup (one per CU: the histogram fills LDS)
 
 // Working vectors of one arithmetic precision of the LSQR loop.
@@ -176,6 +175,7 @@ struct lsqr_handle {
     int64_t bwidth = 0;           // attitude starts per bucket (W)
     int att_g = 1;                // attitude-pass workgroups per bucket
     int64_t att_buckets = 0;      // requested bucket count (0: as few as fit)
+    int att_rhs = 1;              // right-hand sides one attitude sweep must hold
     double* S2 = nullptr;         // [nbk att_g][3][W + 3] slices of the attitude pass
     double* us_raw = nullptr;     // [m] lsqr_aprod2's row vector in bucket order
     double* x3_raw = nullptr;     // interleaved attitude section of lsqr_aprod1's x
@@ -362,7 +362,7 @@ template <typename T, typename Acc>
 void launch_att_dot(const lsqr_handle* h, Path<Acc>& P, hipStream_t st)
 {
     const size_t lds = (size_t)(kAxes * att_span(h)) * sizeof(Acc);
-    hipLaunchKernelGGL((k_att_dot<T, Acc, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock), lds,
+    hipLaunchKernelGGL((k_att_dot<T, Acc, 1, 1, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock), lds,
                        st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
                        (const int64_t*)h->bstart, h->bwidth, h->att_g, h->sv.n_dfa,
                        (const Acc*)P.vp3, P.u, h->sc);
@@ -392,7 +392,7 @@ template <typename T, typename Acc>
 void launch_att_pass(lsqr_handle* h, const Acc* ub, Acc* q, const Scalars* sc, hipStream_t st)
 {
     const size_t lds = (size_t)(kAxes * att_span(h) * 8);
-    hipLaunchKernelGGL((k_att_hist<T, Acc, 1, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock),
+    hipLaunchKernelGGL((k_att_hist<T, Acc, 1, 1, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock),
                        lds, st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
                        (const int64_t*)h->bstart, h->bwidth, h->att_g, ub, h->S2, sc);
     hipLaunchKernelGGL((k_att_reduce<Acc, 1>), dim3(h->nbc), dim3(kBlock), 0, st,
@@ -541,18 +541,20 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     return LSQR_OK;
 }
 
-// Attitude bucket geometry: the fewest buckets whose FP64 histogram fits in
-// LDS, or the requested count (raised if needed). Workgroups per bucket G:
+// Attitude bucket geometry: the fewest buckets whose FP64 histogram (for
+// att_rhs right-hand sides per sweep) fits in LDS, or the requested count
+// (raised if needed). Workgroups per bucket G:
 // one workgroup fits per CU, so the pass takes ceil(nbk G / CUs) rounds of
 // 1/G of a bucket each; G minimises that (up to max(8, CUs / nbk), ties to
 // the smaller G, which keeps the slices to add up few).
 void att_geometry(lsqr_handle* h)
 {
     const int64_t nt = h->sv.n_dfa - kParAxis + 1;
-    int64_t nb = h->att_buckets > 0 ? h->att_buckets : cdiv(nt, kAttWidthMax);
+    const int64_t wmax = kLdsInstrBudget / (kAxes * 8 * h->att_rhs) - (kParAxis - 1);
+    int64_t nb = h->att_buckets > 0 ? h->att_buckets : cdiv(nt, wmax);
     nb = std::max<int64_t>(1, std::min(nb, nt));
     int64_t w = cdiv(nt, nb);
-    if (w > kAttWidthMax) w = kAttWidthMax;
+    if (w > wmax) w = wmax;
     h->bwidth = w;
     h->nbk = cdiv(nt, w);
     const int64_t cu = std::max(1, h->num_cu);
@@ -895,23 +897,63 @@ constexpr int batch_nt() { return K <= 2 ? kBlock2 : kBlock; }
 template <int K>
 int batch_grid(const lsqr_handle* h) { return K <= 2 ? h->nb2 : h->nba; }
 
-// The fused pass of a K = 2 tile holds two RHS worth of gathered vector
-// values as well as the row: 512-thread workgroups (256 registers per lane).
-template <int K>
-constexpr int fused_nt() { return K == 1 ? kBlock2 : (K == 2 ? kBlock1 : kBlock); }
+// Workgroup shape of the fused pass of a K-tile: multi-RHS tiles carry K
+// values per gathered vector entry and 5K running star sums, so K = 2 runs
+// 512-thread workgroups (256 registers per lane) and wider tiles 256; after
+// the attitude pre-pass (kAttPre, no attitude gathers) K = 4 fits 512 too.
+template <int K, int AM>
+constexpr int fused_nt()
+{
+    if (K == 1) return kBlock2;
+    return K == 2 || (K == 4 && AM == kAttPre) ? kBlock1 : kBlock;
+}
 
+template <int K, int AM>
+int fused_grid(const lsqr_handle* h) { return (int)(h->nw / (fused_nt<K, AM>() / kWave)); }
+
+// Workgroups (partials) of the fused pass an iteration of a K-tile runs
 template <int K>
-int fused_grid(const lsqr_handle* h) { return (int)(h->nw / (fused_nt<K>() / kWave)); }
+int batch_fused_grid(const lsqr_handle* h)
+{
+    return h->fused == 2 ? fused_grid<K, kAttPre>(h) : fused_grid<K, kAttX>(h);
+}
+
+// Right-hand sides per sweep of the bucket-order attitude passes of a K-tile:
+// the largest power of two up to K whose window or histogram, 3 (W + 3) KS
+// doubles, fits in LDS. Narrower buckets (more of them) widen the sweeps.
+template <int K>
+int att_sweep(const lsqr_handle* h)
+{
+    const int64_t fit = kLdsInstrBudget / (kAxes * att_span(h) * 8);
+    int ks = 1;
+    while (ks * 2 <= K && ks * 2 <= fit) ks *= 2;
+    return ks;
+}
+
+template <int K, typename F>
+void by_sweep(int ks, F&& f)
+{
+    if constexpr (K >= 8)
+        if (ks == 8) return f(std::integral_constant<int, 8>());
+    if constexpr (K >= 4)
+        if (ks == 4) return f(std::integral_constant<int, 4>());
+    if constexpr (K >= 2)
+        if (ks == 2) return f(std::integral_constant<int, 2>());
+    f(std::integral_constant<int, 1>());
+}
 
 template <typename T, int K>
 void batch_att_pass(lsqr_handle* h, hipStream_t st)
 {
     auto& B = h->batch;
-    const size_t lds = (size_t)(kAxes * att_span(h) * 8);
-    hipLaunchKernelGGL((k_att_hist<T, double, K, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock),
-                       lds, st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
-                       (const int64_t*)h->bstart, h->bwidth, h->att_g, (const double*)B.U, B.S2,
-                       B.sc);
+    const int ks = att_sweep<K>(h);
+    by_sweep<K>(ks, [&](auto KS) {
+        hipLaunchKernelGGL((k_att_hist<T, double, K, KS(), kAttBlock>), dim3(att_slices(h)),
+                           dim3(kAttBlock), (size_t)(kAxes * att_span(h) * 8 * ks), st, h->sv.m,
+                           (const T*)h->att_sorted, (const int32_t*)h->tloc,
+                           (const int64_t*)h->bstart, h->bwidth, h->att_g, (const double*)B.U,
+                           B.S2, B.sc);
+    });
     hipLaunchKernelGGL((k_att_reduce<double, K>), dim3(h->nbc), dim3(kBlock), 0, st,
                        (const double*)B.S2, h->nbk, h->att_g, h->bwidth, h->sv.n_dfa,
                        B.Q + h->sv.att_base * K, B.sc);
@@ -956,19 +998,19 @@ template <typename T, int K, bool LDSX, int AM>
 void batch_fused_as(lsqr_handle* h, const double* X3, int64_t hc, size_t lds, hipStream_t st)
 {
     auto& B = h->batch;
-    constexpr int NT = fused_nt<K>();
+    constexpr int NT = fused_nt<K, AM>();
     if (h->sv.star32)
         hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, LDSX, AM, true>),
-                           dim3(fused_grid<K>(h)), dim3(NT), lds, st, h->sv, (const double*)B.VP,
+                           dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv, (const double*)B.VP,
                            X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc, B.sc, row_map(h));
     else
         hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, LDSX, AM, false>),
-                           dim3(fused_grid<K>(h)), dim3(NT), lds, st, h->sv, (const double*)B.VP,
+                           dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv, (const double*)B.VP,
                            X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc, B.sc, row_map(h));
 }
 
-// The fused pass of a k-tile; a one-RHS tile in fused mode 2 first runs the
-// attitude pre-pass (k_att_dot on the tile's U, X3 and Scalars).
+// The fused pass of a k-tile; in fused mode 2 the attitude pre-pass
+// (k_att_dot on the tile's U, X3 and Scalars) runs first.
 template <typename T, int K>
 void batch_fused(lsqr_handle* h, hipStream_t st)
 {
@@ -976,7 +1018,7 @@ void batch_fused(lsqr_handle* h, hipStream_t st)
     int64_t hc = 0;
     int ldsx = 0;
     const size_t lds = batch_fused_lds<K>(h, &hc, &ldsx);
-    const bool pre = K == 1 && h->fused == 2;
+    const bool pre = h->fused == 2;
     const double* X3 = nullptr;
     if (h->att_il || pre) {
         hipLaunchKernelGGL((batched::k_interleave_att<K>), dim3(h->nbc), dim3(kBlock), 0, st,
@@ -984,11 +1026,14 @@ void batch_fused(lsqr_handle* h, hipStream_t st)
         X3 = B.X3;
     }
     if (pre) {
-        hipLaunchKernelGGL((k_att_dot<T, double, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock),
-                           (size_t)(kAxes * att_span(h) * 8), st, h->sv.m,
-                           (const T*)h->att_sorted, (const int32_t*)h->tloc,
-                           (const int64_t*)h->bstart, h->bwidth, h->att_g, h->sv.n_dfa, X3, B.U,
-                           (const Scalars*)B.sc);
+        const int ks = att_sweep<K>(h);
+        by_sweep<K>(ks, [&](auto KS) {
+            hipLaunchKernelGGL((k_att_dot<T, double, K, KS(), kAttBlock>), dim3(att_slices(h)),
+                               dim3(kAttBlock), (size_t)(kAxes * att_span(h) * 8 * ks), st,
+                               h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
+                               (const int64_t*)h->bstart, h->bwidth, h->att_g, h->sv.n_dfa, X3,
+                               B.U, (const Scalars*)B.sc);
+        });
         if (ldsx) batch_fused_as<T, K, true, kAttPre>(h, nullptr, hc, lds, st);
         else batch_fused_as<T, K, false, kAttPre>(h, nullptr, hc, lds, st);
     } else if (ldsx) {
@@ -1011,10 +1056,10 @@ void batch_iteration(lsqr_handle* h, hipStream_t st, hipEvent_t* ev)
         batch_fused<T, K>(h, st);
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL((batched::k_scalar_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1,
-                           fused_grid<K>(h), B.sc);
+                           batch_fused_grid<K>(h), B.sc);
         if (ev) (void)hipEventRecord(ev[2], st);
         hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
-                           (const double*)B.gpart, fused_grid<K>(h), B.Q + h->sv.glob_base * K,
+                           (const double*)B.gpart, batch_fused_grid<K>(h), B.Q + h->sv.glob_base * K,
                            B.sc);
         batch_att_pass<T, K>(h, st);
     } else {
@@ -1577,6 +1622,13 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         if (!(value == 0.0 || value == 1.0 || value == 2.0 || value == 4.0 || value == 8.0))
             return fail(LSQR_E_INVALID, "k-tile must be 0 (autotune), 1, 2, 4 or 8");
         h->ktile = (int)value;
+        return LSQR_OK;
+    case LSQR_OPT_ATT_RHS:
+        if (h->att_ready)
+            return fail(LSQR_E_STATE, "attitude sweep width must be set before the first solve");
+        if (!(value == 1.0 || value == 2.0 || value == 4.0 || value == 8.0))
+            return fail(LSQR_E_INVALID, "attitude sweep width must be 1, 2, 4 or 8");
+        h->att_rhs = (int)value;
         return LSQR_OK;
     case LSQR_OPT_ATT_BUCKETS: {
         if (h->att_ready)

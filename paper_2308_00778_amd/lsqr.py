@@ -24,7 +24,8 @@ LSQR_F32 = 1
 
 OPTIONS = {"conlim": 1, "tests": 2, "chunk": 3, "graph": 4, "profile": 5, "outer_tol": 6,
            "att_mode": 7, "astro_scan": 8, "ktile": 9, "att_buckets": 10,
-           "att_interleave": 11, "fused": 12, "variance": 13, "compact_index": 14}
+           "att_interleave": 11, "fused": 12, "variance": 13, "compact_index": 14,
+           "att_rhs": 15}
 
 SYMBOLS = ("lsqr_create", "lsqr_destroy", "lsqr_set_option", "lsqr_aprod1", "lsqr_aprod2",
            "lsqr_get_precond", "lsqr_get_variance", "lsqr_num_cols", "lsqr_solve",

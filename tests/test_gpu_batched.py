@@ -141,3 +141,47 @@ def test_batched_wide_instrumental(torch_cuda, ktile):
         x_ref, _ = o.lsqr(B[:, j], itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)
         assert infos[j].itn == itn
         assert rel_inf(Xh[:, j], x_ref) <= 1e-10, j
+
+
+# 7000 attitude starts: the bucket count sets how many right-hand sides one
+# sweep of the bucket-order attitude passes holds (3 (W + 3) KS doubles in
+# LDS): 2 buckets -> 1 per sweep, 3 -> 2, 6 -> 4. Five RHS in tiles of 2, 4
+# and 8 (the last tile of each carries frozen slots). 35,815 rows for 24,041
+# unknowns: with 300 stars x 20..60 rows the system is underdetermined and
+# two FP64 LSQRs drift apart within 30 iterations (the oracle and SciPy's
+# LSQR differ by 8e-8 there, by 4e-15 on this system).
+@pytest.fixture(scope="module")
+def wide_att():
+    spec = synth.tiny(seed=25, n_stars=600, obs=(40, 80), n_dfa=7000, n_instr_cols=40)
+    S = synth.make_system(spec)
+    o = oracle.OracleSystem.from_synth(S)
+    xt = synth.x_true(spec)
+    B = np.stack([o.aprod1(xt, synth.noise(spec, S.m, rhs=j)) for j in range(5)], axis=1)
+    return S, o, B
+
+
+# ("att_rhs", r): the bucket geometry sized for r RHS per sweep (2 -> 3
+# buckets, 4 -> 5, 8 -> 9 here).
+@pytest.mark.parametrize("geometry", [("att_buckets", 2), ("att_buckets", 3),
+                                      ("att_buckets", 6), ("att_rhs", 2), ("att_rhs", 4),
+                                      ("att_rhs", 8)])
+@pytest.mark.parametrize("ktile", [2, 4, 8])
+def test_batched_attitude_sweeps(torch_cuda, wide_att, geometry, ktile):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LsqrSystem
+
+    S, o, B = wide_att
+    itn = 30
+    say(f"batched parity: wide_att k=5 ktile={ktile} {geometry[0]}={geometry[1]} itn={itn}")
+    g = LsqrSystem.from_host(S, "cuda:0")
+    g.set_option(*geometry)
+    g.set_option("tests", 0)
+    g.set_option("ktile", ktile)
+    X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(B)).cuda(), itn, 0.0, 0.0)
+    Xh = X.cpu().numpy()
+    g.close()
+    for j in range(B.shape[1]):
+        x_ref, i_ref = o.lsqr(B[:, j], itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+        assert infos[j].itn == itn
+        assert rel_inf(Xh[:, j], x_ref) <= 1e-10, j
+        assert abs(infos[j].rnorm - i_ref.rnorm) <= 1e-8 * i_ref.rnorm

@@ -345,7 +345,7 @@ def test_option_errors(torch_cuda):
     say("option validation: few_rows")
     g = gpu_system(torch, S)
     bad = [("att_mode", 2), ("ktile", 3), ("chunk", 0), ("att_buckets", -1), ("outer_tol", -1.0),
-           ("fused", 3)]
+           ("fused", 3), ("att_rhs", 3), ("att_rhs", 0)]
     for name, value in bad:
         with pytest.raises(LsqrError) as ei:
             g.set_option(name, value)
@@ -354,9 +354,10 @@ def test_option_errors(torch_cuda):
     g.set_option("tests", 0)
     b = _b(S, o)
     g.solve(torch.from_numpy(b).cuda(), 5, atol=0.0, btol=0.0)
-    with pytest.raises(LsqrError) as ei:  # the bucket order exists now
-        g.set_option("att_buckets", 3)
-    assert ei.value.status == LSQR_E_STATE
+    for name, value in (("att_buckets", 3), ("att_rhs", 2)):
+        with pytest.raises(LsqrError) as ei:  # the bucket order exists now
+            g.set_option(name, value)
+        assert ei.value.status == LSQR_E_STATE, name
     with pytest.raises(LsqrError) as ei:  # refinement needs FP32-stored values
         g.solve_refined(torch.from_numpy(b).cuda(), 5, atol=1e-6, btol=1e-6, outer_limit=2)
     assert ei.value.status == LSQR_E_STATE
