@@ -270,9 +270,12 @@ def attitude_ab(dev, cfg: int = 1, itn: int = 20):
     print(json.dumps({"attitude_ab": out, "rows": m, "iterations": itn}))
 
 
-def batched_leg(cfg: int, dev, singles: int = 2):
+def batched_leg(cfg: int, dev, singles: int = 2, att_rhs: int = 4):
     """k noise realisations of b solved together (to convergence, atol = btol =
-    1e-12) against single-RHS solves of the same right-hand sides."""
+    1e-12) against single-RHS solves of the same right-hand sides. The batched
+    handle sizes its attitude buckets for att_rhs right-hand sides per sweep;
+    the single solves run on a handle of the default geometry (the fastest
+    single-RHS configuration)."""
     import torch
 
     import synth
@@ -283,17 +286,33 @@ def batched_leg(cfg: int, dev, singles: int = 2):
     t0 = time.perf_counter()
     arrays, first = synth.device_system(spec, dev)
     m = int(first[-1])
-    g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
-                   n_instr_cols=spec.n_instr_cols)
+    kw = dict(n_stars=spec.n_stars, n_dfa=spec.n_dfa, n_instr_cols=spec.n_instr_cols)
+    g1 = LsqrSystem(**arrays, **kw)
     xt = synth.device_x_true(spec, dev)
     B = torch.empty((m, k), dtype=torch.float64, device=dev)
     for j in range(k):
         bj = synth.device_noise(spec, m, j, dev)
-        g.aprod1(xt, bj)
+        g1.aprod1(xt, bj)
         B[:, j] = bj
         del bj
     torch.cuda.synchronize()
-    log(f"batched leg: m={m} n={g.n} k={k} ready in {time.perf_counter() - t0:.1f} s")
+    log(f"batched leg: m={m} n={g1.n} k={k} ready in {time.perf_counter() - t0:.1f} s")
+    # single-RHS solves of the first right-hand sides, same tolerances
+    g1.solve(B[:, 0].contiguous(), 3, 0.0, 0.0)  # bucket order, graphs
+    t_single, single_itn, xs = 0.0, 0, []
+    for j in range(singles):
+        bj = B[:, j].contiguous()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        xj, ij = g1.solve(bj, 500, 1e-12, 1e-12)
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t2
+        single_itn += ij.itn
+        xs.append(xj)
+    g1.close()
+    per_rhs_iter_single = t_single / single_itn
+    g = LsqrSystem(**arrays, **kw)
+    g.set_option("att_rhs", att_rhs)
     # autotune (first call) outside the timed region
     g.set_option("tests", 0)
     g.solve_batched(B[:, :8].contiguous(), 2, 0.0, 0.0)
@@ -305,22 +324,12 @@ def batched_leg(cfg: int, dev, singles: int = 2):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t1
     rhs_itn = sum(i.itn for i in infos)
-    # single-RHS solves of the first right-hand sides, same tolerances
-    t_single, single_itn, err = 0.0, 0, 0.0
-    for j in range(singles):
-        bj = B[:, j].contiguous()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        xj, ij = g.solve(bj, 500, 1e-12, 1e-12)
-        torch.cuda.synchronize()
-        t_single += time.perf_counter() - t2
-        single_itn += ij.itn
-        err = max(err, rel_inf(X[:, j], xj))
-    per_rhs_iter_single = t_single / single_itn
+    err = max(rel_inf(X[:, j], xs[j]) for j in range(singles))
     out = {
         "workload": f"{spec.n_stars} stars x {spec.obs_lo} obs = {m} rows x {g.n} unknowns, "
                     f"FP64, k = {k} noise realisations of b",
-        "k": k, "k_tile": tune["k_tile"], "autotune_ms_per_rhs_iter": tune["ms_per_rhs_iter"],
+        "k": k, "att_rhs": att_rhs, "k_tile": tune["k_tile"],
+        "autotune_ms_per_rhs_iter": tune["ms_per_rhs_iter"],
         "batched_seconds": t_batch, "rhs_iterations": rhs_itn,
         "rhs_iter_per_s": rhs_itn / t_batch,
         "itn_per_rhs": [i.itn for i in infos], "istop": sorted({i.istop for i in infos}),
@@ -330,7 +339,7 @@ def batched_leg(cfg: int, dev, singles: int = 2):
     }
     log(f"batched leg: {rhs_itn} RHS-iterations in {t_batch:.2f} s "
         f"({out['rhs_iter_per_s']:.1f}/s, single {out['single_rhs_iter_per_s']:.1f}/s, "
-        f"k_tile {tune['k_tile']}), err vs single {err:.2e}")
+        f"k_tile {tune['k_tile']}, att_rhs {att_rhs}), err vs single {err:.2e}")
     g.close()
     del arrays, B, X
     torch.cuda.empty_cache()
