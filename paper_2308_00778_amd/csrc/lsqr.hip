@@ -117,6 +117,7 @@ struct Path {
     size_t lds = 0;        // dynamic LDS bytes of aprod2's main pass
     size_t lds_f = 0;      // dynamic LDS bytes of the fused pass
     int f_ldsx = 0;        // fused pass: instrumental slice of vp in LDS
+    int64_t f_hcols = 0;   // fused pass: instrumental columns in its histogram
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
     bool ready = false;
@@ -275,6 +276,34 @@ void launch_instr_tail(const lsqr_handle* h, const Acc* U, const int32_t* inv, A
     }
 }
 
+// LDS of a fused pass over K right-hand sides: the FP64 histogram of the
+// first *hc instrumental columns and, when it fits beside it, the
+// instrumental slice of the vector (vbytes per value and RHS; *ldsx = 1).
+// When both do not fit, the histogram shrinks to leave room for the slice
+// as long as the columns it leaves out fit one tail window: gathering the
+// slice from L2 costs more than the extra tail pass over the rows (1e8 rows,
+// 2-RHS tiles: 140 -> 155 RHS-iterations/s).
+inline size_t fused_lds_plan(const lsqr_handle* h, int64_t K, int64_t vbytes, int64_t* hc,
+                             int* ldsx)
+{
+    *hc = instr_hcols(h, K);
+    const int64_t hist = (*hc * K * 8 + 15) & ~(int64_t)15;
+    const int64_t xbytes = h->sv.n_instr_cols * K * vbytes;
+    *ldsx = 1;
+    if (hist + xbytes <= kLdsInstrBudget) return (size_t)(hist + xbytes);
+    const int64_t tw = std::max<int64_t>(1, kLdsInstrBudget / (8 * K));
+    if (h->sv.ni > 0 && xbytes < kLdsInstrBudget) {
+        const int64_t room = std::min<int64_t>(
+            *hc, ((kLdsInstrBudget - xbytes) / (K * 8)) & ~(int64_t)63);
+        if (room >= 64 && h->sv.n_instr_cols - room <= tw) {
+            *hc = room;
+            return (size_t)(room * K * 8 + xbytes);
+        }
+    }
+    *ldsx = 0;
+    return (size_t)(*hc * K * 8);
+}
+
 // Constraint rows of aprod1 (y, b: their entries, after the observation
 // rows) and, except in A1_ACCUM, their share of ||u||^2 into part[0].
 template <typename Acc, typename VX, typename VY, int MODE>
@@ -349,11 +378,11 @@ void launch_fused_as(const lsqr_handle* h, Path<Acc>& P, const Acc* x3, hipStrea
     if (h->sv.star32)
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, LDSX, AM, true>), dim3(h->nb2), dim3(kBlock2),
                            P.lds_f, st, h->sv, (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart,
-                           h->part1, P.hcols, h->sc, row_map(h));
+                           h->part1, P.f_hcols, h->sc, row_map(h));
     else
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, LDSX, AM, false>), dim3(h->nb2),
                            dim3(kBlock2), P.lds_f, st, h->sv, (const Acc*)P.vp, x3, P.u, P.q,
-                           h->wb, P.gpart, h->part1, P.hcols, h->sc, row_map(h));
+                           h->wb, P.gpart, h->part1, P.f_hcols, h->sc, row_map(h));
 }
 
 // Attitude part of aprod1 in bucket order, folded into u~ (fused mode 2):
@@ -383,7 +412,7 @@ void launch_fused(const lsqr_handle* h, Path<Acc>& P, hipStream_t st, bool pre)
         if (x3) launch_fused_as<T, Acc, false, kAttX3>(h, P, x3, st);
         else launch_fused_as<T, Acc, false, kAttX>(h, P, x3, st);
     }
-    launch_instr_tail<T, Acc, 1, false>(h, P.u, row_map(h), P.q, P.hcols, h->sc, st);
+    launch_instr_tail<T, Acc, 1, false>(h, P.u, row_map(h), P.q, P.f_hcols, h->sc, st);
 }
 
 // Attitude part of aprod2 in bucket order: per-workgroup LDS histograms of
@@ -527,14 +556,10 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
     LSQR_TRY(dalloc(&P.q, n));
     LSQR_TRY(dalloc(&P.gpart, std::max<int64_t>(h->nb2, (int64_t)h->nba * kGlobMax)));
     LSQR_TRY(dalloc(&P.vp3, (int64_t)kAxes * h->sv.n_dfa));
-    // LDS histograms are FP64 whatever Acc is (k_att_hist); the fused pass
-    // keeps the histogram and, if both fit, the instrumental slice of vp
+    // LDS histograms are FP64 whatever Acc is (k_att_hist)
     P.hcols = instr_hcols(h, 1);
     P.lds = (size_t)(P.hcols * 8);
-    const int64_t hist = (P.hcols * 8 + 15) & ~(int64_t)15;
-    const int64_t xbytes = h->sv.n_instr_cols * (int64_t)sizeof(Acc);
-    P.f_ldsx = hist + xbytes <= kLdsInstrBudget ? 1 : 0;
-    P.lds_f = (size_t)(P.f_ldsx ? hist + xbytes : P.hcols * 8);
+    P.lds_f = fused_lds_plan(h, 1, (int64_t)sizeof(Acc), &P.f_hcols, &P.f_ldsx);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n, P.q, (Acc)0);
     HIP_TRY(hipGetLastError());
     P.ready = true;
@@ -981,17 +1006,11 @@ void batch_aprod2(lsqr_handle* h, hipStream_t st)
     if (h->att_mode != 0) batch_att_pass<T, K>(h, st);
 }
 
-// LDS of the fused pass of a K-tile: the histogram of the first hc
-// instrumental columns and, when every column is in it and both fit, the
-// instrumental slice of VP.
+// LDS of the fused pass of a K-tile (VP's values are FP64)
 template <int K>
 size_t batch_fused_lds(const lsqr_handle* h, int64_t* hc, int* ldsx)
 {
-    *hc = instr_hcols(h, K);
-    const int64_t hist = (*hc * K * 8 + 15) & ~(int64_t)15;
-    const int64_t xbytes = h->sv.n_instr_cols * K * 8;
-    *ldsx = hist + xbytes <= kLdsInstrBudget ? 1 : 0;
-    return (size_t)(*ldsx ? hist + xbytes : *hc * K * 8);
+    return fused_lds_plan(h, K, 8, hc, ldsx);
 }
 
 template <typename T, int K, bool LDSX, int AM>

@@ -116,9 +116,10 @@ def test_batched_autotune_picks_a_tile(torch_cuda, c0):
     assert rel_inf(Xh[:, 2], x_ref) <= 1e-10
 
 
-# 9000 instrumental columns: the fused pass keeps the K = 2 histogram in LDS
-# (144 KB) and gathers the instrumental slice from memory; K = 4 does not fit
-# and runs the separate passes.
+# 9000 instrumental columns: a K = 2 tile keeps the instrumental slice of VP
+# in LDS (144 KB) beside a 704-column histogram and leaves the other columns
+# to one tail window; a K = 4 tile keeps a 4,864-column histogram, gathers
+# the slice from memory and leaves the rest to the tail.
 @pytest.mark.parametrize("ktile", [2, 4])
 def test_batched_wide_instrumental(torch_cuda, ktile):
     torch = torch_cuda

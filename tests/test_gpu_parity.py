@@ -53,6 +53,14 @@ SPECS = {
     # copies) and four LDS windows (one histogram, three tail windows)
     "instr_70k": synth.tiny(seed=28, n_stars=300, obs=(30, 60), n_dfa=150,
                             n_instr_cols=70000),
+    # 12,000 instrumental columns: the FP64 histogram and the slice of vp do
+    # not both fit in LDS, so the fused pass keeps the slice and a 7,424-column
+    # histogram and leaves the rest to one tail window (FP32 values: FP64
+    # arithmetic on them, the same plan)
+    "instr_12k": synth.tiny(seed=29, n_stars=600, obs=(40, 80), n_dfa=150,
+                            n_instr_cols=12000),
+    "instr_12k_f32": synth.tiny(seed=30, n_stars=600, obs=(40, 80), n_dfa=150,
+                                n_instr_cols=12000, value_dtype="f32"),
     # FP32 values, 8,997 attitude starts: the default layout has two buckets
     # of FP64 histograms (exact operators and fixed-iteration solves only:
     # more attitude columns than rows)
@@ -163,6 +171,7 @@ def _b(S, o, rhs=0):
 @pytest.mark.parametrize("name,itn", [("c0", 50), ("c0", 200), ("ragged", 120),
                                        ("one_star", 15), ("few_rows", 15), ("wide_instr", 60),
                                        ("huge_instr", 30), ("instr_70k", 30),
+                                       ("instr_12k", 30), ("instr_12k_f32", 30),
                                        ("wide_att_f32", 30)])
 @pytest.mark.parametrize("graph", [1, 0])
 def test_solve_fixed_iterations(torch_cuda, name, itn, graph):
@@ -186,7 +195,7 @@ def test_solve_without_interleaved_attitude(torch_cuda, name, itn):
 @pytest.mark.parametrize("fused", [1, 0])
 @pytest.mark.parametrize("name,itn", [("c0", 60), ("ragged", 60), ("one_star", 15),
                                        ("few_rows", 15), ("wide_instr", 40),
-                                       ("wide_att_f32", 30)])
+                                       ("instr_12k", 30), ("wide_att_f32", 30)])
 def test_solve_other_fused_modes(torch_cuda, name, itn, fused):
     _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], fused=fused)
 
