@@ -451,9 +451,18 @@ def test_fp64_solve_on_float_values(torch_cuda):
     assert rel_inf(xg, x_ref) <= 1e-10
 
 
-def test_refined_matches_fp64_oracle(torch_cuda):
+# F32_WIDE: 30,000 instrumental columns. The FP32 inner solve keeps the
+# instrumental slice of vp (120 KB) and a 4,416-column histogram in LDS and
+# leaves the other columns to two tail windows; the FP64 residual and the
+# oracle see every column.
+F32_WIDE = synth.tiny(seed=32, n_stars=700, obs=(60, 100), n_dfa=200, n_instr_cols=30000,
+                      value_dtype="f32", astro_scale=(-2.0, 2.0))
+
+
+@pytest.mark.parametrize("spec", [F32_SPEC, F32_WIDE], ids=["f32", "f32_wide_instr"])
+def test_refined_matches_fp64_oracle(torch_cuda, spec):
     torch = torch_cuda
-    S = synth.make_system(F32_SPEC)
+    S = synth.make_system(spec)
     o = oracle.OracleSystem.from_synth(S)
     b = _b(S, o)
     x_ref, i_ref = o.lsqr(b, 500, atol=1e-14, btol=1e-14, conlim=0.0)
