@@ -972,7 +972,10 @@ template <typename T, int K>
 void batch_att_pass(lsqr_handle* h, hipStream_t st)
 {
     auto& B = h->batch;
-    const int ks = att_sweep<K>(h);
+    // at most 2 RHS per histogram sweep: 4 FP64 histograms fill LDS, leave
+    // one workgroup per CU and halve the rate of its atomics (1e8 rows, 64
+    // buckets: one 4-RHS sweep 6.3 ms, two 2-RHS sweeps 2 x 2.15 ms)
+    const int ks = std::min(2, att_sweep<K>(h));
     by_sweep<K>(ks, [&](auto KS) {
         hipLaunchKernelGGL((k_att_hist<T, double, K, KS(), kAttBlock>), dim3(att_slices(h)),
                            dim3(kAttBlock), (size_t)(kAxes * att_span(h) * 8 * ks), st, h->sv.m,
