@@ -218,6 +218,23 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
  * Asynchronous on the handle's stream; x and y must not overlap. */
 lsqr_status lsqr_aprod1(lsqr_handle* h, const double* x, double* y);
 
+/* Scratch capacity of lsqr_aprod1_noalloc, in doubles: 3 * 2^20 (24 MiB per
+ * GPU, so n_dfa <= 2^20 attitude columns per axis). */
+#define LSQR_NOALLOC_ATT_MAX (3 * 1048576)
+
+/* For callers that cannot allocate device memory (work recorded under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same y += A x as lsqr_aprod1, and calling no allocating routine. Its only
+ * scratch, the attitude section of x interleaved by axis (3 n_dfa doubles),
+ * lives in one library-wide device array of LSQR_NOALLOC_ATT_MAX doubles per
+ * GPU, held until the process ends and shared by every handle and thread on
+ * that GPU: calls that overlap on one GPU (two streams, two threads) race
+ * on it. Each call rewrites every element it reads, so nothing needs
+ * clearing between calls. Returns LSQR_E_INVALID when 3 n_dfa exceeds
+ * LSQR_NOALLOC_ATT_MAX. Asynchronous on the handle's stream, like
+ * lsqr_aprod1. */
+lsqr_status lsqr_aprod1_noalloc(lsqr_handle* h, const double* x, double* y);
+
 /* aprod mode 2, Eq. (3): x[n] += A^T y[m] with the raw A. Same conventions. */
 lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y);
 

@@ -26,6 +26,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -35,9 +36,22 @@
 
 using namespace avugsr;
 
+// Library-wide scratch of the no-allocation entry point (lsqr_aprod1_noalloc):
+// the attitude section of x interleaved by axis, LSQR_NOALLOC_ATT_MAX doubles.
+// Every GPU the library runs on holds its own copy at its own address until
+// the process ends. Host code never passes this name to a kernel (on the host
+// it only stands in for the symbol): it uses the per-device address taken
+// with hipGetSymbolAddress in lsqr_create.
+static __device__ __align__(256) double scratch[LSQR_NOALLOC_ATT_MAX];
+
 namespace {
 
 thread_local std::string g_last_error;
+
+// Device address of `scratch` per device ordinal, taken once per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
 
 lsqr_status fail(lsqr_status st, const char* fmt, ...)
 {
@@ -1311,6 +1325,22 @@ lsqr_status check_handle(lsqr_handle* h)
     return LSQR_OK;
 }
 
+// Address of the no-allocation scratch on the current device `dev`, taken
+// once per device (with that device current) and kept for later calls.
+lsqr_status scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(LSQR_E_UNSUPPORTED, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return LSQR_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+        return fail(LSQR_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    return LSQR_OK;
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -1367,6 +1397,8 @@ lsqr_status lsqr_create(const lsqr_system* sys, lsqr_handle** out)
     if (e != hipSuccess)
         return bail(fail(LSQR_E_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e)));
     h->num_cu = prop.multiProcessorCount;
+    // device address of the no-allocation scratch, once per device
+    if (lsqr_status sst = scratch_setup(h->device); sst != LSQR_OK) return bail(sst);
 
     SysView& s = h->sv;
     s.val = sys->values;
@@ -1700,6 +1732,37 @@ lsqr_status lsqr_aprod1(lsqr_handle* h, const double* x, double* y)
         if (!h->x3_raw) LSQR_TRY(dalloc(&h->x3_raw, (int64_t)kAxes * h->sv.n_dfa));
         launch_interleave_att<double>(h, x, h->x3_raw, nullptr, h->user_stream);
         x3 = h->x3_raw;
+    }
+    if (h->value_type == LSQR_F64)
+        launch_aprod1<double, double, double, double, A1_ACCUM>(h, x, y, nullptr, nullptr, nullptr,
+                                                                h->user_stream, nullptr, x3);
+    else
+        launch_aprod1<float, double, double, double, A1_ACCUM>(h, x, y, nullptr, nullptr, nullptr,
+                                                               h->user_stream, nullptr, x3);
+    HIP_TRY(hipGetLastError());
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_aprod1_noalloc(lsqr_handle* h, const double* x, double* y)
+{
+    LSQR_TRY(check_handle(h));
+    if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
+    const double* x3 = nullptr;
+    if (h->att_il && h->sv.natt > 0 && !h->generic) {
+        const int64_t need = (int64_t)kAxes * h->sv.n_dfa;
+        if (need > (int64_t)LSQR_NOALLOC_ATT_MAX)
+            return fail(LSQR_E_INVALID,
+                        "lsqr_aprod1_noalloc: 3 n_dfa = %lld exceeds the scratch of %lld doubles",
+                        (long long)need, (long long)LSQR_NOALLOC_ATT_MAX);
+        double* sp = nullptr;
+        {
+            std::lock_guard<std::mutex> lock(g_scratch_mu);
+            sp = g_scratch_ptr[h->device];
+        }
+        if (!sp) return fail(LSQR_E_STATE, "no-allocation scratch not set up on this device");
+        // every element that k_aprod1 reads is rewritten here first
+        launch_interleave_att<double>(h, x, sp, nullptr, h->user_stream);
+        x3 = sp;
     }
     if (h->value_type == LSQR_F64)
         launch_aprod1<double, double, double, double, A1_ACCUM>(h, x, y, nullptr, nullptr, nullptr,

@@ -28,6 +28,7 @@ OPTIONS = {"conlim": 1, "tests": 2, "chunk": 3, "graph": 4, "profile": 5, "outer
            "att_rhs": 15}
 
 SYMBOLS = ("lsqr_create", "lsqr_destroy", "lsqr_set_option", "lsqr_aprod1", "lsqr_aprod2",
+           "lsqr_aprod1_noalloc",
            "lsqr_get_precond", "lsqr_get_variance", "lsqr_num_cols", "lsqr_solve",
            "lsqr_solve_refined",
            "lsqr_solve_batched", "lsqr_batch_tuning", "lsqr_kernel_times", "lsqr_pass_times",
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "lsqr_set_option": ([H, I32, F64], I32),
         "lsqr_aprod1": ([H, P, P], I32),
         "lsqr_aprod2": ([H, P, P], I32),
+        "lsqr_aprod1_noalloc": ([H, P, P], I32),
         "lsqr_get_precond": ([H, P], I32),
         "lsqr_get_variance": ([H, P], I32),
         "lsqr_num_cols": ([H, ctypes.POINTER(I64)], I32),
@@ -236,6 +238,15 @@ class LsqrSystem:
 
         _check(_lib.lsqr_aprod1(self._h, _dev_ptr(x, torch.float64, (self.n,), "x"),
                                 _dev_ptr(y, torch.float64, (self.m,), "y")))
+        return y
+
+    def aprod1_noalloc(self, x, y):
+        """y += A x like aprod1, through the entry point that allocates nothing
+        (its scratch is the library's per-GPU array; overlapping calls race)."""
+        import torch
+
+        _check(_lib.lsqr_aprod1_noalloc(self._h, _dev_ptr(x, torch.float64, (self.n,), "x"),
+                                        _dev_ptr(y, torch.float64, (self.m,), "y")))
         return y
 
     def aprod2(self, x, y):
