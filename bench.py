@@ -5,11 +5,15 @@ values (19.2 GB), 3 x 100,000 attitude columns, 6,000 instrumental columns,
 1 global column (5,306,001 unknowns); synthetic seeded inputs shaped like the
 paper's system. A step is one LSQR iteration (aprod1, beta, aprod2, alpha,
 Givens rotation, x/w update, stopping tests); the timed region is one
-lsqr_solve of exactly `steps` iterations (stopping tests off) with HIP events
-around every launch of the two row passes on the stream they run on: the
-fused pass (aprod1 with the astrometric, instrumental and global part of
-aprod2) and the bucket-order attitude pass. The same iterations with
-separate aprod1 / aprod2 launches are timed for comparison.
+lsqr_solve of exactly `steps` iterations (stopping tests off; its start and
+end, one aprod2 and a few vector kernels, included) with HIP events around
+every launch of the row passes on the stream they run on: the attitude
+pre-pass, the fused pass (the rest of aprod1 with the astrometric,
+instrumental and global part of aprod2) and the bucket-order attitude pass.
+The same iterations with other pass arrangements are timed for comparison,
+then the extra legs: FP32 storage + FP64 refinement (4e8 rows), batched
+right-hand sides (1e8 rows, k = 16), the largest system (1e9 rows, FP32,
+refined and batched, k = 4), and the oracle on the host cores.
 
 Prints one JSON line.
 """
@@ -64,7 +68,7 @@ def pass_times(g, mode=None):
     pt.pop("mode", None)
     pt.pop("compact", None)
     per = {k: ms / max(1, n) for k, (ms, n) in pt.items()}
-    if mode == 2:
+    if mode in (2, 3):
         return {"attitude_dot": per["pre"], "fused_rest": per["fused"],
                 "attitude": per["attitude"]}
     a, b = ("fused", "attitude") if mode == 1 else ("aprod1", "aprod2")
@@ -105,31 +109,56 @@ def counter_traffic(kernel: str):
     return rec.get(kernel)
 
 
-def cpu_baseline(spec, sample_stars=40_000, itn=(1, 21)):
-    """The oracle as it stands, single thread, on the first `sample_stars`
-    stars of the workload (same N_DFA and instrumental columns), per-iteration
-    time from two runs of different length, scaled to the full row count."""
-    import numpy as np
+def host_ram_gb():
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal:"):
+                    return int(line.split()[1]) / 1e6
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(spec, dev, itn=(1, 6)):
+    """The oracle's OpenMP timing build (the same source as the pinned
+    single-thread oracle, -O3 -fopenmp) on all host cores, on the full
+    workload: the system generated on the GPU and copied to host memory, b
+    formed there too; LSQR runs of itn[0] and itn[1] iterations timed, the
+    difference per iteration is the figure (set-up excluded)."""
+    import torch
 
     import oracle
     import synth
 
-    sub = spec.scaled(n_stars=sample_stars)
-    S = synth.make_system(sub)
-    o = oracle.OracleSystem.from_synth(S)
-    b = o.aprod1(synth.x_true(sub), synth.noise(sub, S.m))
-    t = []
-    for k in itn:
-        t0 = time.perf_counter()
-        o.lsqr(b, k, atol=0.0, btol=0.0, conlim=0.0, tests=False)
-        t.append(time.perf_counter() - t0)
-    per_iter = (t[1] - t[0]) / (itn[1] - itn[0])
-    full_rows = spec.n_stars * spec.obs_lo
-    per_iter_full = per_iter * full_rows / S.m
-    return {"value": 1.0 / per_iter_full, "unit": "iter/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_stars} stars ({S.m} rows) of the workload, LSQR "
-                      f"iterations {itn[0]} and {itn[1]} timed, difference per iteration "
-                      f"({per_iter:.3f} s) scaled by {full_rows}/{S.m} rows",
+    if not os.path.exists(oracle.OMP_LIB_PATH):
+        oracle.build(openmp=True)
+    oracle.use_library(oracle.OMP_LIB_PATH)
+    try:
+        arrays, first = synth.device_system(spec, dev)
+        m = int(first[-1])
+        host = {k: v.cpu().numpy() for k, v in arrays.items()}
+        del arrays
+        torch.cuda.empty_cache()
+        o = oracle.OracleSystem(host["values"], host["star_of_row"], host["att_start"],
+                                host["instr_idx"], n_stars=spec.n_stars, n_dfa=spec.n_dfa,
+                                n_instr_cols=spec.n_instr_cols)
+        b = o.aprod1(synth.x_true(spec), synth.noise(spec, m))
+        t = []
+        for k in itn:
+            t0 = time.perf_counter()
+            o.lsqr(b, k, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+            t.append(time.perf_counter() - t0)
+        per_iter = (t[1] - t[0]) / (itn[1] - itn[0])
+        threads = oracle.num_threads()
+    finally:
+        oracle.use_library(None)
+    return {"value": 1.0 / per_iter, "unit": "iter/s", "cores": threads, "kind": "oracle",
+            "sample": f"the full workload ({m} rows, FP64) in host memory; the oracle's OpenMP "
+                      f"timing build, LSQR runs of {itn[0]} and {itn[1]} iterations timed, "
+                      f"difference per iteration {per_iter:.3f} s",
+            "nproc": os.cpu_count(), "host_ram_GB": host_ram_gb(),
+            "build": "gcc -O3 -fopenmp -ffp-contract=off (oracle/oracle.c)",
             "seconds": sum(t)}
 
 
@@ -137,34 +166,105 @@ def rel_inf(a, b):
     return float((a - b).abs().max() / b.abs().max())
 
 
-def stream_ceiling(dev, gib: float = 20.0, reps: int = 5):
-    """Practical HBM ceilings on this GPU: a plain reduction (read) and fill
-    (write) over a `gib` GiB FP64 buffer with PyTorch's own kernels, median of
-    `reps` runs each."""
+_sc_lib = None
+
+
+def _stream_lib():
+    """libstreamceil.so: hand-written streaming read / write / copy kernels."""
+    global _sc_lib
+    if _sc_lib is None:
+        import ctypes
+
+        path = os.path.join(ROOT, "paper_2308_00778_amd", "libstreamceil.so")
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built: run __graft_entry__.build() first")
+        lib = ctypes.CDLL(path)
+        P, I64 = ctypes.c_void_p, ctypes.c_int64
+        lib.sc_grid.argtypes, lib.sc_grid.restype = [], ctypes.c_int
+        lib.sc_read.argtypes, lib.sc_read.restype = [P, I64, P, P], ctypes.c_int
+        lib.sc_write.argtypes, lib.sc_write.restype = [P, I64, P], ctypes.c_int
+        lib.sc_copy.argtypes, lib.sc_copy.restype = [P, P, I64, P], ctypes.c_int
+        _sc_lib = lib
+    return _sc_lib
+
+
+def _time_launch(fn, reps: int):
+    """Median milliseconds of `fn` (launches on torch's current stream),
+    timed with events on that stream, after one warm-up."""
     import torch
 
-    buf = torch.empty(int(gib * 2**30) // 8, dtype=torch.float64, device=dev)
-    buf.fill_(1.0)
-    out = {}
-    for name, fn in (("read", lambda: buf.sum()), ("write", lambda: buf.fill_(2.0))):
+    fn()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         fn()
-        ts = []
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        out[f"{name}_GBps"] = buf.numel() * 8 / sorted(ts)[reps // 2] / 1e9
-    out["kernels"] = f"torch sum / fill over {gib:.0f} GiB FP64, median of {reps}"
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return sorted(ts)[reps // 2]
+
+
+def read_rate(bufs, reps: int = 5):
+    """GB/s of the hand-written streaming read over the given device tensors
+    (one launch each, timed together)."""
+    import torch
+
+    lib = _stream_lib()
+    sink = torch.empty(lib.sc_grid(), dtype=torch.float64, device=bufs[0].device)
+    st = torch.cuda.current_stream().cuda_stream
+    total = sum(t.numel() * t.element_size() for t in bufs)
+
+    def go():
+        for t in bufs:
+            rc = lib.sc_read(t.data_ptr(), t.numel() * t.element_size(), sink.data_ptr(), st)
+            if rc != 0:
+                raise RuntimeError(f"sc_read failed ({rc})")
+
+    ms = _time_launch(go, reps)
+    return total / (ms * 1e-3) / 1e9
+
+
+def stream_ceiling(dev, gib: float = 20.0, reps: int = 5):
+    """Practical HBM ceilings on this GPU with hand-written streaming kernels
+    (paper_2308_00778_amd/csrc/stream_ceiling.hip: 16-byte nontemporal loads
+    and stores, grid-stride): read and write of a `gib` GiB buffer, and a
+    copy of half of it into the other half; median of `reps` runs each."""
+    import torch
+
+    lib = _stream_lib()
+    nbytes = int(gib * 2**30) & ~255
+    buf = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    p = buf.data_ptr()
+    ms_w = _time_launch(lambda: lib.sc_write(p, nbytes, st), reps)
+    out = {"read_GBps": read_rate([buf], reps), "write_GBps": nbytes / (ms_w * 1e-3) / 1e9}
+    half = nbytes // 2
+    ms_c = _time_launch(lambda: lib.sc_copy(p, p + half, half, st), reps)
+    out["copy_GBps"] = 2 * half / (ms_c * 1e-3) / 1e9  # bytes read + written
+    out["kernels"] = (f"hand-written streaming read / write / copy (stream_ceiling.hip) over "
+                      f"{gib:.0f} GiB, median of {reps}")
     del buf
     torch.cuda.empty_cache()
     return out
 
 
+def _timed(fn):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
 def refine_leg(cfg: int, dev):
-    """FP32 storage + FP64 refinement against the FP64 solve of the same
-    (FP32-stored) system, both to convergence at atol = btol = 1e-12."""
+    """FP32 storage + FP64 refinement against plain FP64 on the same GPU, all
+    to convergence at atol = btol = 1e-12 (the FP32-rounded values define
+    the system): the comparator is the FP64 solve of an FP64-stored copy of
+    those values (the same iteration, twice the value bytes); the FP64 solve
+    of the FP32-stored values (widened in registers) is reported beside it."""
     import torch
 
     import synth
@@ -174,43 +274,52 @@ def refine_leg(cfg: int, dev):
     t0 = time.perf_counter()
     arrays, first = synth.device_system(spec, dev)
     m = int(first[-1])
-    g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
-                   n_instr_cols=spec.n_instr_cols)
+    kw = dict(n_stars=spec.n_stars, n_dfa=spec.n_dfa, n_instr_cols=spec.n_instr_cols)
+    g = LsqrSystem(**arrays, **kw)
     b = synth.device_noise(spec, m, 0, dev)
     g.aprod1(synth.device_x_true(spec, dev), b)
     torch.cuda.synchronize()
     log(f"refine leg: m={m} n={g.n} ready in {time.perf_counter() - t0:.1f} s")
     out = {"workload": f"{spec.n_stars} stars x {spec.obs_lo} obs = {m} rows x {g.n} unknowns, "
                        f"FP32 values, astrometric column scale 10^U{spec.astro_scale}"}
-    # warm both paths (graph capture, lazy workspaces) on a short solve
+    # plain FP64: an FP64-stored copy of the same values, its own handle
+    v64 = arrays["values"].double()
+    g64 = LsqrSystem(**{**arrays, "values": v64}, **kw)
+    g64.solve(b, 2, atol=0.0, btol=0.0)  # bucket order, graphs
+    (x64s, i64s), t_fp64s = _timed(lambda: g64.solve(b, 500, atol=1e-12, btol=1e-12))
+    g64.close()
+    del v64, g64
+    torch.cuda.empty_cache()
+    # the FP32-stored handle: FP64 arithmetic on the widened values, and the
+    # refined solve
     g.solve(b, 2, atol=0.0, btol=0.0)
     g.solve_refined(b, 2, atol=1e-6, btol=1e-6, outer_limit=1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    x64, i64 = g.solve(b, 500, atol=1e-12, btol=1e-12)
-    torch.cuda.synchronize()
-    t_fp64 = time.perf_counter() - t1
-    t2 = time.perf_counter()
-    x32, i32 = g.solve_refined(b, 200, atol=1e-6, btol=1e-6, outer_limit=10)
-    torch.cuda.synchronize()
-    t_ref = time.perf_counter() - t2
+    (x64, i64), t_fp64 = _timed(lambda: g.solve(b, 500, atol=1e-12, btol=1e-12))
+    (x32, i32), t_ref = _timed(lambda: g.solve_refined(b, 200, atol=1e-6, btol=1e-6,
+                                                        outer_limit=10))
     # per-iteration kernel times of the FP32 inner loop
     g.set_option("profile", 1)
     g.solve_refined(b, 20, atol=0.0, btol=0.0, outer_limit=1)
     g.set_option("profile", 0)
     ms = pass_times(g)
     out.update({
-        "fp64_seconds": t_fp64, "fp64_itn": i64.itn, "fp64_istop": i64.istop,
+        "fp64_stored_seconds": t_fp64s, "fp64_stored_itn": i64s.itn,
+        "fp64_stored_istop": i64s.istop,
+        "fp64_on_fp32_values_seconds": t_fp64, "fp64_on_fp32_values_itn": i64.itn,
         "refined_seconds": t_ref, "refined_inner_itn": i32.itn,
-        "refined_outer_steps": i32.outer_steps, "speedup_vs_fp64": t_fp64 / t_ref,
-        "rel_inf_err_vs_fp64": rel_inf(x32, x64),
+        "refined_outer_steps": i32.outer_steps,
+        "speedup_vs_fp64": t_fp64s / t_ref,
+        "speedup_vs_fp64_on_fp32_values": t_fp64 / t_ref,
+        "rel_inf_err_vs_fp64": rel_inf(x32, x64s),
+        "rel_inf_err_vs_fp64_on_fp32_values": rel_inf(x32, x64),
         "inner_kernels": {k: {"ms": ms[k], "GBps": BYTES_PER_ROW_F32[k] * m / (ms[k] * 1e-3) / 1e9,
                               "bytes_per_row": BYTES_PER_ROW_F32[k]} for k in ms},
     })
-    log(f"refine leg: fp64 {t_fp64:.2f} s ({i64.itn} it), refined {t_ref:.2f} s "
-        f"({i32.itn} inner, {i32.outer_steps} outer), err {out['rel_inf_err_vs_fp64']:.2e}")
+    log(f"refine leg: fp64-stored {t_fp64s:.2f} s ({i64s.itn} it), fp64 on fp32 values "
+        f"{t_fp64:.2f} s ({i64.itn} it), refined {t_ref:.2f} s ({i32.itn} inner, "
+        f"{i32.outer_steps} outer), err {out['rel_inf_err_vs_fp64']:.2e}")
     g.close()
-    del arrays, b, x64, x32
+    del arrays, b, x64, x32, x64s
     torch.cuda.empty_cache()
     return out
 
@@ -347,14 +456,15 @@ def batched_leg(cfg: int, dev, singles: int = 2, att_rhs: int = 4):
 
 
 def largest_leg(cfg: int, dev):
-    """The largest single-GPU workload (FP32 values, uneven stars): the FP64
-    solve of the FP32-stored system, the FP32 + FP64 refinement solve, and its
-    k noise realisations batched (FP64 arithmetic on the FP32 values, k-tile
-    2 to stay within HBM), all to convergence at atol = btol = 1e-12."""
+    """The largest single-GPU workload (FP32 values, uneven stars, k = 4
+    right-hand sides) in its own form: FP32 storage with FP64 refinement and
+    the k right-hand sides batched (lsqr_solve_batched_refined), all to
+    convergence at atol = btol = 1e-12, against the single-RHS FP64 solve of
+    the same (FP32-rounded) system, and the single-RHS refined solve."""
     import torch
 
     import synth
-    from paper_2308_00778_amd import LsqrError, LsqrSystem
+    from paper_2308_00778_amd import LsqrSystem
 
     def free_gb():
         return torch.cuda.mem_get_info(dev)[0] / 1e9
@@ -367,25 +477,25 @@ def largest_leg(cfg: int, dev):
     g = LsqrSystem(**arrays, n_stars=spec.n_stars, n_dfa=spec.n_dfa,
                    n_instr_cols=spec.n_instr_cols)
     xt = synth.device_x_true(spec, dev)
-    b = synth.device_noise(spec, m, 0, dev)
-    g.aprod1(xt, b)
+    B = torch.empty((m, k), dtype=torch.float64, device=dev)
+    for j in range(k):
+        bj = synth.device_noise(spec, m, j, dev)
+        g.aprod1(xt, bj)
+        B[:, j] = bj
+        del bj
+    del xt
     torch.cuda.synchronize()
-    log(f"largest leg: m={m} n={g.n} ready in {time.perf_counter() - t0:.1f} s, "
+    log(f"largest leg: m={m} n={g.n} k={k} ready in {time.perf_counter() - t0:.1f} s, "
         f"{free_gb():.0f} GB free")
     out = {"workload": f"{spec.n_stars} stars x U{{{spec.obs_lo}..{spec.obs_hi}}} obs = {m} rows "
                        f"x {g.n} unknowns, FP32 values, N_DFA={spec.n_dfa}, "
                        f"{spec.n_instr_cols} instrumental, k = {k}"}
+    b = B[:, 0].contiguous()
     g.solve(b, 2, atol=0.0, btol=0.0)
     g.solve_refined(b, 2, atol=1e-6, btol=1e-6, outer_limit=1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    x64, i64 = g.solve(b, 500, atol=1e-12, btol=1e-12)
-    torch.cuda.synchronize()
-    t_fp64 = time.perf_counter() - t1
-    t2 = time.perf_counter()
-    x32, i32 = g.solve_refined(b, 200, atol=1e-6, btol=1e-6, outer_limit=10)
-    torch.cuda.synchronize()
-    t_ref = time.perf_counter() - t2
+    (x64, i64), t_fp64 = _timed(lambda: g.solve(b, 500, atol=1e-12, btol=1e-12))
+    (x32, i32), t_ref = _timed(lambda: g.solve_refined(b, 200, atol=1e-6, btol=1e-6,
+                                                        outer_limit=10))
     g.set_option("profile", 1)
     g.set_option("tests", 0)
     g.solve(b, 16, atol=0.0, btol=0.0)
@@ -394,6 +504,8 @@ def largest_leg(cfg: int, dev):
     ms32 = pass_times(g)
     g.set_option("profile", 0)
     g.set_option("tests", 1)
+    del b
+    torch.cuda.empty_cache()
     # FP64 arithmetic on FP32 values (FP64 row vector); the FP32 inner solve:
     # BYTES_PER_ROW_F32
     bpr64 = bytes_per_row(4, 8)
@@ -412,35 +524,29 @@ def largest_leg(cfg: int, dev):
         f"{free_gb():.0f} GB free")
     del x32
     torch.cuda.empty_cache()
-    try:
-        B = torch.empty((m, k), dtype=torch.float64, device=dev)
-        B[:, 0] = b
-        del b
-        for j in range(1, k):
-            bj = synth.device_noise(spec, m, j, dev)
-            g.aprod1(xt, bj)
-            B[:, j] = bj
-            del bj
-        torch.cuda.synchronize()
-        g.set_option("ktile", 2)
-        t3 = time.perf_counter()
-        X, infos = g.solve_batched(B, 500, 1e-12, 1e-12)
-        torch.cuda.synchronize()
-        t_b = time.perf_counter() - t3
-        rhs_itn = sum(i.itn for i in infos)
-        out["batched"] = {"k": k, "k_tile": 2, "seconds": t_b, "rhs_iterations": rhs_itn,
-                          "rhs_iter_per_s": rhs_itn / t_b,
-                          "fp64_single_rhs_iter_per_s": i64.itn / t_fp64,
-                          "rel_inf_err_rhs0_vs_single": rel_inf(X[:, 0], x64),
-                          "itn_per_rhs": [i.itn for i in infos]}
-        log(f"largest leg: batched {rhs_itn} RHS-iterations in {t_b:.2f} s, "
-            f"{free_gb():.0f} GB free")
-        del B, X
-    except (LsqrError, torch.cuda.OutOfMemoryError) as e:
-        out["batched"] = {"skipped": f"{type(e).__name__}: {e}"}
-        log(f"largest leg: batched skipped ({e})")
+    # the workload's own form: refined and batched in one solve (autotuned
+    # k-tile outside the timed region, on a short inner solve)
+    g.set_option("tests", 0)
+    g.solve_batched_refined(B, 2, atol=1e-6, btol=1e-6, outer_limit=1)
+    g.set_option("tests", 1)
+    tune = g.batch_tuning()
+    (X, infos), t_b = _timed(lambda: g.solve_batched_refined(B, 200, atol=1e-6, btol=1e-6,
+                                                              outer_limit=10))
+    inner = sum(i.itn for i in infos)
+    out["batched_refined"] = {
+        "k": k, "k_tile": tune["k_tile"], "autotune_ms_per_rhs_iter": tune["ms_per_rhs_iter"],
+        "seconds": t_b, "inner_rhs_iterations": inner,
+        "outer_steps": [i.outer_steps for i in infos], "inner_itn": [i.itn for i in infos],
+        # k right-hand sides solved in t_b against k single FP64 / refined solves
+        "speedup_vs_fp64_single": k * t_fp64 / t_b,
+        "speedup_vs_refined_single": k * t_ref / t_b,
+        "rel_inf_err_rhs0_vs_fp64": rel_inf(X[:, 0], x64),
+    }
+    log(f"largest leg: refined batched {k} RHS in {t_b:.2f} s (k-tile {tune['k_tile']}, "
+        f"{inner} inner RHS-iterations), {k * t_fp64 / t_b:.2f}x {k} FP64 solves, err rhs0 "
+        f"{out['batched_refined']['rel_inf_err_rhs0_vs_fp64']:.2e}; {free_gb():.0f} GB free")
     g.close()
-    del arrays, x64
+    del arrays, x64, X, B
     torch.cuda.empty_cache()
     return out
 
@@ -465,10 +571,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="refine,batched",
+    ap.add_argument("--forms", default="refine,batched,largest",
                     help="comma list of extra legs: refine (FP32 + FP64 refinement), "
                          "batched (k right-hand sides), largest (the 1e9-row FP32 "
-                         "workload, about 270 GB of HBM), none")
+                         "workload with refinement and k batched right-hand sides, "
+                         "about 260 GB of HBM), none")
     ap.add_argument("--copy", action="store_true", help="only run the copy calibration")
     ap.add_argument("--attitude-ab", action="store_true",
                     help="only time the attitude variants of aprod2")
@@ -534,6 +641,14 @@ def main():
     g.solve(b, args.steps, atol=0.0, btol=0.0)
     torch.cuda.synchronize()
     wall_graph = time.perf_counter() - t2
+    # the solve's start (u = b, beta, the first aprod2, alpha, v, w) and end
+    # (x = p .* y): a solve of 0 iterations, median of 3
+    t_init = sorted(_timed(lambda: g.solve(b, 0, atol=0.0, btol=0.0))[1] for _ in range(3))[1]
+    # the hand-written streaming read over the system's own arrays (values and
+    # index arrays as stored, 232 bytes per row): what a pass that only streams
+    # the matrix reaches
+    sys_read = read_rate([arrays["values"], arrays["star_of_row"], arrays["att_start"],
+                          arrays["instr_idx"]])
 
     # the same iterations with the attitude dot product inside the fused pass
     # (fused mode 1) and with separate aprod1 / aprod2 launches (mode 0)
@@ -587,6 +702,8 @@ def main():
                            if compact and k in ("fused", "fused_rest") else {})}
                     for k in ms},
         "graph_iter_per_s": args.steps / wall_graph,
+        # value counts the solve's start and end in its timed region; without them:
+        "iterations_only": {"iter_per_s": args.steps / (wall - t_init), "init_ms": t_init * 1e3},
         "fused_att_in_pass": other[1],
         "unfused": other[0],
         "solve_info": {"itn": info.itn, "istop": info.istop, "rnorm": info.rnorm},
@@ -595,9 +712,11 @@ def main():
     del arrays, b, xt, x
     torch.cuda.empty_cache()
     sc = stream_ceiling(dev)
+    sc["system_read_GBps"] = sys_read
     sc["dominant_kernel_frac_of_read"] = gbps[dom] / sc["read_GBps"]
     result["stream_ceiling"] = sc
-    log(f"stream ceiling: read {sc['read_GBps']:.0f} GB/s, write {sc['write_GBps']:.0f} GB/s")
+    log(f"stream ceiling: read {sc['read_GBps']:.0f} GB/s (system arrays {sys_read:.0f}), "
+        f"write {sc['write_GBps']:.0f} GB/s, copy {sc['copy_GBps']:.0f} GB/s")
     forms = [f for f in args.forms.split(",") if f and f != "none"]
     if "refine" in forms:
         result["fp32_refine"] = refine_leg(2, dev)
@@ -606,8 +725,10 @@ def main():
     if "largest" in forms:
         result["largest"] = largest_leg(4, dev)
     if not args.no_cpu_baseline:
-        log("timing the oracle on a sample ...")
-        result["cpu_baseline"] = cpu_baseline(spec)
+        log("timing the oracle (OpenMP timing build) on the full workload ...")
+        result["cpu_baseline"] = cpu_baseline(spec, dev)
+        log(f"cpu baseline: {result['cpu_baseline']['value']:.3f} iter/s on "
+            f"{result['cpu_baseline']['cores']} threads")
     print(json.dumps(result), flush=True)
 
 

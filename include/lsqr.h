@@ -167,6 +167,13 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         bucket order (the bucket's attitude columns of v in
  *                         LDS, no gathers from global memory) and folded into
  *                         u~, so the fused pass skips the attitude section;
+ *                         3: as 2, but u~ stays in star order: the pre-pass
+ *                         writes the attitude part to a separate bucket-order
+ *                         vector (8 bytes per row, allocated on first use)
+ *                         that the fused pass reads through the permutation,
+ *                         and the attitude pass reads u~ through it, so no
+ *                         pass writes through the permutation (batched k-tiles
+ *                         run mode 2);
  *                         0: separate aprod1 and aprod2
  *   LSQR_OPT_VARIANCE     1: lsqr_solve also accumulates the variance estimate of
  *                         the unknowns, sum over iterations of (w/rho)^2 (Algorithm
@@ -182,8 +189,8 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         memory; the caller's arrays are used otherwise and
  *                         by every other pass; 0: never (frees the copies)
  *   LSQR_OPT_KTILE        batched solves: right-hand sides advanced together per
- *                         pass over A (1, 2, 4, 8), 0 (default) = autotune once
- *                         per handle
+ *                         pass over A (1, 2, 4, 8), 0 (default) = autotune (see
+ *                         lsqr_batch_tuning)
  *   LSQR_OPT_ATT_RHS      right-hand sides one sweep of the bucket-order
  *                         attitude passes holds (1 default, 2, 4, 8): the
  *                         buckets narrow until that many LDS windows /
@@ -192,6 +199,11 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         pass instead of once per RHS (single-RHS passes pay
  *                         a few percent for the extra buckets); settable only
  *                         before the first solve or aprod2
+ *   LSQR_OPT_PIPELINE     1 (default): each thread of the single-RHS bucket-order
+ *                         passes issues the loads of its next row before the
+ *                         store (or LDS atomics) of the current one, so that no
+ *                         row waits for the previous row's store; 0: one row at
+ *                         a time (same results)
  */
 #define LSQR_OPT_CONLIM 1
 #define LSQR_OPT_TESTS 2
@@ -208,6 +220,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_VARIANCE 13
 #define LSQR_OPT_COMPACT_INDEX 14
 #define LSQR_OPT_ATT_RHS 15
+#define LSQR_OPT_PIPELINE 16
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
 
 /* Below, m counts every row: n_rows observation rows plus n_con constraint
@@ -237,6 +250,15 @@ lsqr_status lsqr_aprod1_noalloc(lsqr_handle* h, const double* x, double* y);
 
 /* aprod mode 2, Eq. (3): x[n] += A^T y[m] with the raw A. Same conventions. */
 lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y);
+
+/* FP32 forms of the two operators for FP32-stored systems (LSQR_F32): Eq. (2)
+ * y[m] += A x[n] and Eq. (3) x[n] += A^T y[m] with FP32 vectors, FP32
+ * products and FP32 accumulation (the LDS histograms of the instrumental and
+ * attitude columns of Eq. (3) add in FP64 and store FP32), the arithmetic of
+ * the refined solve's inner iterations. Asynchronous on the handle's stream;
+ * x and y must not overlap. LSQR_E_STATE on an LSQR_F64 system. */
+lsqr_status lsqr_aprod1_f32(lsqr_handle* h, const float* x, float* y);
+lsqr_status lsqr_aprod2_f32(lsqr_handle* h, float* x, const float* y);
 
 /* Variance estimate of the unknowns from the last lsqr_solve run with
  * LSQR_OPT_VARIANCE = 1: var_out[j] = p_j^2 sum_k (w_kj / rho_k)^2 (Algorithm 1,
@@ -271,7 +293,8 @@ lsqr_status lsqr_solve(lsqr_handle* h, const double* b, double* x, int32_t itn_l
  * b: FP64 [m]; x: FP64 [n] output (x_0 = 0). info->itn counts the inner
  * iterations of all steps, info->outer_steps the outer steps, info->istop and
  * the estimates are those of the last inner solve (its rnorm estimates
- * ||b - A x||), info->bnorm is ||b||. Synchronous; info may be NULL. */
+ * ||b - A x||), info->bnorm is ||b|| (of b rounded to FP32, the first inner
+ * solve's start vector). Synchronous; info may be NULL. */
 lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32_t itn_limit,
                                double atol, double btol, int32_t outer_limit, lsqr_info* info);
 
@@ -287,9 +310,35 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
 lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32_t k,
                                int32_t itn_limit, double atol, double btol, lsqr_info* infos);
 
-/* Autotuner result of this handle: the chosen k-tile (0 if not tuned yet) and
- * the measured milliseconds per RHS-iteration for K = 1, 2, 4, 8 (4 host
- * doubles, 0 where not measured). Host pointers; either may be NULL. */
+/* k right-hand sides of an FP32-stored system (LSQR_F32), each solved by the
+ * FP64 iterative refinement of lsqr_solve_refined, with the FP32 inner LSQR
+ * solves of a k-tile advancing together (the SpMM form of
+ * lsqr_solve_batched; the FP64 outer residuals r_j = b_j - A x_j are formed
+ * for the whole tile in one pass). Per RHS j: outer step r_j in FP64 (FP32
+ * values widened, FP64 accumulation, stored as the FP32 start vector), inner
+ * LSQR with FP32 products and accumulation and FP64 scalars, stopped once
+ * ||Abar^T (r_j - A d_j)|| <= atol ||Abar^T r_j|| or after itn_limit
+ * iterations (btol unused), then x_j += d_j in FP64; RHS j stops refining
+ * when ||d_j||_inf <= OUTER_TOL ||x_j||_inf, when r_j is zero or orthogonal
+ * to the range of A, or after outer_limit steps, and is frozen while the
+ * others continue. Each x[:, j] is the result lsqr_solve_refined would give
+ * for b[:, j] up to rounding order. B: FP64 [m][k], X: FP64 [n][k] output,
+ * layouts as in lsqr_solve_batched. infos (host, may be NULL): per RHS, itn
+ * = inner iterations of all its steps, outer_steps = its steps, istop and
+ * estimates of its last inner solve, bnorm = ||b_j|| (as for
+ * lsqr_solve_refined, of b_j rounded to FP32). Returns LSQR_E_STATE on
+ * an LSQR_F64 system. Synchronous. */
+lsqr_status lsqr_solve_batched_refined(lsqr_handle* h, const double* B, double* X, int32_t k,
+                                       int32_t itn_limit, double atol, double btol,
+                                       int32_t outer_limit, lsqr_info* infos);
+
+/* Autotuner result of this handle: the k-tile of its last autotuned batched
+ * solve (0 if none yet) and the measured milliseconds per RHS-iteration for
+ * K = 1, 2, 4, 8 of that tuning (4 host doubles, 0 where not measured). The
+ * tuner runs on the first batched call for each precision (FP64 tiles,
+ * FP32 inner tiles of the refined form) and each min(k, 8), and again after
+ * an option that selects kernels changes. Host pointers; either may be
+ * NULL. */
 lsqr_status lsqr_batch_tuning(lsqr_handle* h, int32_t* k_tile, double* ms_per_rhs_iter);
 
 /* Per-kernel timing of the last solve run with LSQR_OPT_PROFILE = 1:
@@ -306,7 +355,7 @@ lsqr_status lsqr_kernel_times(lsqr_handle* h, double* ms_aprod1, int64_t* n_apro
  * the aprod1 window (the fused pass, or aprod1), ms[2] the aprod2 window (the
  * attitude pass, or aprod2); n[i] the iterations timed. Host arrays of 3.
  * mode (may be NULL): the fused mode the last FP64 or refined solve ran
- * (0, 1 or 2, see LSQR_OPT_FUSED); compact (may be NULL): 1 when the fused
+ * (0 to 3, see LSQR_OPT_FUSED); compact (may be NULL): 1 when the fused
  * passes read the compact index copies (LSQR_OPT_COMPACT_INDEX). */
 lsqr_status lsqr_pass_times(lsqr_handle* h, double* ms, int64_t* n, int32_t* mode,
                             int32_t* compact);

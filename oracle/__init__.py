@@ -25,22 +25,32 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# Timing build of the same source (OpenMP, -O3): the CPU baseline only.
+OMP_LIB_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
 
 
-def build(verbose: bool = False, src: str | None = None, out: str | None = None) -> str:
-    """Compile liboracle.so: single thread, -O2, no floating-point contraction.
+def build(verbose: bool = False, src: str | None = None, out: str | None = None,
+          openmp: bool = False) -> str:
+    """Compile liboracle.so: single thread, -O2, no floating-point contraction
+    (the pinned reference build). openmp=True compiles the timing build
+    liboracle_omp.so from the same source (-O3 -fopenmp).
 
     src/out let the mutation tests compile a modified copy elsewhere."""
     src = src or os.path.join(_HERE, "oracle.c")
-    out = out or _LIB_PATH
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-std=c11", "-o", out + ".tmp", src, "-lm"]
+    out = out or (OMP_LIB_PATH if openmp else _LIB_PATH)
+    flags = (["-O3", "-fopenmp"] if openmp else ["-O2"]) + ["-ffp-contract=off", "-fno-fast-math"]
+    cmd = ["gcc", *flags, "-fPIC", "-shared", "-std=c11", "-o", out + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
     return out
+
+
+def num_threads() -> int:
+    """Threads the loaded build runs on (1 for the reference build)."""
+    return int(_load().orc_num_threads())
 
 
 class _Sys(ctypes.Structure):
@@ -97,6 +107,8 @@ def _load():
                              ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                              ctypes.POINTER(_Info), P]
     lib.orc_lsqr.restype = ctypes.c_int
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = ctypes.c_int32
     _lib = lib
     return lib
 

@@ -31,11 +31,24 @@
  *   - tests=0 disables the stopping tests 1..6 (fixed iteration count).
  *
  * No code is shared with the GPU library.
+ *
+ * Builds. The reference build (single thread, -O2, no floating-point
+ * contraction) is the pinned oracle. The same source compiled with -fopenmp
+ * is the timing build of the CPU baseline: the OpenMP pragmas below only
+ * split loops whose iterations are independent (rows of aprod1, elements of
+ * the vector updates), reductions, and aprod2 / the column norms, where
+ * threads own star-aligned row ranges (so each star's astrometric columns
+ * belong to one thread) and accumulate the attitude, instrumental and global
+ * columns privately, added up at the end. Without -fopenmp the pragmas are
+ * ignored and every loop runs as written, in order.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int64_t m;             /* rows (observations) */
@@ -98,11 +111,22 @@ static int64_t column(const orc_system* s, int32_t c, int64_t i)
     return glob_base + c;
 }
 
+/* Threads of the timing build (1 in the reference build). */
+int32_t orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* Eq. (2): y[i] += sum_c A_d[i][c] * x[col(i,c)], rows in order, then the
  * constraint rows. */
 void orc_aprod1(const orc_system* s, const double* x, double* y)
 {
     const int32_t np = n_par_of(s);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < s->m; ++i) {
         double sum = 0.0;
         for (int32_t c = 0; c < np; ++c) sum += coef(s, c, i) * x[column(s, c, i)];
@@ -129,11 +153,58 @@ void orc_aprod1_rows(const orc_system* s, const double* x, const int64_t* rows, 
     }
 }
 
+#ifdef _OPENMP
+/* Timing build: x[col] += A_d[i][c] * w_i (w_i = y[i], or A_d[i][c] itself
+ * when y is NULL: the squared column norms) with threads owning star-aligned
+ * row ranges; astrometric columns are written directly (one thread holds all
+ * rows of a star), the other columns go to per-thread accumulators that are
+ * added to x at the end. */
+static int aprod2_threads(const orc_system* s, double* x, const double* y)
+{
+    const int nt = omp_get_max_threads();
+    const int32_t np = n_par_of(s);
+    const int64_t att_base = (int64_t)s->n_astro * s->n_stars;
+    const int64_t nrest = orc_ncols(s) - att_base;
+    double* priv = (double*)calloc((size_t)nt * (size_t)(nrest > 0 ? nrest : 1), sizeof(double));
+    if (!priv) return -1;
+#pragma omp parallel num_threads(nt)
+    {
+        const int t = omp_get_thread_num();
+        int64_t r0 = s->m * t / nt, r1 = s->m * (t + 1) / nt;
+        while (r0 > 0 && r0 < s->m && s->star[r0] == s->star[r0 - 1]) ++r0;
+        while (r1 > 0 && r1 < s->m && s->star[r1] == s->star[r1 - 1]) ++r1;
+        double* acc = priv + (size_t)t * (size_t)nrest;
+        for (int64_t i = r0; i < r1; ++i)
+            for (int32_t c = 0; c < np; ++c) {
+                const double a = coef(s, c, i);
+                const int64_t j = column(s, c, i);
+                const double v = a * (y ? y[i] : a);
+                if (j < att_base) x[j] += v;
+                else acc[j - att_base] += v;
+            }
+#pragma omp barrier
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < nrest; ++j) {
+            double sum = 0.0;
+            for (int k = 0; k < nt; ++k) sum += priv[(size_t)k * (size_t)nrest + j];
+            x[att_base + j] += sum;
+        }
+    }
+    free(priv);
+    return 0;
+}
+#endif
+
 /* Eq. (3): x[col(i,c)] += A_d[i][c] * y[i], rows in order, then the
  * constraint rows. */
 void orc_aprod2(const orc_system* s, double* x, const double* y)
 {
     const int32_t np = n_par_of(s);
+#ifdef _OPENMP
+    if (omp_get_max_threads() > 1 && aprod2_threads(s, x, y) == 0) {
+        /* done by the threads */
+    } else
+#endif
     for (int64_t i = 0; i < s->m; ++i)
         for (int32_t c = 0; c < np; ++c) x[column(s, c, i)] += coef(s, c, i) * y[i];
     for (int64_t r = 0; r < s->n_con; ++r)
@@ -145,9 +216,11 @@ void orc_aprod2(const orc_system* s, double* x, const double* y)
 double orc_norm(const double* a, int64_t n)
 {
     double mx = 0.0;
+#pragma omp parallel for reduction(max : mx) schedule(static)
     for (int64_t i = 0; i < n; ++i) if (fabs(a[i]) > mx) mx = fabs(a[i]);
     if (mx == 0.0) return 0.0;
     double ssq = 0.0;
+#pragma omp parallel for reduction(+ : ssq) schedule(static)
     for (int64_t i = 0; i < n; ++i) { double t = a[i] / mx; ssq += t * t; }
     return mx * sqrt(ssq);
 }
@@ -158,6 +231,11 @@ void orc_precond(const orc_system* s, double* p)
     const int64_t n = orc_ncols(s);
     const int32_t np = n_par_of(s);
     double* ssq = (double*)calloc((size_t)n, sizeof(double));
+#ifdef _OPENMP
+    if (omp_get_max_threads() > 1 && aprod2_threads(s, ssq, NULL) == 0) {
+        /* done by the threads */
+    } else
+#endif
     for (int64_t i = 0; i < s->m; ++i)
         for (int32_t c = 0; c < np; ++c) {
             double a = coef(s, c, i);
@@ -199,6 +277,7 @@ int orc_lsqr(const orc_system* s, const double* b, double* x, int32_t itn_limit,
     else for (int64_t j = 0; j < n; ++j) p[j] = 1.0;
     double* ad = (double*)scaled;
     for (int32_t c = 0; c < np; ++c)
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < m_obs; ++i)
             ad[(int64_t)c * m_obs + i] = coef(s, c, i) * p[column(s, c, i)];
     for (int64_t e = 0; e < nnz; ++e) con_scaled[e] = s->con_val[e] * p[s->con_col[e]];
@@ -216,11 +295,14 @@ int orc_lsqr(const orc_system* s, const double* b, double* x, int32_t itn_limit,
     double alpha = 0.0;
     memset(v, 0, (size_t)n * sizeof(double));
     if (beta > 0.0) {
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < m; ++i) u[i] /= beta;
         orc_aprod2(&sb, v, u);
         alpha = orc_norm(v, n);
     }
-    if (alpha > 0.0) for (int64_t j = 0; j < n; ++j) v[j] /= alpha;
+    if (alpha > 0.0)
+#pragma omp parallel for schedule(static)
+        for (int64_t j = 0; j < n; ++j) v[j] /= alpha;
     memcpy(w, v, (size_t)n * sizeof(double));
 
     const double bnorm = beta;
@@ -234,17 +316,22 @@ int orc_lsqr(const orc_system* s, const double* b, double* x, int32_t itn_limit,
     while (itn < itn_limit) {
         ++itn;
         /* beta_{i+1} u_{i+1} = Abar v_i - alpha_i u_i */
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < m; ++i) u[i] = -alpha * u[i];
         orc_aprod1(&sb, v, u);
         beta = orc_norm(u, m);
         if (beta > 0.0) {
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < m; ++i) u[i] /= beta;
             anorm = sqrt(anorm * anorm + alpha * alpha + beta * beta);
             /* alpha_{i+1} v_{i+1} = Abar^T u_{i+1} - beta_{i+1} v_i */
+#pragma omp parallel for schedule(static)
             for (int64_t j = 0; j < n; ++j) v[j] = -beta * v[j];
             orc_aprod2(&sb, v, u);
             alpha = orc_norm(v, n);
-            if (alpha > 0.0) for (int64_t j = 0; j < n; ++j) v[j] /= alpha;
+            if (alpha > 0.0)
+#pragma omp parallel for schedule(static)
+                for (int64_t j = 0; j < n; ++j) v[j] /= alpha;
         }
         /* plane rotation eliminating beta_{i+1} */
         const double rho = sqrt(rhobar * rhobar + beta * beta);
@@ -257,12 +344,14 @@ int orc_lsqr(const orc_system* s, const double* b, double* x, int32_t itn_limit,
 
         /* y_i = y_{i-1} + (phi/rho) w_i ; w_{i+1} = v_{i+1} - (theta/rho) w_i */
         double dd = 0.0;
+#pragma omp parallel for reduction(+ : dd) schedule(static)
         for (int64_t j = 0; j < n; ++j) {
             const double dk = w[j] / rho;
             dd += dk * dk;
             if (var) var[j] += dk * dk;
         }
         ddnorm += dd;
+#pragma omp parallel for schedule(static)
         for (int64_t j = 0; j < n; ++j) {
             y[j] += (phi / rho) * w[j];
             w[j] = v[j] - (theta / rho) * w[j];

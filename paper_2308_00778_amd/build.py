@@ -20,6 +20,12 @@ HIPCC_FLAGS = [
 ]
 
 
+# Streaming read/write/copy kernels that measure the practical HBM ceiling
+# (benchmark only; the solver library does not use them)
+STREAM_LIB = os.path.join(HERE, "libstreamceil.so")
+STREAM_SOURCES = [os.path.join(HERE, "csrc", "stream_ceiling.hip")]
+
+
 def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     cmd = [hipcc, *HIPCC_FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"),
@@ -28,6 +34,11 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    cmd = [hipcc, *HIPCC_FLAGS, "-o", STREAM_LIB + ".tmp", *STREAM_SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(STREAM_LIB + ".tmp", STREAM_LIB)
     return LIB
 
 

@@ -14,14 +14,22 @@
 //   k_aprod2      x += A^T y over star-aligned per-wave row ranges:
 //                   astrometric: segmented reduction over the star key (rows
 //                     are sorted by star), plain stores, no atomics;
-//                   attitude: scatter-add with device atomics;
+//                   attitude: left to the bucket-order pass (k_att_hist +
+//                     k_att_reduce: rows sorted by the bucket of their
+//                     attitude start, per-workgroup FP64 LDS histograms, no
+//                     device atomics) by default; scatter-add with device
+//                     atomics in the ATT instances (attitude mode 0);
 //                   instrumental: workgroup-private LDS histogram, flushed
-//                     once per workgroup;
+//                     once per workgroup (k_instr_tail beyond its columns);
 //                   global: wave shuffle -> LDS -> per-workgroup partial,
 //                     summed in a deterministic second stage (k_glob_sum).
+//   k_fused       one sweep doing aprod1 and the non-attitude part of aprod2
+//                 of an LSQR step (the attitude dot product optionally first,
+//                 by k_att_dot in bucket order).
 //   k_col_a/b     column-vector updates of the LSQR step (FP64).
 //   k_scalar_*    single-workgroup kernels: norm finishers, Givens rotation,
 //                 estimates and stopping tests, all FP64.
+//   namespace batched: the same steps for a k-tile of right-hand sides.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -574,15 +582,20 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
 // the instrumental slice of x (LDSX, n_instr_cols Acc).
 // AM, the attitude part of the dot product: kAttX reads three 4-value windows
 // of x, kAttX3 one 12-value window of x3, kAttPre none: k_att_dot has already
-// replaced u~ by (attitude part of A vp) - coef u~, so the row adds that.
-enum { kAttX = 0, kAttX3 = 1, kAttPre = 2 };
+// replaced u~ by (attitude part of A vp) - coef u~, so the row adds that;
+// kAttGather: k_att_dot has written the attitude part of every row to datt in
+// bucket order, the row reads it at datt[inv[i]] and keeps u~ in star order
+// (u[i]), so that u~ is read and written sequentially and the only permuted
+// access is that read.
+enum { kAttX = 0, kAttX3 = 1, kAttPre = 2, kAttGather = 3 };
 template <typename T, typename Acc, int NT, bool LDSX, int AM, bool CIDX>
 __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ x,
                                                const Acc* __restrict__ x3, Acc* __restrict__ u,
                                                Acc* __restrict__ q, const int64_t* __restrict__ wb,
                                                Acc* __restrict__ gpart, double* __restrict__ part,
                                                int64_t hcols, const Scalars* __restrict__ sc,
-                                               const int32_t* __restrict__ inv)
+                                               const int32_t* __restrict__ inv,
+                                               const Acc* __restrict__ datt = nullptr)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ Acc gred[NT / kWave];
@@ -626,15 +639,17 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
         const int64_t stc = star_of<CIDX>(s, ic);
         const int64_t st = i < re ? stc : kNoStar;
-        const int64_t t = AM == kAttPre ? 0 : ldnt(&s.att[ic]);
+        constexpr bool kNoAtt = AM == kAttPre || AM == kAttGather;
+        const int64_t t = kNoAtt ? 0 : ldnt(&s.att[ic]);
         T a[kPar];
 #pragma unroll
         for (int c = 0; c < kPar; ++c)
-            if (AM != kAttPre || c < kOffAtt || c >= kOffInstr) a[c] = ldnt(&val[c * m + ic]);
+            if (!kNoAtt || c < kOffAtt || c >= kOffInstr) a[c] = ldnt(&val[c * m + ic]);
         int32_t ix[kInstr];
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) ix[j] = instr_of<CIDX>(s, j, ic);
-        const int64_t pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
+        const int64_t pu = (AM != kAttGather && inv) ? (int64_t)ldnt(&inv[ic]) : ic;
+        const Acc dg = AM == kAttGather ? datt[ldnt(&inv[ic])] : (Acc)0;
         const Acc uo = u[pu];
 
         // Eq. (2): the row's dot product with vp, in section order
@@ -642,7 +657,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         const Acc* xa = x + kAstro * stc;
 #pragma unroll
         for (int j = 0; j < kAstro; ++j) d += (Acc)a[j] * xa[j];
-        if (AM != kAttPre) {
+        if (!kNoAtt) {
 #pragma unroll
             for (int ax = 0; ax < kAxes; ++ax) {
 #pragma unroll
@@ -658,6 +673,8 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         d += (Acc)a[kOffGlob] * xg;
         if (AM == kAttPre)
             d += uo;
+        else if (AM == kAttGather)
+            d += dg - coef * uo;
         else
             d -= coef * uo;
         if (ok) u[pu] = d;
@@ -1466,17 +1483,6 @@ __global__ __launch_bounds__(kBlock) void k_bucket_starts(const int32_t* __restr
     }
 }
 
-// us[k] = u[perm[k]]: a vector in row order placed in bucket order
-template <typename V>
-__global__ __launch_bounds__(kBlock) void k_gather_perm(const V* __restrict__ u,
-                                                         const int32_t* __restrict__ perm,
-                                                         int64_t m, V* __restrict__ us)
-{
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m;
-         k += (int64_t)gridDim.x * kBlock)
-        us[k] = u[perm[k]];
-}
-
 // att_sorted[c][k] = values[off_att + c][perm[k]], c < 12 ;
 // tloc[k] = t of row perm[k] minus its bucket's first start.
 template <typename T>
@@ -1507,8 +1513,15 @@ __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val
 // (win[(3 c + axis) KS + j], 3 (W + 3) KS Acc), so no row gathers from global
 // memory. KS right-hand sides share one sweep over the rows (one window each);
 // K / KS sweeps cover the tile. Frozen RHS (done) keep u~. The fused pass
-// (kAttPre) then adds the other sections.
-template <typename T, typename Acc, int K, int KS, int NT>
+// (kAttPre) then adds the other sections. SEP: u is a separate bucket-order
+// vector that receives the attitude part alone (u[k] <- sum_c a_c x[col_c],
+// nothing read), for the fused pass's kAttGather form.
+// PIPE: each thread issues the loads of its next row before the store of the
+// current one. A wave's vector-memory counter retires loads and stores in
+// issue order, so a store issued before the next row's loads would be waited
+// for together with them (one store round trip per row); after them it is
+// not.
+template <typename T, typename Acc, int K, int KS, int NT, bool SEP = false, bool PIPE = true>
 __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__ att_sorted,
                                                  const int32_t* __restrict__ tloc,
                                                  const int64_t* __restrict__ bstart,
@@ -1544,12 +1557,9 @@ __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__
             }
         }
         __syncthreads();
-        for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += (int64_t)G * NT) {
-            const int64_t tl = ldnt(&tloc[k]);
-            T a[kAxes * kParAxis];
-#pragma unroll
-            for (int c = 0; c < kAxes * kParAxis; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
-            Acc d[KS];
+        constexpr int kAtt = kAxes * kParAxis;
+        // the attitude dot product of one row from the LDS window
+        auto row_dot_win = [&](int64_t tl, const T (&a)[kAtt], Acc (&d)[KS]) {
 #pragma unroll
             for (int j = 0; j < KS; ++j) d[j] = (Acc)0;
 #pragma unroll
@@ -1561,11 +1571,80 @@ __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__
 #pragma unroll
                     for (int j = 0; j < KS; ++j) d[j] += av * w[j];
                 }
+        };
+        const int64_t stride = (int64_t)G * NT;
+        if (PIPE) {
+            // Three rows in flight, each in its own registers (no copies,
+            // which would wait for the loads): a row's loads are issued two
+            // rows before it is finished, so a store is only ever waited for
+            // two rows after it was issued. Rows past the end repeat the
+            // last row: loaded before that row's store, they store the same
+            // value again.
+            struct Row {
+                int64_t tl;
+                T a[kAtt];
+                Acc uo[KS];
+            };
+            auto load = [&](Row& r, int64_t k) {
+                r.tl = ldnt(&tloc[k]);
 #pragma unroll
-            for (int j = 0; j < KS; ++j) {
-                if (!((live >> j) & 1u)) continue;
-                Acc* up = u + k * K + s0 + j;
-                *up = d[j] - coef[j] * *up;
+                for (int c = 0; c < kAtt; ++c) r.a[c] = ldnt(&att_sorted[c * m + k]);
+#pragma unroll
+                for (int j = 0; j < KS; ++j) r.uo[j] = SEP ? (Acc)0 : u[k * K + s0 + j];
+            };
+            auto finish = [&](const Row& r, int64_t k) {
+                Acc d[KS];
+                row_dot_win(r.tl, r.a, d);
+#pragma unroll
+                for (int j = 0; j < KS; ++j)
+                    if (KS == 1 || ((live >> j) & 1u))
+                        u[k * K + s0 + j] = SEP ? d[j] : d[j] - coef[j] * r.uo[j];
+            };
+            int64_t k0 = b0 + g * NT + threadIdx.x;
+            if (k0 < r1) {
+                const int64_t klast = k0 + (r1 - 1 - k0) / stride * stride;
+                auto next = [&](int64_t k) { return k < klast ? k + stride : klast; };
+                Row A, B, C;
+                int64_t k1 = next(k0);
+                load(A, k0);
+                load(B, k1);
+                for (;;) {
+                    // scheduling fences keep the issue order of each step:
+                    // the loads of the row two ahead, then this row's store
+                    const int64_t k2 = next(k1);
+                    load(C, k2);
+                    __builtin_amdgcn_sched_barrier(0);
+                    finish(A, k0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int64_t k3 = next(k2);
+                    load(A, k3);
+                    __builtin_amdgcn_sched_barrier(0);
+                    finish(B, k1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int64_t k4 = next(k3);
+                    load(B, k4);
+                    __builtin_amdgcn_sched_barrier(0);
+                    finish(C, k2);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (k2 >= klast) break;  // rows from k3 on repeat the last row
+                    k0 = k3;
+                    k1 = k4;
+                }
+            }
+        } else {
+            for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += stride) {
+                const int64_t tl = ldnt(&tloc[k]);
+                T a[kAtt];
+#pragma unroll
+                for (int c = 0; c < kAtt; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
+                Acc d[KS];
+                row_dot_win(tl, a, d);
+#pragma unroll
+                for (int j = 0; j < KS; ++j) {
+                    if (!((live >> j) & 1u)) continue;
+                    Acc* up = u + k * K + s0 + j;
+                    *up = SEP ? d[j] : d[j] - coef[j] * *up;
+                }
             }
         }
         __syncthreads();  // the next sweep restages the window
@@ -1582,14 +1661,20 @@ __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__
 // runs at 7.6x the rate of the FP32 one (measured, random addresses over
 // 150 KB: 1550 vs 204 G/s), and the sums are more accurate. U is in bucket
 // order ([m][K]); K / KS sweeps cover the tile. Frozen RHS (done or
-// beta_zero) are skipped.
-template <typename T, typename Acc, int K, int KS, int NT>
+// beta_zero) are skipped. GATHER: U is in star order instead, and the row at
+// bucket position k is read at U[perm[k]] (a read through the permutation,
+// whose targets form one increasing run per bucket).
+// PIPE: each thread issues the loads of its next row before the atomics of
+// the current one (with GATHER, the current row's read through the
+// permutation first: its index came with the previous loads).
+template <typename T, typename Acc, int K, int KS, int NT, bool GATHER = false, bool PIPE = true>
 __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict__ att_sorted,
                                                   const int32_t* __restrict__ tloc,
                                                   const int64_t* __restrict__ bstart,
                                                   int64_t width, int G, const Acc* __restrict__ U,
                                                   double* __restrict__ S2,
-                                                  const Scalars* __restrict__ sc)
+                                                  const Scalars* __restrict__ sc,
+                                                  const int32_t* __restrict__ perm = nullptr)
 {
     static_assert(K % KS == 0, "sweeps of KS right-hand sides cover the tile");
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1605,14 +1690,8 @@ __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict_
         if (live == 0) continue;  // uniform over the grid
         for (int64_t e = threadIdx.x; e < kAxes * span * KS; e += NT) hist[e] = 0.0;
         __syncthreads();
-        for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += (int64_t)G * NT) {
-            const int64_t tl = ldnt(&tloc[k]);
-            double uk[KS];
-#pragma unroll
-            for (int j = 0; j < KS; ++j) uk[j] = (double)U[k * K + s0 + j];
-            T a[kAxes * kParAxis];  // all loads issued before the first atomic
-#pragma unroll
-            for (int c = 0; c < kAxes * kParAxis; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
+        constexpr int kAtt = kAxes * kParAxis;
+        auto scatter = [&](int64_t tl, const T (&a)[kAtt], const double (&uk)[KS]) {
 #pragma unroll
             for (int ax = 0; ax < kAxes; ++ax)
 #pragma unroll
@@ -1622,6 +1701,78 @@ __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict_
                         if ((live >> j) & 1u)
                             atomicAdd(&hist[(ax * span + tl + qq) * KS + j],
                                       (double)a[ax * kParAxis + qq] * uk[j]);
+        };
+        const int64_t stride = (int64_t)G * NT;
+        if (PIPE) {
+            // Three rows in flight as in k_att_dot; rows past the end repeat
+            // the last row with a zero weight. With GATHER a row's value is
+            // read through the permutation one step before the row is
+            // scattered (its index came with the row's loads).
+            struct Row {
+                int64_t tl, ku;
+                T a[kAtt];
+                double uk[KS];
+            };
+            auto load = [&](Row& r, int64_t k) {
+                r.tl = ldnt(&tloc[k]);
+                r.ku = GATHER ? (int64_t)ldnt(&perm[k]) : k;
+#pragma unroll
+                for (int c = 0; c < kAtt; ++c) r.a[c] = ldnt(&att_sorted[c * m + k]);
+                if (!GATHER)
+#pragma unroll
+                    for (int j = 0; j < KS; ++j) r.uk[j] = (double)U[k * K + s0 + j];
+            };
+            auto value = [&](Row& r, double w) {
+#pragma unroll
+                for (int j = 0; j < KS; ++j)
+                    r.uk[j] = w * (GATHER ? (double)U[r.ku * K + s0 + j] : r.uk[j]);
+            };
+            int64_t k0 = b0 + g * NT + threadIdx.x;
+            if (k0 < r1) {
+                const int64_t klast = k0 + (r1 - 1 - k0) / stride * stride;
+                // next row and its weight (0 for a repeat of the last row)
+                auto next = [&](int64_t k) { return k < klast ? k + stride : klast; };
+                Row A, B, C;
+                int64_t k1 = next(k0);
+                load(A, k0);
+                load(B, k1);
+                value(A, 1.0);
+                for (;;) {
+                    const int64_t k2 = next(k1);
+                    value(B, k1 > k0 ? 1.0 : 0.0);
+                    load(C, k2);
+                    __builtin_amdgcn_sched_barrier(0);
+                    scatter(A.tl, A.a, A.uk);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int64_t k3 = next(k2);
+                    value(C, k2 > k1 ? 1.0 : 0.0);
+                    load(A, k3);
+                    __builtin_amdgcn_sched_barrier(0);
+                    scatter(B.tl, B.a, B.uk);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int64_t k4 = next(k3);
+                    value(A, k3 > k2 ? 1.0 : 0.0);
+                    load(B, k4);
+                    __builtin_amdgcn_sched_barrier(0);
+                    scatter(C.tl, C.a, C.uk);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (k2 >= klast) break;
+                    k0 = k3;
+                    k1 = k4;
+                }
+            }
+        } else {
+            for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += stride) {
+                const int64_t tl = ldnt(&tloc[k]);
+                const int64_t ku = GATHER ? (int64_t)ldnt(&perm[k]) : k;
+                double uk[KS];
+#pragma unroll
+                for (int j = 0; j < KS; ++j) uk[j] = (double)U[ku * K + s0 + j];
+                T a[kAtt];  // all loads issued before the first atomic
+#pragma unroll
+                for (int c = 0; c < kAtt; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
+                scatter(tl, a, uk);
+            }
         }
         __syncthreads();
         for (int j = 0; j < KS; ++j) {
@@ -1912,20 +2063,153 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const Acc* __restrict_
     }
 }
 
-// X3[(3 c + axis) K + r] = VP[(att_base + axis n_dfa + c) K + r]: the attitude
-// section interleaved by axis, K values per column kept together.
-template <int K>
-__global__ __launch_bounds__(kBlock) void k_interleave_att(const double* __restrict__ VP,
+// X3[(3 c + axis) K + r] = VP[(att_base + axis n_dfa + c) ld + r]: the
+// attitude section interleaved by axis, K values per column kept together
+// (ld: row stride of VP, K for a tile's own vectors).
+template <typename V, int K>
+__global__ __launch_bounds__(kBlock) void k_interleave_att(const V* __restrict__ VP, int64_t ld,
                                                             int64_t att_base, int64_t n_dfa,
-                                                            double* __restrict__ X3)
+                                                            V* __restrict__ X3)
 {
     const int64_t total = (int64_t)kAxes * n_dfa * K;
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < total;
          j += (int64_t)gridDim.x * kBlock) {
         const int64_t col = j / K, r = j - col * K;
         const int64_t c = col / kAxes, ax = col - c * kAxes;
-        X3[j] = VP[(att_base + ax * n_dfa + c) * K + r];
+        X3[j] = VP[(att_base + ax * n_dfa + c) * ld + r];
     }
+}
+
+// Refinement residual of a k-tile: U_r = B_r - A X_r for the RHS with bit r
+// of `live` set (FP32-stored values widened, FP64 accumulation, stored as
+// VU at row i's place inv[i] (or i)), U_r = 0 for the others; FP64 sums of
+// squares of the stored values per RHS. X: [n][ldx], B: [m][ldb]; X3: the
+// attitude section of X interleaved by axis, K values per column.
+template <typename T, typename VU, int K>
+__global__ __launch_bounds__(kBlock) void k_resid(SysView s, const double* __restrict__ X,
+                                                   int64_t ldx, const double* __restrict__ X3,
+                                                   const double* __restrict__ B, int64_t ldb,
+                                                   VU* __restrict__ U, double* __restrict__ part,
+                                                   const int32_t* __restrict__ inv, uint32_t live)
+{
+    __shared__ double red[K * kWavesPerBlock];
+    const T* __restrict__ val = static_cast<const T*>(s.val);
+    const int64_t m = s.m;
+    double ssq[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) ssq[r] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int64_t st = ldnt(&s.star[i]);
+        const int64_t t = ldnt(&s.att[i]);
+        T a[kPar];
+#pragma unroll
+        for (int c = 0; c < kPar; ++c) a[c] = ldnt(&val[c * m + i]);
+        int32_t ic[kInstr];
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) ic[j] = ldnt(&s.instr[j * m + i]);
+        double d[K];
+#pragma unroll
+        for (int r = 0; r < K; ++r) d[r] = 0.0;
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j)
+#pragma unroll
+            for (int r = 0; r < K; ++r) d[r] += (double)a[j] * X[(kAstro * st + j) * ldx + r];
+#pragma unroll
+        for (int ax = 0; ax < kAxes; ++ax)
+#pragma unroll
+            for (int qq = 0; qq < kParAxis; ++qq) {
+                const double* xv = X3 + (kAxes * (t + qq) + ax) * K;
+                const double av = (double)a[kOffAtt + ax * kParAxis + qq];
+#pragma unroll
+                for (int r = 0; r < K; ++r) d[r] += av * xv[r];
+            }
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j)
+#pragma unroll
+            for (int r = 0; r < K; ++r)
+                d[r] += (double)a[kOffInstr + j] * X[(s.instr_base + ic[j]) * ldx + r];
+#pragma unroll
+        for (int r = 0; r < K; ++r) d[r] += (double)a[kOffGlob] * X[s.glob_base * ldx + r];
+        VU* u = U + (inv ? (int64_t)ldnt(&inv[i]) : i) * K;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const VU v = ((live >> r) & 1u) ? (VU)(B[i * ldb + r] - d[r]) : (VU)0;
+            u[r] = v;
+            ssq[r] += (double)v * (double)v;
+        }
+    }
+    block_sums_k<K>(ssq, part, red);
+}
+
+// Refinement step of a k-tile: X_r += p .* Y_r for the RHS with bit r of
+// `live` set; per-RHS partial maxima of |p .* Y_r| and |X_r|
+// (part_d/part_x [nblk][K]).
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_refine_update(int64_t n, const double* __restrict__ p,
+                                                           const double* __restrict__ Y,
+                                                           double* __restrict__ X, int64_t ldx,
+                                                           uint32_t live,
+                                                           double* __restrict__ part_d,
+                                                           double* __restrict__ part_x)
+{
+    __shared__ double red[kWavesPerBlock];
+    double dm[K], xm[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) dm[r] = xm[r] = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * kBlock) {
+        const double pj = p[j];
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            if (!((live >> r) & 1u)) continue;
+            const double d = pj * Y[j * K + r];
+            const double xj = X[j * ldx + r] + d;
+            X[j * ldx + r] = xj;
+            dm[r] = fmax(dm[r], fabs(d));
+            xm[r] = fmax(xm[r], fabs(xj));
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+        double v = block_max(dm[r], red);
+        if (threadIdx.x == 0) part_d[(int64_t)blockIdx.x * K + r] = v;
+        v = block_max(xm[r], red);
+        if (threadIdx.x == 0) part_x[(int64_t)blockIdx.x * K + r] = v;
+    }
+}
+
+// sc[r].dmax, sc[r].xmax = maxima over the partials of k_refine_update.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_refine_norms(const double* __restrict__ part_d,
+                                                          const double* __restrict__ part_x,
+                                                          int nblk, Scalars* __restrict__ sc)
+{
+    __shared__ double red[kWavesPerBlock];
+    for (int r = 0; r < K; ++r) {
+        double v = 0.0, w = 0.0;
+        for (int k = threadIdx.x; k < nblk; k += kBlock) {
+            v = fmax(v, part_d[(int64_t)k * K + r]);
+            w = fmax(w, part_x[(int64_t)k * K + r]);
+        }
+        const double d = block_max(v, red);
+        const double x = block_max(w, red);
+        if (threadIdx.x == 0) {
+            sc[r].dmax = d;
+            sc[r].xmax = x;
+        }
+    }
+}
+
+// X[j][r] = 0 (row stride ldx), r < K
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_zero_cols(int64_t n, double* __restrict__ X,
+                                                       int64_t ldx)
+{
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * kBlock)
+#pragma unroll
+        for (int r = 0; r < K; ++r) X[j * ldx + r] = 0.0;
 }
 
 // Fused iteration pass of a K-tile (the batched form of the single-RHS fused
@@ -2279,6 +2563,7 @@ __global__ __launch_bounds__(kBlock) void k_scalar_init_alpha(const double* __re
             s.rhobar = alpha;
             s.phibar = s.beta;
             s.arnorm = alpha * s.beta;
+            s.arnorm0 = s.arnorm;
             s.inv_alpha = alpha > 0.0 ? 1.0 / alpha : 1.0;
             s.coef_u = alpha / s.beta;
             if (s.arnorm == 0.0) s.done = 1;
@@ -2381,6 +2666,8 @@ __global__ __launch_bounds__(kBlock) void k_scalar_stop(const double* __restrict
                 if (test2 <= s.atol) istop = 2;
                 if (test1 <= rtol) istop = 1;
             }
+            // relative normal-equation test of a refinement's inner solve
+            if (s.rel_ar > 0.0 && arnorm <= s.rel_ar * s.arnorm0) istop = 2;
             s.istop = istop;
             if (istop != 0) s.done = 1;
         }

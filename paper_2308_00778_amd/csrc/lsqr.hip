@@ -127,6 +127,7 @@ struct Path {
     Acc* q = nullptr;      // [n] aprod2 accumulator (zero between uses)
     Acc* gpart = nullptr;  // [nb2] global-column partials
     Acc* vp3 = nullptr;    // [3 n_dfa] attitude section of vp interleaved by axis
+    Acc* datt = nullptr;   // [m] fused mode 3: attitude part of A vp in bucket order
     int64_t hcols = 0;     // instrumental columns kept in the row passes' LDS histogram
     size_t lds = 0;        // dynamic LDS bytes of aprod2's main pass
     size_t lds_f = 0;      // dynamic LDS bytes of the fused pass
@@ -192,8 +193,9 @@ struct lsqr_handle {
     int64_t att_buckets = 0;      // requested bucket count (0: as few as fit)
     int att_rhs = 1;              // right-hand sides one attitude sweep must hold
     double* S2 = nullptr;         // [nbk att_g][3][W + 3] slices of the attitude pass
-    double* us_raw = nullptr;     // [m] lsqr_aprod2's row vector in bucket order
     double* x3_raw = nullptr;     // interleaved attitude section of lsqr_aprod1's x
+    float* x3_raw32 = nullptr;    // the same for lsqr_aprod1_f32
+    float* gpart_raw32 = nullptr; // global-column partials of lsqr_aprod2_f32
     bool att_ready = false;
 
     // variance estimate of the last lsqr_solve (LSQR_OPT_VARIANCE)
@@ -201,18 +203,30 @@ struct lsqr_handle {
     int var_on = 0;               // accumulate during solves
     int var_valid = 0;            // var belongs to the last solve
 
-    // batched right-hand sides (tile buffers for the largest K, reused per tile)
+    // batched right-hand sides (tile buffers for the largest K, reused per
+    // tile): the FP64 tiles of lsqr_solve_batched and the FP32 inner tiles of
+    // lsqr_solve_batched_refined (U, VP, Q, global partials and the
+    // interleaved attitude copy in each precision; V, W, Y, partials and
+    // scalars shared)
     struct Batch {
         int kmax = 0;
+        bool has64 = false, has32 = false;
         double *U = nullptr, *V = nullptr, *W = nullptr, *Y = nullptr, *VP = nullptr, *Q = nullptr;
         double *gpart = nullptr, *part1 = nullptr, *partc = nullptr, *partdd = nullptr,
                *partxx = nullptr, *S2 = nullptr, *X3 = nullptr;
+        float *U32 = nullptr, *VP32 = nullptr, *Q32 = nullptr, *gpart32 = nullptr, *X332 = nullptr;
         Scalars* sc = nullptr;
         int32_t* flag = nullptr;
-        hipGraphExec_t graph[9] = {};  // by K
+        hipGraphExec_t graph[9] = {};    // FP64 tiles, by K
         int graph_chunk[9] = {};
-        int tuned_k = 0;               // autotuner's choice for this handle
-        double tuned_ms[9] = {};       // measured ms per RHS-iteration by K
+        hipGraphExec_t graph32[9] = {};  // FP32 inner tiles, by K
+        int graph32_chunk[9] = {};
+        // autotuner: chosen k-tile per precision (0, 1) and per cap min(k, 8)
+        // (index log2), and the measured ms per RHS-iteration by K of the last
+        // tuning
+        int tuned_k[2][4] = {};
+        int last_tuned = 0;
+        double tuned_ms[9] = {};
     } batch;
 
     // options
@@ -226,8 +240,10 @@ struct lsqr_handle {
     int att_il = 1;      // aprod1 gathers attitude values from the interleaved copy
     int fused = 2;       // 1: one pass for aprod1 and the non-attitude part of aprod2;
                          // 2: the same with the attitude part of aprod1 in a bucket-order
-                         // pre-pass (k_att_dot); 0: separate aprod1 and aprod2
+                         // pre-pass (k_att_dot); 3: as 2 with the row vector in star
+                         // order (pre-pass output gathered); 0: separate aprod1 and aprod2
     int last_mode = 0;   // fused mode of the last single-RHS solve
+    int pipe = 1;        // bucket-order passes load the next row before storing the current
     int compact = 1;     // compact index copies for the fused passes when they fit
     int compact_tried = 0;
     int32_t* star32 = nullptr;    // [m] compact star index (or null)
@@ -244,14 +260,37 @@ struct lsqr_handle {
 
 namespace {
 
-// Placement of the solver's row vector: bucket order in attitude mode 1.
 inline bool att_pass_on(const lsqr_handle* h) { return h->att_mode == 1 && h->sv.natt > 0; }
+
+// The fused pass serves the default attitude mode (bucket-order pass).
+inline bool use_fused(const lsqr_handle* h)
+{
+    return h->fused && att_pass_on(h) && !h->generic;
+}
+
+// Effective fused mode of a single-RHS iteration: 0 separate passes, 1 fused
+// pass with the attitude dot product, 2 attitude pre-pass + fused pass, 3 the
+// same with the row vector kept in star order.
+inline int fused_mode(const lsqr_handle* h) { return use_fused(h) ? h->fused : 0; }
+
+// Fused mode 3 keeps the single-RHS row vector in star order: the star-order
+// pass reads and writes it sequentially, and the bucket-order passes reach it
+// (or the pre-pass's separate output) through the permutation, read-only.
+inline bool star_order_u(const lsqr_handle* h) { return fused_mode(h) == 3; }
 
 // Partials of ||u||^2 that a scalar kernel sums: the row-pass partials plus,
 // with constraint rows, their share stored right after them.
 inline int n_part(const lsqr_handle* h, int nb) { return nb + (h->nc > 0 ? 1 : 0); }
 
+// Placement of the single-RHS solver's row vector: bucket order in attitude
+// mode 1 (row i at u[invperm[i]]) except in fused mode 3.
 inline const int32_t* row_map(const lsqr_handle* h)
+{
+    return (att_pass_on(h) && !star_order_u(h)) ? h->invperm : nullptr;
+}
+
+// Placement of a batched k-tile's row vectors: bucket order in attitude mode 1.
+inline const int32_t* batch_row_map(const lsqr_handle* h)
 {
     return att_pass_on(h) ? h->invperm : nullptr;
 }
@@ -390,34 +429,54 @@ void launch_interleave_att(const lsqr_handle* h, const V* x, V* x3, const Scalar
 template <typename T, typename Acc, bool LDSX, int AM>
 void launch_fused_as(const lsqr_handle* h, Path<Acc>& P, const Acc* x3, hipStream_t st)
 {
+    // kAttGather reads the pre-pass output through invperm; u~ is in star order
+    const int32_t* inv = AM == kAttGather ? (const int32_t*)h->invperm : row_map(h);
+    const Acc* datt = AM == kAttGather ? (const Acc*)P.datt : nullptr;
     if (h->sv.star32)
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, LDSX, AM, true>), dim3(h->nb2), dim3(kBlock2),
                            P.lds_f, st, h->sv, (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart,
-                           h->part1, P.f_hcols, h->sc, row_map(h));
+                           h->part1, P.f_hcols, h->sc, inv, datt);
     else
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, LDSX, AM, false>), dim3(h->nb2),
                            dim3(kBlock2), P.lds_f, st, h->sv, (const Acc*)P.vp, x3, P.u, P.q,
-                           h->wb, P.gpart, h->part1, P.f_hcols, h->sc, row_map(h));
+                           h->wb, P.gpart, h->part1, P.f_hcols, h->sc, inv, datt);
 }
 
-// Attitude part of aprod1 in bucket order, folded into u~ (fused mode 2):
-// x3 must hold the interleaved attitude section of vp.
+// Attitude part of aprod1 in bucket order (x3 must hold the interleaved
+// attitude section of vp): folded into u~ in fused mode 2, written alone to
+// the bucket-order vector datt in fused mode 3.
+template <typename T, typename Acc, bool SEP, bool PIPE>
+void launch_att_dot_as(const lsqr_handle* h, Path<Acc>& P, hipStream_t st)
+{
+    const size_t lds = (size_t)(kAxes * att_span(h)) * sizeof(Acc);
+    hipLaunchKernelGGL((k_att_dot<T, Acc, 1, 1, kAttBlock, SEP, PIPE>), dim3(att_slices(h)),
+                       dim3(kAttBlock), lds, st, h->sv.m, (const T*)h->att_sorted,
+                       (const int32_t*)h->tloc, (const int64_t*)h->bstart, h->bwidth, h->att_g,
+                       h->sv.n_dfa, (const Acc*)P.vp3, SEP ? P.datt : P.u, h->sc);
+}
+
 template <typename T, typename Acc>
 void launch_att_dot(const lsqr_handle* h, Path<Acc>& P, hipStream_t st)
 {
-    const size_t lds = (size_t)(kAxes * att_span(h)) * sizeof(Acc);
-    hipLaunchKernelGGL((k_att_dot<T, Acc, 1, 1, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock), lds,
-                       st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
-                       (const int64_t*)h->bstart, h->bwidth, h->att_g, h->sv.n_dfa,
-                       (const Acc*)P.vp3, P.u, h->sc);
+    if (star_order_u(h)) {
+        if (h->pipe) launch_att_dot_as<T, Acc, true, true>(h, P, st);
+        else launch_att_dot_as<T, Acc, true, false>(h, P, st);
+    } else {
+        if (h->pipe) launch_att_dot_as<T, Acc, false, true>(h, P, st);
+        else launch_att_dot_as<T, Acc, false, false>(h, P, st);
+    }
 }
 
 // pre: the attitude part of the row products is already in u~ (fused mode 2)
+// or in datt (fused mode 3)
 template <typename T, typename Acc>
 void launch_fused(const lsqr_handle* h, Path<Acc>& P, hipStream_t st, bool pre)
 {
     const Acc* x3 = h->att_il ? (const Acc*)P.vp3 : nullptr;
-    if (pre) {
+    if (pre && star_order_u(h)) {
+        if (P.f_ldsx) launch_fused_as<T, Acc, true, kAttGather>(h, P, nullptr, st);
+        else launch_fused_as<T, Acc, false, kAttGather>(h, P, nullptr, st);
+    } else if (pre) {
         if (P.f_ldsx) launch_fused_as<T, Acc, true, kAttPre>(h, P, nullptr, st);
         else launch_fused_as<T, Acc, false, kAttPre>(h, P, nullptr, st);
     } else if (P.f_ldsx) {
@@ -431,14 +490,29 @@ void launch_fused(const lsqr_handle* h, Path<Acc>& P, hipStream_t st, bool pre)
 }
 
 // Attitude part of aprod2 in bucket order: per-workgroup LDS histograms of
-// each bucket's columns (ub: the row vector in bucket order), then their sum.
+// each bucket's columns, then their sum. ub: the row vector in bucket order,
+// or (gperm = perm) in star order, read through the permutation.
 template <typename T, typename Acc>
-void launch_att_pass(lsqr_handle* h, const Acc* ub, Acc* q, const Scalars* sc, hipStream_t st)
+void launch_att_pass(lsqr_handle* h, const Acc* ub, Acc* q, const Scalars* sc, hipStream_t st,
+                     const int32_t* gperm)
 {
     const size_t lds = (size_t)(kAxes * att_span(h) * 8);
-    hipLaunchKernelGGL((k_att_hist<T, Acc, 1, 1, kAttBlock>), dim3(att_slices(h)), dim3(kAttBlock),
-                       lds, st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
-                       (const int64_t*)h->bstart, h->bwidth, h->att_g, ub, h->S2, sc);
+    auto go = [&](auto gather, auto pipe) {
+        hipLaunchKernelGGL((k_att_hist<T, Acc, 1, 1, kAttBlock, decltype(gather)::value,
+                                       decltype(pipe)::value>),
+                           dim3(att_slices(h)), dim3(kAttBlock), lds, st, h->sv.m,
+                           (const T*)h->att_sorted, (const int32_t*)h->tloc,
+                           (const int64_t*)h->bstart, h->bwidth, h->att_g, ub, h->S2, sc, gperm);
+    };
+    using Y = std::true_type;
+    using N = std::false_type;
+    if (gperm) {
+        if (h->pipe) go(Y(), Y());
+        else go(Y(), N());
+    } else {
+        if (h->pipe) go(N(), Y());
+        else go(N(), N());
+    }
     hipLaunchKernelGGL((k_att_reduce<Acc, 1>), dim3(h->nbc), dim3(kBlock), 0, st,
                        (const double*)h->S2, h->nbk, h->att_g, h->bwidth, h->sv.n_dfa,
                        q + h->sv.att_base, sc);
@@ -448,10 +522,11 @@ void launch_att_pass(lsqr_handle* h, const Acc* ub, Acc* q, const Scalars* sc, h
 // the main pass over the rows in star order (row i of u at u[inv[i]], or u[i]
 // without inv), the
 // global-column second stage and, in attitude mode 1, the attitude pass over
-// ub, the same vector in bucket order.
+// ub, the same vector in bucket order (or in star order, read through gperm).
 template <typename T, typename Acc>
 void launch_aprod2(lsqr_handle* h, const Acc* u, const int32_t* inv, Acc* q, Acc* gpart,
-                   int64_t hcols, const Scalars* sc, hipStream_t st, const Acc* ub)
+                   int64_t hcols, const Scalars* sc, hipStream_t st, const Acc* ub,
+                   const int32_t* gperm)
 {
     const size_t lds = (size_t)(hcols * 8);
     const dim3 g(h->nb2), bm(kBlock2), b(kBlock);
@@ -467,7 +542,7 @@ void launch_aprod2(lsqr_handle* h, const Acc* u, const int32_t* inv, Acc* q, Acc
         hipLaunchKernelGGL((k_gen_glob_sum<Acc>), dim3(1), b, 0, st, gpart, h->nba, h->sv.ng,
                            q + h->sv.glob_base, sc);
         launch_instr_tail<T, Acc, 1, false>(h, u, inv, q, hcols, sc, st);
-        if (!att) launch_att_pass<T, Acc>(h, ub, q, sc, st);
+        if (!att) launch_att_pass<T, Acc>(h, ub, q, sc, st, gperm);
         return;
     }
     if (att && h->astro_scan)
@@ -484,18 +559,8 @@ void launch_aprod2(lsqr_handle* h, const Acc* u, const int32_t* inv, Acc* q, Acc
                            h->sv, u, q, h->wb, gpart, hcols, sc, inv);
     hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), b, 0, st, gpart, h->nb2, q + h->sv.glob_base, sc);
     launch_instr_tail<T, Acc, 1, false>(h, u, inv, q, hcols, sc, st);
-    if (!att) launch_att_pass<T, Acc>(h, ub, q, sc, st);
+    if (!att) launch_att_pass<T, Acc>(h, ub, q, sc, st, gperm);
 }
-
-// The fused pass serves the default attitude mode (bucket-order pass).
-inline bool use_fused(const lsqr_handle* h)
-{
-    return h->fused && att_pass_on(h) && !h->generic;
-}
-
-// Effective fused mode of an iteration: 0 separate passes, 1 fused pass with
-// the attitude dot product, 2 attitude pre-pass + fused pass.
-inline int fused_mode(const lsqr_handle* h) { return use_fused(h) ? h->fused : 0; }
 
 // One LSQR iteration; ev (optional) = kEvIter events: [0, 1] around aprod1
 // (with the fused pass: the attitude pre-pass, if any, and that pass), [2, 3]
@@ -505,7 +570,7 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
 {
     const int64_t n = h->sv.n;
     if (ev) (void)hipEventRecord(ev[0], st);
-    const bool pre = fused_mode(h) == 2;
+    const bool pre = fused_mode(h) >= 2;
     const bool il = (h->att_il || pre) && h->sv.natt > 0 && !h->generic;
     if (il) launch_interleave_att<Acc>(h, P.vp, P.vp3, h->sc, st);
     if (pre) launch_att_dot<T, Acc>(h, P, st);
@@ -520,7 +585,8 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
         if (ev) (void)hipEventRecord(ev[2], st);
         hipLaunchKernelGGL((k_glob_sum<Acc>), dim3(1), dim3(kBlock), 0, st, P.gpart, h->nb2,
                            P.q + h->sv.glob_base, h->sc);
-        launch_att_pass<T, Acc>(h, P.u, P.q, h->sc, st);
+        launch_att_pass<T, Acc>(h, P.u, P.q, h->sc, st,
+                                star_order_u(h) ? (const int32_t*)h->perm : nullptr);
         launch_con_aprod2<Acc, Acc>(h, P.u + h->sv.m, P.q, h->sc, st);
     } else {
         launch_aprod1<T, Acc, Acc, Acc, A1_LSQR>(h, (const Acc*)P.vp, P.u, nullptr, h->sc,
@@ -530,7 +596,8 @@ void launch_iteration(lsqr_handle* h, Path<Acc>& P, hipStream_t st, hipEvent_t* 
         hipLaunchKernelGGL(k_scalar_beta, dim3(1), dim3(kBlock), 0, st, h->part1,
                            n_part(h, h->nb1), h->sc);
         if (ev) (void)hipEventRecord(ev[2], st);
-        launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.hcols, h->sc, st, P.u);
+        launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.hcols, h->sc, st, P.u,
+                              nullptr);
     }
     if (ev) (void)hipEventRecord(ev[3], st);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
@@ -553,7 +620,8 @@ void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st)
                        n_part(h, h->nb1), h->sc);
     hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, P.q, (Acc)0);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->v, 0.0);
-    launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.hcols, h->sc, st, P.u);
+    launch_aprod2<T, Acc>(h, P.u, row_map(h), P.q, P.gpart, P.hcols, h->sc, st, P.u,
+                          star_order_u(h) ? (const int32_t*)h->perm : nullptr);
     hipLaunchKernelGGL((k_col_a<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, P.q, h->v,
                        h->sc, h->partc);
     hipLaunchKernelGGL(k_scalar_init_alpha, dim3(1), dim3(kBlock), 0, st, h->partc, h->nbc, h->sc);
@@ -561,23 +629,57 @@ void launch_init(lsqr_handle* h, Path<Acc>& P, hipStream_t st)
                        h->y, P.vp, h->sc);
 }
 
-template <typename T, typename Acc>
-lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
+void batch_free(lsqr_handle* h);
+template <typename Acc>
+void release_path(Path<Acc>& P);
+
+template <typename Acc>
+lsqr_status path_alloc(lsqr_handle* h, Path<Acc>& P)
 {
-    if (P.ready) return LSQR_OK;
     const int64_t m = h->sv.m, n = h->sv.n;
     LSQR_TRY(dalloc(&P.u, m + h->nc));  // observation rows, then constraint rows
     LSQR_TRY(dalloc(&P.vp, n));
     LSQR_TRY(dalloc(&P.q, n));
     LSQR_TRY(dalloc(&P.gpart, std::max<int64_t>(h->nb2, (int64_t)h->nba * kGlobMax)));
     LSQR_TRY(dalloc(&P.vp3, (int64_t)kAxes * h->sv.n_dfa));
-    // LDS histograms are FP64 whatever Acc is (k_att_hist)
-    P.hcols = instr_hcols(h, 1);
-    P.lds = (size_t)(P.hcols * 8);
-    P.lds_f = fused_lds_plan(h, 1, (int64_t)sizeof(Acc), &P.f_hcols, &P.f_ldsx);
-    hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n, P.q, (Acc)0);
-    HIP_TRY(hipGetLastError());
-    P.ready = true;
+    return LSQR_OK;
+}
+
+// Working vectors of one precision of the single-RHS loop. When device
+// memory runs short, the batched tile buffers are released (a later batched
+// solve allocates them again) and the allocation is tried once more.
+template <typename T, typename Acc>
+lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
+{
+    if (!P.ready) {
+        const int64_t n = h->sv.n;
+        lsqr_status rc = path_alloc(h, P);
+        if (rc == LSQR_E_NOMEM) {
+            release_path(P);
+            batch_free(h);
+            g_last_error.clear();
+            rc = path_alloc(h, P);
+        }
+        if (rc != LSQR_OK) {
+            release_path(P);
+            return rc;
+        }
+        // LDS histograms are FP64 whatever Acc is (k_att_hist)
+        P.hcols = instr_hcols(h, 1);
+        P.lds = (size_t)(P.hcols * 8);
+        P.lds_f = fused_lds_plan(h, 1, (int64_t)sizeof(Acc), &P.f_hcols, &P.f_ldsx);
+        hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n, P.q,
+                           (Acc)0);
+        HIP_TRY(hipGetLastError());
+        P.ready = true;
+    }
+    if (star_order_u(h) && !P.datt) {  // fused mode 3: the pre-pass output
+        if (dalloc(&P.datt, h->sv.m) == LSQR_E_NOMEM) {
+            batch_free(h);
+            g_last_error.clear();
+            LSQR_TRY(dalloc(&P.datt, h->sv.m));
+        }
+    }
     return LSQR_OK;
 }
 
@@ -686,10 +788,13 @@ void drop_graphs(lsqr_handle* h)
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
     }
-    for (auto& g : h->batch.graph) {
-        if (g) (void)hipGraphExecDestroy(g);
-        g = nullptr;
-    }
+    for (auto* gs : {h->batch.graph, h->batch.graph32})
+        for (int k = 0; k < 9; ++k) {
+            if (gs[k]) (void)hipGraphExecDestroy(gs[k]);
+            gs[k] = nullptr;
+        }
+    // the autotuner's choice was made with the kernels these options select
+    memset(h->batch.tuned_k, 0, sizeof h->batch.tuned_k);
 }
 
 // Compact index copies for the fused passes (int32 star, uint16 instrumental
@@ -734,6 +839,7 @@ void release_path(Path<Acc>& P)
     dfree(P.q);
     dfree(P.gpart);
     dfree(P.vp3);
+    dfree(P.datt);
     P.ready = false;
 }
 
@@ -881,27 +987,31 @@ lsqr_status solve_fp64(lsqr_handle* h, const double* b, double* x, int32_t itn_l
 }
 
 // ------------------------------------------------------------- batched RHS
-lsqr_status batch_alloc(lsqr_handle* h, int kmax)
+void batch_free(lsqr_handle* h)
 {
     auto& B = h->batch;
-    if (B.kmax >= kmax && (B.S2 || !h->att_ready)) return LSQR_OK;
-    kmax = std::max(kmax, B.kmax);
-    const int64_t m = h->sv.m, n = h->sv.n;
-    // free the smaller set (graphs reference it)
-    for (auto& g : B.graph)
-        if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+    for (auto* gs : {B.graph, B.graph32})
+        for (int k = 0; k < 9; ++k) {
+            if (gs[k]) (void)hipGraphExecDestroy(gs[k]);
+            gs[k] = nullptr;
+        }
     dfree(B.U); dfree(B.V); dfree(B.W); dfree(B.Y); dfree(B.VP); dfree(B.Q);
     dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
     dfree(B.sc); dfree(B.flag); dfree(B.S2); dfree(B.X3);
+    dfree(B.U32); dfree(B.VP32); dfree(B.Q32); dfree(B.gpart32); dfree(B.X332);
     B.kmax = 0;
+    B.has64 = B.has32 = false;
+}
+
+lsqr_status batch_alloc_once(lsqr_handle* h, int kmax, bool want64, bool want32)
+{
+    auto& B = h->batch;
+    const int64_t m = h->sv.m, n = h->sv.n;
     if (h->att_ready) LSQR_TRY(dalloc(&B.S2, att_slices(h) * kAxes * att_span(h) * kmax));
     LSQR_TRY(dalloc(&B.X3, (int64_t)kAxes * h->sv.n_dfa * kmax));
-    LSQR_TRY(dalloc(&B.U, m * kmax));
     LSQR_TRY(dalloc(&B.V, n * kmax));
     LSQR_TRY(dalloc(&B.W, n * kmax));
     LSQR_TRY(dalloc(&B.Y, n * kmax));
-    LSQR_TRY(dalloc(&B.VP, n * kmax));
-    LSQR_TRY(dalloc(&B.Q, n * kmax));
     LSQR_TRY(dalloc(&B.gpart, (int64_t)h->nba * kmax));
     LSQR_TRY(dalloc(&B.part1, (int64_t)std::max(h->nb1, h->nba) * kmax));
     LSQR_TRY(dalloc(&B.partc, (int64_t)h->nbc * kmax));
@@ -909,24 +1019,76 @@ lsqr_status batch_alloc(lsqr_handle* h, int kmax)
     LSQR_TRY(dalloc(&B.partxx, (int64_t)h->nbc * kmax));
     LSQR_TRY(dalloc(&B.sc, kmax));
     LSQR_TRY(dalloc(&B.flag, 1));
-    hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n * kmax, B.Q,
-                       0.0);
+    if (want64) {
+        LSQR_TRY(dalloc(&B.U, m * kmax));
+        LSQR_TRY(dalloc(&B.VP, n * kmax));
+        LSQR_TRY(dalloc(&B.Q, n * kmax));
+        hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n * kmax,
+                           B.Q, 0.0);
+    }
+    if (want32) {
+        LSQR_TRY(dalloc(&B.U32, m * kmax));
+        LSQR_TRY(dalloc(&B.VP32, n * kmax));
+        LSQR_TRY(dalloc(&B.Q32, n * kmax));
+        LSQR_TRY(dalloc(&B.gpart32, (int64_t)h->nba * kmax));
+        LSQR_TRY(dalloc(&B.X332, (int64_t)kAxes * h->sv.n_dfa * kmax));
+        hipLaunchKernelGGL((k_fill<float>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n * kmax,
+                           B.Q32, 0.0f);
+    }
     HIP_TRY(hipGetLastError());
     B.kmax = kmax;
+    B.has64 = want64;
+    B.has32 = want32;
     return LSQR_OK;
 }
 
-void batch_free(lsqr_handle* h)
+// Tile buffers for up to kmax right-hand sides in the wanted precision
+// (FP64 tiles, FP32 inner tiles). A set too small, or of the other precision
+// only, is freed first (the captured graphs go with it). When device memory
+// runs short, the single-RHS working vectors are released (a later single
+// solve allocates them again) and the allocation is tried once more.
+lsqr_status batch_alloc(lsqr_handle* h, int kmax, bool fp32)
 {
     auto& B = h->batch;
-    for (auto& g : B.graph)
-        if (g) (void)hipGraphExecDestroy(g), g = nullptr;
-    dfree(B.U); dfree(B.V); dfree(B.W); dfree(B.Y); dfree(B.VP); dfree(B.Q);
-    dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
-    dfree(B.sc); dfree(B.flag); dfree(B.S2); dfree(B.X3);
-    B.kmax = 0;
+    if (B.kmax >= kmax && (fp32 ? B.has32 : B.has64) && (B.S2 || !h->att_ready)) return LSQR_OK;
+    kmax = std::max(kmax, B.kmax);
+    batch_free(h);
+    lsqr_status rc = batch_alloc_once(h, kmax, !fp32, fp32);
+    if (rc == LSQR_E_NOMEM) {
+        batch_free(h);
+        release_path(h->p64);
+        release_path(h->p32);
+        g_last_error.clear();
+        rc = batch_alloc_once(h, kmax, !fp32, fp32);
+    }
+    if (rc != LSQR_OK) batch_free(h);
+    return rc;
 }
 
+// The buffers of one precision of a k-tile.
+template <typename Acc>
+struct TileBufs {
+    Acc *U, *VP, *Q, *gpart, *X3;
+    hipGraphExec_t* graph;
+    int* graph_chunk;
+};
+
+template <typename Acc>
+TileBufs<Acc> tile_bufs(lsqr_handle* h);
+
+template <>
+TileBufs<double> tile_bufs<double>(lsqr_handle* h)
+{
+    auto& B = h->batch;
+    return {B.U, B.VP, B.Q, B.gpart, B.X3, B.graph, B.graph_chunk};
+}
+
+template <>
+TileBufs<float> tile_bufs<float>(lsqr_handle* h)
+{
+    auto& B = h->batch;
+    return {B.U32, B.VP32, B.Q32, B.gpart32, B.X332, B.graph32, B.graph32_chunk};
+}
 
 // Workgroup shape of the batched row passes over the star-aligned ranges: K <= 2
 // fits the 128 registers a lane has in a 1024-thread workgroup; wider tiles
@@ -952,19 +1114,21 @@ template <int K, int AM>
 int fused_grid(const lsqr_handle* h) { return (int)(h->nw / (fused_nt<K, AM>() / kWave)); }
 
 // Workgroups (partials) of the fused pass an iteration of a K-tile runs
+// (fused mode 3 runs as 2 in k-tiles)
 template <int K>
 int batch_fused_grid(const lsqr_handle* h)
 {
-    return h->fused == 2 ? fused_grid<K, kAttPre>(h) : fused_grid<K, kAttX>(h);
+    return h->fused >= 2 ? fused_grid<K, kAttPre>(h) : fused_grid<K, kAttX>(h);
 }
 
 // Right-hand sides per sweep of the bucket-order attitude passes of a K-tile:
 // the largest power of two up to K whose window or histogram, 3 (W + 3) KS
-// doubles, fits in LDS. Narrower buckets (more of them) widen the sweeps.
+// values (FP64 for the histograms, vbytes each for the windows), fits in LDS.
+// Narrower buckets (more of them) widen the sweeps.
 template <int K>
-int att_sweep(const lsqr_handle* h)
+int att_sweep(const lsqr_handle* h, int64_t vbytes = 8)
 {
-    const int64_t fit = kLdsInstrBudget / (kAxes * att_span(h) * 8);
+    const int64_t fit = kLdsInstrBudget / (kAxes * att_span(h) * vbytes);
     int ks = 1;
     while (ks * 2 <= K && ks * 2 <= fit) ks *= 2;
     return ks;
@@ -982,154 +1146,148 @@ void by_sweep(int ks, F&& f)
     f(std::integral_constant<int, 1>());
 }
 
-template <typename T, int K>
+template <typename T, typename Acc, int K>
 void batch_att_pass(lsqr_handle* h, hipStream_t st)
 {
     auto& B = h->batch;
+    const TileBufs<Acc> tb = tile_bufs<Acc>(h);
     // at most 2 RHS per histogram sweep: 4 FP64 histograms fill LDS, leave
     // one workgroup per CU and halve the rate of its atomics (1e8 rows, 64
     // buckets: one 4-RHS sweep 6.3 ms, two 2-RHS sweeps 2 x 2.15 ms)
     const int ks = std::min(2, att_sweep<K>(h));
     by_sweep<K>(ks, [&](auto KS) {
-        hipLaunchKernelGGL((k_att_hist<T, double, K, KS(), kAttBlock>), dim3(att_slices(h)),
+        hipLaunchKernelGGL((k_att_hist<T, Acc, K, KS(), kAttBlock>), dim3(att_slices(h)),
                            dim3(kAttBlock), (size_t)(kAxes * att_span(h) * 8 * ks), st, h->sv.m,
                            (const T*)h->att_sorted, (const int32_t*)h->tloc,
-                           (const int64_t*)h->bstart, h->bwidth, h->att_g, (const double*)B.U,
-                           B.S2, B.sc);
+                           (const int64_t*)h->bstart, h->bwidth, h->att_g, (const Acc*)tb.U,
+                           B.S2, B.sc, (const int32_t*)nullptr);
     });
-    hipLaunchKernelGGL((k_att_reduce<double, K>), dim3(h->nbc), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL((k_att_reduce<Acc, K>), dim3(h->nbc), dim3(kBlock), 0, st,
                        (const double*)B.S2, h->nbk, h->att_g, h->bwidth, h->sv.n_dfa,
-                       B.Q + h->sv.att_base * K, B.sc);
+                       tb.Q + h->sv.att_base * K, B.sc);
 }
 
-template <typename T, int K>
+template <typename T, typename Acc, int K>
 void batch_aprod2(lsqr_handle* h, hipStream_t st)
 {
     auto& B = h->batch;
+    const TileBufs<Acc> tb = tile_bufs<Acc>(h);
     const int64_t hc = instr_hcols(h, K);
     const size_t lds = (size_t)(hc * K * 8);
     constexpr int NT = batch_nt<K>();
     const int grid = batch_grid<K>(h);
     if (h->att_mode == 0)
-        hipLaunchKernelGGL((batched::k_aprod2<T, double, K, true, NT>), dim3(grid), dim3(NT), lds,
-                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, hc, B.sc,
-                           row_map(h));
+        hipLaunchKernelGGL((batched::k_aprod2<T, Acc, K, true, NT>), dim3(grid), dim3(NT), lds, st,
+                           h->sv, (const Acc*)tb.U, tb.Q, h->wb, tb.gpart, hc, B.sc,
+                           batch_row_map(h));
     else
-        hipLaunchKernelGGL((batched::k_aprod2<T, double, K, false, NT>), dim3(grid), dim3(NT), lds,
-                           st, h->sv, (const double*)B.U, B.Q, h->wb, B.gpart, hc, B.sc,
-                           row_map(h));
-    hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
-                       (const double*)B.gpart, grid, B.Q + h->sv.glob_base * K, B.sc);
-    launch_instr_tail<T, double, K, false>(h, (const double*)B.U, row_map(h), B.Q, hc, B.sc, st);
-    if (h->att_mode != 0) batch_att_pass<T, K>(h, st);
+        hipLaunchKernelGGL((batched::k_aprod2<T, Acc, K, false, NT>), dim3(grid), dim3(NT), lds,
+                           st, h->sv, (const Acc*)tb.U, tb.Q, h->wb, tb.gpart, hc, B.sc,
+                           batch_row_map(h));
+    hipLaunchKernelGGL((batched::k_glob_sum<Acc, K>), dim3(1), dim3(kBlock), 0, st,
+                       (const Acc*)tb.gpart, grid, tb.Q + h->sv.glob_base * K, B.sc);
+    launch_instr_tail<T, Acc, K, false>(h, (const Acc*)tb.U, batch_row_map(h), tb.Q, hc, B.sc, st);
+    if (h->att_mode != 0) batch_att_pass<T, Acc, K>(h, st);
 }
 
-// LDS of the fused pass of a K-tile (VP's values are FP64)
-template <int K>
-size_t batch_fused_lds(const lsqr_handle* h, int64_t* hc, int* ldsx)
-{
-    return fused_lds_plan(h, K, 8, hc, ldsx);
-}
-
-template <typename T, int K, bool LDSX, int AM>
-void batch_fused_as(lsqr_handle* h, const double* X3, int64_t hc, size_t lds, hipStream_t st)
+template <typename T, typename Acc, int K, bool LDSX, int AM>
+void batch_fused_as(lsqr_handle* h, const Acc* X3, int64_t hc, size_t lds, hipStream_t st)
 {
     auto& B = h->batch;
+    const TileBufs<Acc> tb = tile_bufs<Acc>(h);
     constexpr int NT = fused_nt<K, AM>();
     if (h->sv.star32)
-        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, LDSX, AM, true>),
-                           dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv, (const double*)B.VP,
-                           X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc, B.sc, row_map(h));
+        hipLaunchKernelGGL((batched::k_fused<T, Acc, K, NT, LDSX, AM, true>),
+                           dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv, (const Acc*)tb.VP,
+                           X3, tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc, batch_row_map(h));
     else
-        hipLaunchKernelGGL((batched::k_fused<T, double, K, NT, LDSX, AM, false>),
-                           dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv, (const double*)B.VP,
-                           X3, B.U, B.Q, h->wb, B.gpart, B.part1, hc, B.sc, row_map(h));
+        hipLaunchKernelGGL((batched::k_fused<T, Acc, K, NT, LDSX, AM, false>),
+                           dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv, (const Acc*)tb.VP,
+                           X3, tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc, batch_row_map(h));
 }
 
 // The fused pass of a k-tile; in fused mode 2 the attitude pre-pass
 // (k_att_dot on the tile's U, X3 and Scalars) runs first.
-template <typename T, int K>
+template <typename T, typename Acc, int K>
 void batch_fused(lsqr_handle* h, hipStream_t st)
 {
     auto& B = h->batch;
+    const TileBufs<Acc> tb = tile_bufs<Acc>(h);
     int64_t hc = 0;
     int ldsx = 0;
-    const size_t lds = batch_fused_lds<K>(h, &hc, &ldsx);
-    const bool pre = h->fused == 2;
-    const double* X3 = nullptr;
+    const size_t lds = fused_lds_plan(h, K, (int64_t)sizeof(Acc), &hc, &ldsx);
+    const bool pre = h->fused >= 2;  // fused mode 3 runs as 2 in k-tiles
+    const Acc* X3 = nullptr;
     if (h->att_il || pre) {
-        hipLaunchKernelGGL((batched::k_interleave_att<K>), dim3(h->nbc), dim3(kBlock), 0, st,
-                           (const double*)B.VP, h->sv.att_base, h->sv.n_dfa, B.X3);
-        X3 = B.X3;
+        hipLaunchKernelGGL((batched::k_interleave_att<Acc, K>), dim3(h->nbc), dim3(kBlock), 0, st,
+                           (const Acc*)tb.VP, (int64_t)K, h->sv.att_base, h->sv.n_dfa, tb.X3);
+        X3 = tb.X3;
     }
     if (pre) {
-        const int ks = att_sweep<K>(h);
+        const int ks = att_sweep<K>(h, (int64_t)sizeof(Acc));
         by_sweep<K>(ks, [&](auto KS) {
-            hipLaunchKernelGGL((k_att_dot<T, double, K, KS(), kAttBlock>), dim3(att_slices(h)),
-                               dim3(kAttBlock), (size_t)(kAxes * att_span(h) * 8 * ks), st,
-                               h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
+            hipLaunchKernelGGL((k_att_dot<T, Acc, K, KS(), kAttBlock>), dim3(att_slices(h)),
+                               dim3(kAttBlock), (size_t)(kAxes * att_span(h) * sizeof(Acc) * ks),
+                               st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
                                (const int64_t*)h->bstart, h->bwidth, h->att_g, h->sv.n_dfa, X3,
-                               B.U, (const Scalars*)B.sc);
+                               tb.U, (const Scalars*)B.sc);
         });
-        if (ldsx) batch_fused_as<T, K, true, kAttPre>(h, nullptr, hc, lds, st);
-        else batch_fused_as<T, K, false, kAttPre>(h, nullptr, hc, lds, st);
+        if (ldsx) batch_fused_as<T, Acc, K, true, kAttPre>(h, nullptr, hc, lds, st);
+        else batch_fused_as<T, Acc, K, false, kAttPre>(h, nullptr, hc, lds, st);
     } else if (ldsx) {
-        if (X3) batch_fused_as<T, K, true, kAttX3>(h, X3, hc, lds, st);
-        else batch_fused_as<T, K, true, kAttX>(h, X3, hc, lds, st);
+        if (X3) batch_fused_as<T, Acc, K, true, kAttX3>(h, X3, hc, lds, st);
+        else batch_fused_as<T, Acc, K, true, kAttX>(h, X3, hc, lds, st);
     } else {
-        if (X3) batch_fused_as<T, K, false, kAttX3>(h, X3, hc, lds, st);
-        else batch_fused_as<T, K, false, kAttX>(h, X3, hc, lds, st);
+        if (X3) batch_fused_as<T, Acc, K, false, kAttX3>(h, X3, hc, lds, st);
+        else batch_fused_as<T, Acc, K, false, kAttX>(h, X3, hc, lds, st);
     }
-    launch_instr_tail<T, double, K, false>(h, (const double*)B.U, row_map(h), B.Q, hc, B.sc, st);
+    launch_instr_tail<T, Acc, K, false>(h, (const Acc*)tb.U, batch_row_map(h), tb.Q, hc, B.sc, st);
 }
 
-template <typename T, int K>
+template <typename T, typename Acc, int K>
 void batch_iteration(lsqr_handle* h, hipStream_t st, hipEvent_t* ev)
 {
     auto& B = h->batch;
+    const TileBufs<Acc> tb = tile_bufs<Acc>(h);
     const int64_t n = h->sv.n;
     if (ev) (void)hipEventRecord(ev[0], st);
     if (use_fused(h)) {
-        batch_fused<T, K>(h, st);
+        batch_fused<T, Acc, K>(h, st);
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL((batched::k_scalar_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1,
                            batch_fused_grid<K>(h), B.sc);
         if (ev) (void)hipEventRecord(ev[2], st);
-        hipLaunchKernelGGL((batched::k_glob_sum<double, K>), dim3(1), dim3(kBlock), 0, st,
-                           (const double*)B.gpart, batch_fused_grid<K>(h), B.Q + h->sv.glob_base * K,
-                           B.sc);
-        batch_att_pass<T, K>(h, st);
+        hipLaunchKernelGGL((batched::k_glob_sum<Acc, K>), dim3(1), dim3(kBlock), 0, st,
+                           (const Acc*)tb.gpart, batch_fused_grid<K>(h),
+                           tb.Q + h->sv.glob_base * K, B.sc);
+        batch_att_pass<T, Acc, K>(h, st);
     } else {
-        hipLaunchKernelGGL((batched::k_aprod1<T, double, K>), dim3(h->nb1), dim3(kBlock), 0, st,
-                           h->sv, (const double*)B.VP, B.U, B.sc, B.part1, row_map(h));
+        hipLaunchKernelGGL((batched::k_aprod1<T, Acc, K>), dim3(h->nb1), dim3(kBlock), 0, st,
+                           h->sv, (const Acc*)tb.VP, tb.U, B.sc, B.part1, batch_row_map(h));
         if (ev) (void)hipEventRecord(ev[1], st);
         hipLaunchKernelGGL((batched::k_scalar_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1,
                            h->nb1, B.sc);
         if (ev) (void)hipEventRecord(ev[2], st);
-        batch_aprod2<T, K>(h, st);
+        batch_aprod2<T, Acc, K>(h, st);
     }
     if (ev) (void)hipEventRecord(ev[3], st);
-    hipLaunchKernelGGL((batched::k_col_a<double, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, B.Q,
-                       B.V, B.sc, B.partc);
+    hipLaunchKernelGGL((batched::k_col_a<Acc, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p,
+                       tb.Q, B.V, B.sc, B.partc);
     hipLaunchKernelGGL((batched::k_scalar_alpha<K>), dim3(1), dim3(kBlock), 0, st, B.partc, h->nbc,
                        B.sc);
-    hipLaunchKernelGGL((batched::k_col_b<double, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, B.V,
-                       B.W, B.Y, B.VP, B.sc, B.partdd, B.partxx);
+    hipLaunchKernelGGL((batched::k_col_b<Acc, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p,
+                       B.V, B.W, B.Y, tb.VP, B.sc, B.partdd, B.partxx);
     hipLaunchKernelGGL((batched::k_scalar_stop<K>), dim3(1), dim3(kBlock), 0, st, B.partdd,
                        B.partxx, h->nbc, B.sc);
     hipLaunchKernelGGL((batched::k_all_done<K>), dim3(1), dim3(kWave), 0, st, B.sc, B.flag);
 }
 
-// One tile of K right-hand sides: B_tile = B[:, j0:j0+K] (row stride ldb),
-// X_tile likewise. Per-RHS results in infos (host, may be NULL).
-template <typename T, int K>
-lsqr_status batch_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X, int64_t ldx,
-                       int32_t itn_limit, double atol, double btol, lsqr_info* infos,
-                       int max_chunks)
+// Uploads the controls of a tile's K scalar sets (rel_ar > 0: the relative
+// normal-equation stop of a refinement's inner solves, tests off).
+template <int K>
+lsqr_status batch_controls(lsqr_handle* h, int32_t itn_limit, double atol, double btol,
+                           double rel_ar = 0.0)
 {
-    auto& B = h->batch;
-    hipStream_t st = h->stream;
-    const int64_t m = h->sv.m, n = h->sv.n;
     Scalars host[8];
     memset(host, 0, sizeof host);
     for (int r = 0; r < K; ++r) {
@@ -1137,43 +1295,66 @@ lsqr_status batch_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X,
         host[r].btol = btol;
         host[r].ctol = h->conlim > 0.0 ? 1.0 / h->conlim : 0.0;
         host[r].itn_limit = itn_limit;
-        host[r].tests = h->tests;
+        host[r].tests = rel_ar > 0.0 ? 0 : h->tests;
+        host[r].rel_ar = rel_ar;
         host[r].inv_alpha = 1.0;
     }
-    HIP_TRY(hipMemcpyAsync(B.sc, host, K * sizeof(Scalars), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL((batched::k_copy_ssq<double, K>), dim3(h->nb1), dim3(kBlock), 0, st, m, Bm,
-                       ldb, B.U, B.part1, row_map(h));
+    HIP_TRY(hipMemcpyAsync(h->batch.sc, host, K * sizeof(Scalars), hipMemcpyHostToDevice,
+                           h->stream));
+    return LSQR_OK;
+}
+
+// Start of a tile's LSQR given U (placed by batch_row_map) and its sums of
+// squares in part1 (h->nb1 partials): beta_1, alpha_1 v_1 = Abar^T u_1, w, y.
+template <typename T, typename Acc, int K>
+lsqr_status batch_init(lsqr_handle* h)
+{
+    auto& B = h->batch;
+    const TileBufs<Acc> tb = tile_bufs<Acc>(h);
+    hipStream_t st = h->stream;
+    const int64_t n = h->sv.n;
     hipLaunchKernelGGL((batched::k_scalar_init_beta<K>), dim3(1), dim3(kBlock), 0, st, B.part1,
                        h->nb1, B.sc);
-    hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n * K, B.Q, 0.0);
+    hipLaunchKernelGGL((k_fill<Acc>), dim3(h->nbc), dim3(kBlock), 0, st, n * K, tb.Q, (Acc)0);
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, st, n * K, B.V, 0.0);
-    batch_aprod2<T, K>(h, st);
-    hipLaunchKernelGGL((batched::k_col_a<double, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p, B.Q,
-                       B.V, B.sc, B.partc);
+    batch_aprod2<T, Acc, K>(h, st);
+    hipLaunchKernelGGL((batched::k_col_a<Acc, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p,
+                       tb.Q, B.V, B.sc, B.partc);
     hipLaunchKernelGGL((batched::k_scalar_init_alpha<K>), dim3(1), dim3(kBlock), 0, st, B.partc,
                        h->nbc, B.sc);
-    hipLaunchKernelGGL((batched::k_col_init<double, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p,
-                       B.V, B.W, B.Y, B.VP, B.sc);
+    hipLaunchKernelGGL((batched::k_col_init<Acc, K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p,
+                       B.V, B.W, B.Y, tb.VP, B.sc);
     hipLaunchKernelGGL((batched::k_all_done<K>), dim3(1), dim3(kWave), 0, st, B.sc, B.flag);
     HIP_TRY(hipGetLastError());
+    return LSQR_OK;
+}
 
+// Runs the tile's iterations in graph-replayed chunks (one flag read per
+// chunk) until every RHS has stopped (or max_chunks chunks, if > 0); host
+// receives the K scalar sets at the end.
+template <typename T, typename Acc, int K>
+lsqr_status batch_run(lsqr_handle* h, int32_t itn_limit, int max_chunks, Scalars* host)
+{
+    const TileBufs<Acc> tb = tile_bufs<Acc>(h);
+    auto& B = h->batch;
+    hipStream_t st = h->stream;
     const int chunk = std::max(1, h->chunk);
     const bool graph = h->use_graph && !h->profile;
-    if (graph && (B.graph[K] == nullptr || B.graph_chunk[K] != chunk)) {
-        if (B.graph[K]) (void)hipGraphExecDestroy(B.graph[K]);
-        B.graph[K] = nullptr;
+    if (graph && (tb.graph[K] == nullptr || tb.graph_chunk[K] != chunk)) {
+        if (tb.graph[K]) (void)hipGraphExecDestroy(tb.graph[K]);
+        tb.graph[K] = nullptr;
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < chunk; ++k) batch_iteration<T, K>(h, st, nullptr);
+        for (int k = 0; k < chunk; ++k) batch_iteration<T, Acc, K>(h, st, nullptr);
         hipError_t e = hipStreamEndCapture(st, &g);
         if (e != hipSuccess) return fail(LSQR_E_HIP, "graph capture: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&B.graph[K], g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&tb.graph[K], g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
-            B.graph[K] = nullptr;
+            tb.graph[K] = nullptr;
             return fail(LSQR_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
         }
-        B.graph_chunk[K] = chunk;
+        tb.graph_chunk[K] = chunk;
     }
     if (h->profile && h->events.size() < (size_t)4 * chunk) {
         while (h->events.size() < (size_t)4 * chunk) {
@@ -1188,10 +1369,10 @@ lsqr_status batch_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X,
     int32_t itn_seen = 0;
     for (int c = 0; !done && itn_limit > 0 && (max_chunks <= 0 || c < max_chunks); ++c) {
         if (graph) {
-            HIP_TRY(hipGraphLaunch(B.graph[K], st));
+            HIP_TRY(hipGraphLaunch(tb.graph[K], st));
         } else {
             for (int k = 0; k < chunk; ++k)
-                batch_iteration<T, K>(h, st, h->profile ? &h->events[4 * k] : nullptr);
+                batch_iteration<T, Acc, K>(h, st, h->profile ? &h->events[4 * k] : nullptr);
             HIP_TRY(hipGetLastError());
         }
         HIP_TRY(hipMemcpyAsync(host, B.sc, K * sizeof(Scalars), hipMemcpyDeviceToHost, st));
@@ -1215,32 +1396,121 @@ lsqr_status batch_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X,
             return fail(LSQR_E_HIP, "batched LSQR made no progress (itn %d)", itn_max);
         itn_seen = itn_max;
     }
-    hipLaunchKernelGGL((batched::k_unprecond<K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p,
-                       (const double*)B.Y, X, ldx);
     HIP_TRY(hipMemcpyAsync(host, B.sc, K * sizeof(Scalars), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (infos) {
+    return LSQR_OK;
+}
+
+void fill_batch_info(lsqr_info& in, const Scalars& s, int32_t itn, int32_t outer, double bnorm)
+{
+    memset(&in, 0, sizeof in);
+    in.istop = s.istop;
+    in.itn = itn;
+    in.outer_steps = outer;
+    in.rnorm = s.rnorm;
+    in.arnorm = s.arnorm;
+    in.anorm = s.anorm;
+    in.acond = s.acond;
+    in.xnorm = s.xnorm;
+    in.bnorm = bnorm;
+}
+
+// One FP64 tile of K right-hand sides: B_tile = B[:, j0:j0+K] (row stride
+// ldb), X_tile likewise. Per-RHS results in infos (host, may be NULL).
+template <typename T, int K>
+lsqr_status batch_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X, int64_t ldx,
+                       int32_t itn_limit, double atol, double btol, lsqr_info* infos,
+                       int max_chunks)
+{
+    auto& B = h->batch;
+    hipStream_t st = h->stream;
+    const int64_t m = h->sv.m, n = h->sv.n;
+    LSQR_TRY(batch_controls<K>(h, itn_limit, atol, btol));
+    hipLaunchKernelGGL((batched::k_copy_ssq<double, K>), dim3(h->nb1), dim3(kBlock), 0, st, m, Bm,
+                       ldb, B.U, B.part1, batch_row_map(h));
+    LSQR_TRY((batch_init<T, double, K>(h)));
+    Scalars host[8];
+    LSQR_TRY((batch_run<T, double, K>(h, itn_limit, max_chunks, host)));
+    hipLaunchKernelGGL((batched::k_unprecond<K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p,
+                       (const double*)B.Y, X, ldx);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    if (infos)
+        for (int r = 0; r < K; ++r) fill_batch_info(infos[r], host[r], host[r].itn, 0, host[r].bnorm);
+    return LSQR_OK;
+}
+
+// One tile of the refined form: K right-hand sides of an FP32-stored system,
+// each with its own FP64 refinement loop (as lsqr_solve_refined) around FP32
+// inner LSQR solves that advance together. Outer step: for every RHS still
+// refining, r = b - A x in FP64 (stored as the FP32 start vector), then the
+// inner tile solve (relative normal-equation stop atol, itn_limit), then
+// x += p .* y. A RHS stops refining when ||d||_inf <= outer_tol ||x||_inf,
+// when its residual is zero or orthogonal to range(A), or after outer_limit
+// steps; from then on it is masked (zero start vector: frozen at once) and
+// its x no longer changes.
+template <typename T, int K>
+lsqr_status batch_refined_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X,
+                               int64_t ldx, int32_t itn_limit, double atol, int32_t outer_limit,
+                               lsqr_info* infos)
+{
+    auto& B = h->batch;
+    hipStream_t st = h->stream;
+    const int64_t m = h->sv.m, n = h->sv.n;
+    hipLaunchKernelGGL((batched::k_zero_cols<K>), dim3(h->nbc), dim3(kBlock), 0, st, n, X, ldx);
+    uint32_t live = (1u << K) - 1u;
+    int32_t total_itn[8] = {}, steps[8] = {};
+    double bnorm[8] = {};
+    Scalars last[8], host[8];
+    memset(last, 0, sizeof last);
+    for (int outer = 1; outer <= outer_limit && live; ++outer) {
+        LSQR_TRY(batch_controls<K>(h, itn_limit, 0.0, 0.0, std::max(atol, 1e-300)));
+        // FP64 residual of the full problem of every live RHS
+        hipLaunchKernelGGL((batched::k_interleave_att<double, K>), dim3(h->nbc), dim3(kBlock), 0,
+                           st, (const double*)X, ldx, h->sv.att_base, h->sv.n_dfa, B.X3);
+        hipLaunchKernelGGL((batched::k_resid<T, float, K>), dim3(h->nb1), dim3(kBlock), 0, st,
+                           h->sv, (const double*)X, ldx, (const double*)B.X3, Bm, ldb, B.U32,
+                           B.part1, batch_row_map(h), live);
+        LSQR_TRY((batch_init<T, float, K>(h)));
+        LSQR_TRY((batch_run<T, float, K>(h, itn_limit, 0, host)));
+        hipLaunchKernelGGL((batched::k_refine_update<K>), dim3(h->nbc), dim3(kBlock), 0, st, n,
+                           h->p, (const double*)B.Y, X, ldx, live, B.partdd, B.partxx);
+        hipLaunchKernelGGL((batched::k_refine_norms<K>), dim3(1), dim3(kBlock), 0, st,
+                           (const double*)B.partdd, (const double*)B.partxx, h->nbc, B.sc);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(host, B.sc, K * sizeof(Scalars), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
         for (int r = 0; r < K; ++r) {
-            lsqr_info& in = infos[r];
-            memset(&in, 0, sizeof in);
-            in.istop = host[r].istop;
-            in.itn = host[r].itn;
-            in.rnorm = host[r].rnorm;
-            in.arnorm = host[r].arnorm;
-            in.anorm = host[r].anorm;
-            in.acond = host[r].acond;
-            in.xnorm = host[r].xnorm;
-            in.bnorm = host[r].bnorm;
+            if (!((live >> r) & 1u)) continue;
+            if (outer == 1) bnorm[r] = host[r].bnorm;
+            steps[r] = outer;
+            total_itn[r] += host[r].itn;
+            last[r] = host[r];
+            // residual zero or orthogonal to range(A) (stopped at the start),
+            // or a correction small against the solution
+            if (host[r].itn == 0 || host[r].dmax <= h->outer_tol * host[r].xmax)
+                live &= ~(1u << r);
         }
     }
+    if (infos)
+        for (int r = 0; r < K; ++r) fill_batch_info(infos[r], last[r], total_itn[r], steps[r], bnorm[r]);
     return LSQR_OK;
 }
 
 template <typename T>
-lsqr_status batch_tile_k(lsqr_handle* h, int K, const double* Bm, int64_t ldb, double* X,
-                         int64_t ldx, int32_t itn_limit, double atol, double btol,
-                         lsqr_info* infos, int max_chunks)
+lsqr_status batch_tile_k(lsqr_handle* h, bool refined, int K, const double* Bm, int64_t ldb,
+                         double* X, int64_t ldx, int32_t itn_limit, double atol, double btol,
+                         int32_t outer_limit, lsqr_info* infos, int max_chunks)
 {
+    if (refined) {
+        switch (K) {
+        case 1: return batch_refined_tile<T, 1>(h, Bm, ldb, X, ldx, itn_limit, atol, outer_limit, infos);
+        case 2: return batch_refined_tile<T, 2>(h, Bm, ldb, X, ldx, itn_limit, atol, outer_limit, infos);
+        case 4: return batch_refined_tile<T, 4>(h, Bm, ldb, X, ldx, itn_limit, atol, outer_limit, infos);
+        case 8: return batch_refined_tile<T, 8>(h, Bm, ldb, X, ldx, itn_limit, atol, outer_limit, infos);
+        default: return fail(LSQR_E_INVALID, "k-tile must be 1, 2, 4 or 8");
+        }
+    }
     switch (K) {
     case 1: return batch_tile<T, 1>(h, Bm, ldb, X, ldx, itn_limit, atol, btol, infos, max_chunks);
     case 2: return batch_tile<T, 2>(h, Bm, ldb, X, ldx, itn_limit, atol, btol, infos, max_chunks);
@@ -1250,35 +1520,64 @@ lsqr_status batch_tile_k(lsqr_handle* h, int K, const double* Bm, int64_t ldb, d
     }
 }
 
+// A few profiled iterations of one tile of K right-hand sides in precision
+// Acc (the FP32 inner solve of the refined form, or FP64), from start vector
+// B[:, 0:K]: milliseconds per RHS-iteration.
+template <typename T, typename Acc, int K>
+lsqr_status batch_probe(lsqr_handle* h, const double* Bm, int64_t ldb, double* ms)
+{
+    auto& B = h->batch;
+    const TileBufs<Acc> tb = tile_bufs<Acc>(h);
+    LSQR_TRY(batch_controls<K>(h, 1 << 20, 0.0, 0.0));
+    hipLaunchKernelGGL((batched::k_copy_ssq<Acc, K>), dim3(h->nb1), dim3(kBlock), 0, h->stream,
+                       h->sv.m, Bm, ldb, tb.U, B.part1, batch_row_map(h));
+    LSQR_TRY((batch_init<T, Acc, K>(h)));
+    Scalars host[8];
+    h->ms1 = h->ms2 = h->ms_pre = 0.0;
+    h->n1 = h->n2 = 0;
+    LSQR_TRY((batch_run<T, Acc, K>(h, 1 << 20, 1, host)));
+    *ms = (h->ms1 + h->ms2) / std::max<int64_t>(1, h->n1) / K;
+    return LSQR_OK;
+}
+
 // Autotuner: times a few profiled iterations of the first k-tile for every
-// candidate K <= k and keeps the K with the lowest time per RHS-iteration.
+// candidate K <= min(k, 8) (in the precision the solve will run) and keeps
+// the K with the lowest time per RHS-iteration; the choice is kept per
+// precision and per min(k, 8) until an option that selects kernels changes.
 template <typename T>
-lsqr_status batch_autotune(lsqr_handle* h, const double* Bm, int64_t ldb, int32_t k)
+lsqr_status batch_autotune(lsqr_handle* h, bool refined, const double* Bm, int64_t ldb, int32_t k,
+                           int* out)
 {
     auto& B = h->batch;
     const int saved_profile = h->profile, saved_chunk = h->chunk, saved_tests = h->tests;
     const double saved[5] = {h->ms1, h->ms2, (double)h->n1, (double)h->n2, h->ms_pre};
-    double* Xs = nullptr;
-    LSQR_TRY(dalloc(&Xs, h->sv.n * 8));
     int best = 1;
     double best_ms = 1e300;
     lsqr_status rc = LSQR_OK;
+    memset(B.tuned_ms, 0, sizeof B.tuned_ms);
+    h->profile = 1;
+    h->tests = 0;
+    h->chunk = 3;
     for (int K = 1; K <= 8 && K <= k; K *= 2) {
-        h->profile = 1;
-        h->tests = 0;
-        h->chunk = 3;
-        h->ms1 = h->ms2 = h->ms_pre = 0.0;
-        h->n1 = h->n2 = 0;
-        rc = batch_tile_k<T>(h, K, Bm, ldb, Xs, K, 1 << 20, 0.0, 0.0, nullptr, 1);
+        double ms = 0.0;
+        auto probe = [&](auto KK) {
+            constexpr int Kc = decltype(KK)::value;
+            return refined ? batch_probe<T, float, Kc>(h, Bm, ldb, &ms)
+                           : batch_probe<T, double, Kc>(h, Bm, ldb, &ms);
+        };
+        switch (K) {
+        case 1: rc = probe(std::integral_constant<int, 1>()); break;
+        case 2: rc = probe(std::integral_constant<int, 2>()); break;
+        case 4: rc = probe(std::integral_constant<int, 4>()); break;
+        default: rc = probe(std::integral_constant<int, 8>()); break;
+        }
         if (rc != LSQR_OK) break;
-        const double per_iter = (h->ms1 + h->ms2) / std::max<int64_t>(1, h->n1);
-        B.tuned_ms[K] = per_iter / K;
-        if (B.tuned_ms[K] < best_ms) {
-            best_ms = B.tuned_ms[K];
+        B.tuned_ms[K] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
             best = K;
         }
     }
-    dfree(Xs);
     h->profile = saved_profile;
     h->chunk = saved_chunk;
     h->tests = saved_tests;
@@ -1288,21 +1587,35 @@ lsqr_status batch_autotune(lsqr_handle* h, const double* Bm, int64_t ldb, int32_
     h->n2 = (int64_t)saved[3];
     h->ms_pre = saved[4];
     if (rc != LSQR_OK) return rc;
-    B.tuned_k = best;
+    *out = best;
     return LSQR_OK;
 }
 
-template <typename T>
-lsqr_status solve_batched(lsqr_handle* h, const double* Bm, double* X, int32_t k,
-                          int32_t itn_limit, double atol, double btol, lsqr_info* infos)
+inline int log2_cap(int32_t k)
 {
+    return k >= 8 ? 3 : (k >= 4 ? 2 : (k >= 2 ? 1 : 0));
+}
+
+template <typename T>
+lsqr_status solve_batched(lsqr_handle* h, bool refined, const double* Bm, double* X, int32_t k,
+                          int32_t itn_limit, double atol, double btol, int32_t outer_limit,
+                          lsqr_info* infos)
+{
+    auto& B = h->batch;
     int K = h->ktile;
     if (K == 0) {
-        LSQR_TRY(batch_alloc(h, std::min(8, k >= 8 ? 8 : (k >= 4 ? 4 : (k >= 2 ? 2 : 1)))));
-        if (h->batch.tuned_k == 0) LSQR_TRY(batch_autotune<T>(h, Bm, k, k));
-        K = h->batch.tuned_k;
+        const int cap = log2_cap(k);
+        int& slot = B.tuned_k[refined ? 1 : 0][cap];
+        if (slot == 0) {
+            LSQR_TRY(batch_alloc(h, 1 << cap, refined));
+            int best = 1;
+            LSQR_TRY(batch_autotune<T>(h, refined, Bm, k, k, &best));
+            slot = best;
+        }
+        K = slot;
+        B.last_tuned = K;
     }
-    LSQR_TRY(batch_alloc(h, K));
+    LSQR_TRY(batch_alloc(h, K, refined));
     if (h->profile) {
         h->ms1 = h->ms2 = h->ms_pre = 0.0;
         h->n1 = h->n2 = 0;
@@ -1311,8 +1624,8 @@ lsqr_status solve_batched(lsqr_handle* h, const double* Bm, double* X, int32_t k
     while (j0 < k) {
         int kt = K;
         while (kt > k - j0) kt /= 2;  // ragged end: 4, 2, 1
-        LSQR_TRY(batch_tile_k<T>(h, kt, Bm + j0, k, X + j0, k, itn_limit, atol, btol,
-                                 infos ? infos + j0 : nullptr, 0));
+        LSQR_TRY(batch_tile_k<T>(h, refined, kt, Bm + j0, k, X + j0, k, itn_limit, atol, btol,
+                                 outer_limit, infos ? infos + j0 : nullptr, 0));
         j0 += kt;
     }
     return LSQR_OK;
@@ -1602,9 +1915,10 @@ lsqr_status lsqr_destroy(lsqr_handle* h)
     dfree(h->invperm);
     dfree(h->bstart);
     dfree(h->S2);
-    dfree(h->us_raw);
     dfree(h->var);
     dfree(h->x3_raw);
+    dfree(h->x3_raw32);
+    dfree(h->gpart_raw32);
     if (h->att_sorted) (void)hipFree(h->att_sorted);
     h->att_sorted = nullptr;
     dfree(h->p);
@@ -1663,8 +1977,9 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
     }
     case LSQR_OPT_ATT_INTERLEAVE:
     case LSQR_OPT_FUSED: {
-        if (option == LSQR_OPT_FUSED && !(value == 0.0 || value == 1.0 || value == 2.0))
-            return fail(LSQR_E_INVALID, "fused mode must be 0, 1 or 2");
+        if (option == LSQR_OPT_FUSED &&
+            !(value == 0.0 || value == 1.0 || value == 2.0 || value == 3.0))
+            return fail(LSQR_E_INVALID, "fused mode must be 0, 1, 2 or 3");
         const int v = option == LSQR_OPT_FUSED ? (int)value : (value != 0.0 ? 1 : 0);
         int& slot = option == LSQR_OPT_FUSED ? h->fused : h->att_il;
         if (slot != v) {
@@ -1712,6 +2027,12 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         }
         if (v && !h->compact) h->compact_tried = 0;
         h->compact = v;
+        return LSQR_OK;
+    }
+    case LSQR_OPT_PIPELINE: {
+        const int v = value != 0.0 ? 1 : 0;
+        if (h->pipe != v) drop_graphs(h);
+        h->pipe = v;
         return LSQR_OK;
     }
     case LSQR_OPT_OUTER_TOL:
@@ -1780,23 +2101,50 @@ lsqr_status lsqr_aprod2(lsqr_handle* h, double* x, const double* y)
     if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
     LSQR_TRY(ensure_att(h));
     const int64_t hc = instr_hcols(h, 1);
-    // y in row order for the star-order pass; a copy in bucket order for the
-    // attitude pass
-    // (only where the bucket order exists: attitude section present, mode 1)
-    const double* yb = nullptr;
-    if (att_pass_on(h)) {
-        if (!h->us_raw) LSQR_TRY(dalloc(&h->us_raw, h->sv.m));
-        hipLaunchKernelGGL((k_gather_perm<double>),
-                           dim3(std::min<int64_t>(cdiv(h->sv.m, kBlock), 65536)), dim3(kBlock), 0,
-                           h->user_stream, y, (const int32_t*)h->perm, h->sv.m, h->us_raw);
-        yb = h->us_raw;
-    }
+    // y in row order: the attitude pass (where the bucket order exists:
+    // attitude section present, mode 1) reads it through the permutation
+    const int32_t* gperm = att_pass_on(h) ? (const int32_t*)h->perm : nullptr;
     if (h->value_type == LSQR_F64)
         launch_aprod2<double, double>(h, y, nullptr, x, h->gpart_raw, hc, nullptr,
-                                      h->user_stream, yb);
+                                      h->user_stream, y, gperm);
     else
         launch_aprod2<float, double>(h, y, nullptr, x, h->gpart_raw, hc, nullptr,
-                                     h->user_stream, yb);
+                                     h->user_stream, y, gperm);
+    HIP_TRY(hipGetLastError());
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_aprod1_f32(lsqr_handle* h, const float* x, float* y)
+{
+    LSQR_TRY(check_handle(h));
+    if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
+    if (h->value_type != LSQR_F32)
+        return fail(LSQR_E_STATE, "lsqr_aprod1_f32 needs an LSQR_F32 system");
+    const float* x3 = nullptr;
+    if (h->att_il && h->sv.natt > 0 && !h->generic) {
+        if (!h->x3_raw32) LSQR_TRY(dalloc(&h->x3_raw32, (int64_t)kAxes * h->sv.n_dfa));
+        launch_interleave_att<float>(h, x, h->x3_raw32, nullptr, h->user_stream);
+        x3 = h->x3_raw32;
+    }
+    launch_aprod1<float, float, float, float, A1_ACCUM>(h, x, y, nullptr, nullptr, nullptr,
+                                                        h->user_stream, nullptr, x3);
+    HIP_TRY(hipGetLastError());
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_aprod2_f32(lsqr_handle* h, float* x, const float* y)
+{
+    LSQR_TRY(check_handle(h));
+    if (!x || !y) return fail(LSQR_E_INVALID, "null vector");
+    if (h->value_type != LSQR_F32)
+        return fail(LSQR_E_STATE, "lsqr_aprod2_f32 needs an LSQR_F32 system");
+    LSQR_TRY(ensure_att(h));
+    if (!h->gpart_raw32)
+        LSQR_TRY(dalloc(&h->gpart_raw32, std::max<int64_t>(h->nb2, (int64_t)h->nba * kGlobMax)));
+    const int64_t hc = instr_hcols(h, 1);
+    const int32_t* gperm = att_pass_on(h) ? (const int32_t*)h->perm : nullptr;
+    launch_aprod2<float, float>(h, y, nullptr, x, h->gpart_raw32, hc, nullptr, h->user_stream, y,
+                                gperm);
     HIP_TRY(hipGetLastError());
     return LSQR_OK;
 }
@@ -1929,16 +2277,41 @@ lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32
     LSQR_TRY(ensure_att(h));
     LSQR_TRY(ensure_compact(h));
     if (h->value_type == LSQR_F64)
-        LSQR_TRY(solve_batched<double>(h, B, X, k, itn_limit, atol, btol, infos));
+        LSQR_TRY(solve_batched<double>(h, false, B, X, k, itn_limit, atol, btol, 0, infos));
     else
-        LSQR_TRY(solve_batched<float>(h, B, X, k, itn_limit, atol, btol, infos));
+        LSQR_TRY(solve_batched<float>(h, false, B, X, k, itn_limit, atol, btol, 0, infos));
+    return LSQR_OK;
+}
+
+lsqr_status lsqr_solve_batched_refined(lsqr_handle* h, const double* B, double* X, int32_t k,
+                                       int32_t itn_limit, double atol, double btol,
+                                       int32_t outer_limit, lsqr_info* infos)
+{
+    LSQR_TRY(check_handle(h));
+    if (!B || !X) return fail(LSQR_E_INVALID, "null matrix");
+    if (h->value_type != LSQR_F32)
+        return fail(LSQR_E_STATE, "lsqr_solve_batched_refined needs an LSQR_F32 system");
+    if (k < 1 || k > 4096) return fail(LSQR_E_INVALID, "k must be in [1, 4096]");
+    if (itn_limit < 0 || outer_limit < 1)
+        return fail(LSQR_E_INVALID, "itn_limit >= 0 and outer_limit >= 1 required");
+    if (!(atol >= 0.0) || !(btol >= 0.0)) return fail(LSQR_E_INVALID, "atol, btol must be >= 0");
+    if (h->generic)
+        return fail(LSQR_E_UNSUPPORTED,
+                    "batched solves are built for the 5 + 3x4 + 6 + 1 row layout only");
+    if (h->nc > 0)
+        return fail(LSQR_E_UNSUPPORTED, "batched solves are built without constraint rows");
+    HIP_TRY(hipStreamSynchronize(h->user_stream));
+    h->var_valid = 0;
+    LSQR_TRY(ensure_att(h));
+    LSQR_TRY(ensure_compact(h));
+    LSQR_TRY(solve_batched<float>(h, true, B, X, k, itn_limit, atol, btol, outer_limit, infos));
     return LSQR_OK;
 }
 
 lsqr_status lsqr_batch_tuning(lsqr_handle* h, int32_t* k_tile, double* ms_per_rhs_iter)
 {
     if (!h) return fail(LSQR_E_INVALID, "null handle");
-    if (k_tile) *k_tile = h->batch.tuned_k;
+    if (k_tile) *k_tile = h->batch.last_tuned;
     if (ms_per_rhs_iter)
         for (int K = 1, i = 0; K <= 8; K *= 2, ++i) ms_per_rhs_iter[i] = h->batch.tuned_ms[K];
     return LSQR_OK;

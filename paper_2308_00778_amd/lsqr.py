@@ -25,13 +25,14 @@ LSQR_F32 = 1
 OPTIONS = {"conlim": 1, "tests": 2, "chunk": 3, "graph": 4, "profile": 5, "outer_tol": 6,
            "att_mode": 7, "astro_scan": 8, "ktile": 9, "att_buckets": 10,
            "att_interleave": 11, "fused": 12, "variance": 13, "compact_index": 14,
-           "att_rhs": 15}
+           "att_rhs": 15, "pipeline": 16}
 
 SYMBOLS = ("lsqr_create", "lsqr_destroy", "lsqr_set_option", "lsqr_aprod1", "lsqr_aprod2",
-           "lsqr_aprod1_noalloc",
+           "lsqr_aprod1_noalloc", "lsqr_aprod1_f32", "lsqr_aprod2_f32",
            "lsqr_get_precond", "lsqr_get_variance", "lsqr_num_cols", "lsqr_solve",
            "lsqr_solve_refined",
-           "lsqr_solve_batched", "lsqr_batch_tuning", "lsqr_kernel_times", "lsqr_pass_times",
+           "lsqr_solve_batched", "lsqr_solve_batched_refined", "lsqr_batch_tuning",
+           "lsqr_kernel_times", "lsqr_pass_times",
            "lsqr_last_error")
 
 
@@ -96,12 +97,16 @@ def load_library(path: str = LIB_PATH):
         "lsqr_aprod1": ([H, P, P], I32),
         "lsqr_aprod2": ([H, P, P], I32),
         "lsqr_aprod1_noalloc": ([H, P, P], I32),
+        "lsqr_aprod1_f32": ([H, P, P], I32),
+        "lsqr_aprod2_f32": ([H, P, P], I32),
         "lsqr_get_precond": ([H, P], I32),
         "lsqr_get_variance": ([H, P], I32),
         "lsqr_num_cols": ([H, ctypes.POINTER(I64)], I32),
         "lsqr_solve": ([H, P, P, I32, F64, F64, ctypes.POINTER(_Info)], I32),
         "lsqr_solve_refined": ([H, P, P, I32, F64, F64, I32, ctypes.POINTER(_Info)], I32),
         "lsqr_solve_batched": ([H, P, P, I32, I32, F64, F64, ctypes.POINTER(_Info)], I32),
+        "lsqr_solve_batched_refined": ([H, P, P, I32, I32, F64, F64, I32,
+                                        ctypes.POINTER(_Info)], I32),
         "lsqr_batch_tuning": ([H, ctypes.POINTER(I32), ctypes.POINTER(F64)], I32),
         "lsqr_kernel_times": ([H, ctypes.POINTER(F64), ctypes.POINTER(I64),
                                ctypes.POINTER(F64), ctypes.POINTER(I64)], I32),
@@ -249,6 +254,22 @@ class LsqrSystem:
                                         _dev_ptr(y, torch.float64, (self.m,), "y")))
         return y
 
+    def aprod1_f32(self, x, y):
+        """y += A x with FP32 vectors and accumulation (FP32-stored systems)."""
+        import torch
+
+        _check(_lib.lsqr_aprod1_f32(self._h, _dev_ptr(x, torch.float32, (self.n,), "x"),
+                                    _dev_ptr(y, torch.float32, (self.m,), "y")))
+        return y
+
+    def aprod2_f32(self, x, y):
+        """x += A^T y with FP32 vectors and accumulation (FP32-stored systems)."""
+        import torch
+
+        _check(_lib.lsqr_aprod2_f32(self._h, _dev_ptr(x, torch.float32, (self.n,), "x"),
+                                    _dev_ptr(y, torch.float32, (self.m,), "y")))
+        return x
+
     def aprod2(self, x, y):
         """x += A^T y (in place, asynchronous on the handle's stream)."""
         import torch
@@ -310,6 +331,23 @@ class LsqrSystem:
         _check(_lib.lsqr_solve_batched(self._h, _dev_ptr(B, torch.float64, (self.m, k), "B"),
                                        _dev_ptr(X, torch.float64, (self.n, k), "X"), k,
                                        int(itn_limit), float(atol), float(btol), infos))
+        return X, [self._info(ci) for ci in infos]
+
+    def solve_batched_refined(self, B, itn_limit: int = 200, atol: float = 1e-6,
+                              btol: float = 1e-6, outer_limit: int = 10, X=None):
+        """FP32-stored system: B [m, k] float64; FP64 refinement per RHS around
+        FP32 inner solves advancing together. Returns X [n, k] and k Info."""
+        import torch
+
+        if B.dim() != 2 or B.shape[0] != self.m:
+            raise ValueError(f"B must be [m, k] with m={self.m}")
+        k = int(B.shape[1])
+        X = torch.empty((self.n, k), dtype=torch.float64, device=self.device) if X is None else X
+        infos = (_Info * k)()
+        _check(_lib.lsqr_solve_batched_refined(
+            self._h, _dev_ptr(B, torch.float64, (self.m, k), "B"),
+            _dev_ptr(X, torch.float64, (self.n, k), "X"), k, int(itn_limit), float(atol),
+            float(btol), int(outer_limit), infos))
         return X, [self._info(ci) for ci in infos]
 
     def batch_tuning(self):

@@ -186,3 +186,79 @@ def test_batched_attitude_sweeps(torch_cuda, wide_att, geometry, ktile):
         assert infos[j].itn == itn
         assert rel_inf(Xh[:, j], x_ref) <= 1e-10, j
         assert abs(infos[j].rnorm - i_ref.rnorm) <= 1e-8 * i_ref.rnorm
+
+
+# The refined form of the batched solve (lsqr_solve_batched_refined) on a
+# system with the features of the largest workload: FP32-stored values,
+# uneven stars (50..150 observations), 30,000 instrumental columns (beyond
+# one LDS histogram: tail windows), 150 attitude buckets, no compact index
+# copies, k = 4. Among the right-hand sides: a consistent one (b = a column
+# of A, stops refining early), a zero one (x = 0, frozen from the start) and
+# noisy ones. Every x[:, j] must match the converged FP64 oracle to 1e-10
+# (the FP32-rounded values define the system) and the single refined solve.
+@pytest.fixture(scope="module")
+def f32_c4like():
+    spec = synth.tiny(seed=41, n_stars=500, obs=(50, 150), n_dfa=1200, n_instr_cols=30000,
+                      value_dtype="f32", astro_scale=(-2.0, 2.0))
+    S = synth.make_system(spec)
+    o = oracle.OracleSystem.from_synth(S)
+    xt = synth.x_true(spec)
+    B = np.stack([o.aprod1(xt, synth.noise(spec, S.m, rhs=j)) for j in range(4)], axis=1)
+    e = np.zeros(o.n)
+    e[5 * 17 + 2] = 1.0
+    B[:, 1] = o.aprod1(e)   # consistent: b = one column of A
+    B[:, 2] = 0.0           # zero right-hand side
+    refs = [o.lsqr(B[:, j], 600, atol=1e-14, btol=1e-14, conlim=0.0) for j in range(4)]
+    return S, o, B, refs
+
+
+@pytest.mark.parametrize("ktile", [4, 2, 1, 0])
+def test_batched_refined_matches_fp64_oracle(torch_cuda, f32_c4like, ktile):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LsqrSystem
+
+    S, o, B, refs = f32_c4like
+    say(f"batched refined: FP32 m={S.m} n={o.n} k=4 ktile={ktile}, 150 buckets, "
+        f"30000 instrumental columns, no compact indices")
+    g = LsqrSystem.from_host(S, "cuda:0")
+    g.set_option("att_buckets", 150)
+    g.set_option("compact_index", 0)
+    g.set_option("ktile", ktile)
+    Bd = torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    X, infos = g.solve_batched_refined(Bd, 200, atol=1e-6, btol=1e-6, outer_limit=8)
+    Xh = X.cpu().numpy()
+    singles = [g.solve_refined(torch.from_numpy(np.ascontiguousarray(B[:, j])).cuda(), 200,
+                               atol=1e-6, btol=1e-6, outer_limit=8) for j in range(4)]
+    tuned = g.batch_tuning()["k_tile"]
+    g.close()
+    for j in range(4):
+        x_ref, i_ref = refs[j]
+        xs, inf = singles[j]
+        xs = xs.cpu().numpy()
+        say(f"  rhs {j}: outer {infos[j].outer_steps} inner {infos[j].itn} "
+            f"(single {inf.outer_steps}/{inf.itn})")
+        if j == 2:  # b = 0: x = 0, no iteration
+            assert infos[j].itn == 0 and infos[j].istop == 0 and not np.any(Xh[:, j])
+            continue
+        assert rel_inf(Xh[:, j], x_ref) <= 1e-10, j
+        assert rel_inf(Xh[:, j], xs) <= 1e-10, j
+        assert infos[j].outer_steps == inf.outer_steps, j
+        assert abs(infos[j].itn - inf.itn) <= infos[j].outer_steps, j
+        # ||b|| of the first inner solve's FP32 start vector
+        assert infos[j].bnorm == pytest.approx(inf.bnorm, rel=1e-12)
+        assert infos[j].bnorm == pytest.approx(float(np.linalg.norm(B[:, j])), rel=1e-6)
+    if ktile == 0:
+        assert tuned in (1, 2, 4)
+
+
+def test_batched_refined_needs_fp32_values(torch_cuda, c0):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LSQR_E_STATE, LsqrError, LsqrSystem
+
+    S, o, B = c0
+    say("batched refined on an FP64 system: LSQR_E_STATE")
+    g = LsqrSystem.from_host(S, "cuda:0")
+    with pytest.raises(LsqrError) as ei:
+        g.solve_batched_refined(torch.from_numpy(np.ascontiguousarray(B)).cuda(), 10)
+    g.close()
+    assert ei.value.status == LSQR_E_STATE

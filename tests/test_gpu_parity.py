@@ -148,6 +148,58 @@ def test_aprod2_parity(torch_cuda, name, variant):
     assert np.all(np.abs(got - want) <= c * EPS * bound + 1e-300)
 
 
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+# FP32 operators (FP32-stored values, FP32 vectors and accumulation) against
+# the oracle on the same float values widened: each element within
+# c * eps32 * sum |terms| (c as for the FP64 operators).
+@pytest.mark.parametrize("variant", [(1, 1), (0, 0)], ids=["bucket_pass", "atomics_plain"])
+@pytest.mark.parametrize("name", ["instr_12k_f32", "wide_att_f32"])
+def test_aprod_f32_parity(torch_cuda, name, variant):
+    torch = torch_cuda
+    S, o = system(name)
+    say(f"FP32 operators: {name} m={S.m} n={o.n} att_mode={variant[0]} "
+        f"interleave={variant[1]}")
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal(o.n).astype(np.float32)
+    y = rng.standard_normal(o.m).astype(np.float32)
+    y0 = rng.standard_normal(o.m).astype(np.float32)
+    x0 = rng.standard_normal(o.n).astype(np.float32)
+    want1 = o.aprod1(x.astype(np.float64), y0.astype(np.float64))
+    bound1 = abs_system(S).aprod1(np.abs(x.astype(np.float64)), np.abs(y0.astype(np.float64)))
+    want2 = o.aprod2(y.astype(np.float64), x0.astype(np.float64))
+    bound2 = abs_system(S).aprod2(np.abs(y.astype(np.float64)), np.abs(x0.astype(np.float64)))
+    g = gpu_system(torch, S)
+    g.set_option("att_mode", variant[0])
+    g.set_option("att_interleave", variant[1])
+    g.set_option("att_buckets", BUCKETS.get(name, 5))
+    yd = torch.from_numpy(y0).cuda()
+    g.aprod1_f32(torch.from_numpy(x).cuda(), yd)
+    xd = torch.from_numpy(x0).cuda()
+    g.aprod2_f32(xd, torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    got1, got2 = yd.cpu().numpy().astype(np.float64), xd.cpu().numpy().astype(np.float64)
+    g.close()
+    assert np.all(np.abs(got1 - want1) <= 32 * EPS32 * bound1 + 1e-30)
+    c = 2.0 * np.sqrt(S.m) + 32
+    assert np.all(np.abs(got2 - want2) <= c * EPS32 * bound2 + 1e-30)
+
+
+def test_aprod_f32_needs_fp32_values(torch_cuda):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LSQR_E_STATE, LsqrError
+
+    S, o = system("few_rows")
+    say("FP32 operators on an FP64 system: LSQR_E_STATE")
+    g = gpu_system(torch, S)
+    with pytest.raises(LsqrError) as ei:
+        g.aprod1_f32(torch.zeros(o.n, dtype=torch.float32, device="cuda"),
+                     torch.zeros(o.m, dtype=torch.float32, device="cuda"))
+    g.close()
+    assert ei.value.status == LSQR_E_STATE
+
+
 @pytest.mark.parametrize("name", ["c0", "ragged", "wide_instr", "huge_instr"])
 def test_precond_parity(torch_cuda, name):
     torch = torch_cuda
@@ -192,7 +244,7 @@ def test_solve_without_interleaved_attitude(torch_cuda, name, itn):
 # The default iteration (fused mode 2: attitude pre-pass in bucket order, then
 # the fused pass) against fused mode 1 (attitude dot product inside the fused
 # pass) and separate aprod1/aprod2 launches (0): all must match the oracle.
-@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("fused", [3, 1, 0])
 @pytest.mark.parametrize("name,itn", [("c0", 60), ("ragged", 60), ("one_star", 15),
                                        ("few_rows", 15), ("wide_instr", 40),
                                        ("instr_12k", 30), ("wide_att_f32", 30)])
@@ -202,7 +254,7 @@ def test_solve_other_fused_modes(torch_cuda, name, itn, fused):
 
 # The fused passes read compact copies of the star and instrumental indices
 # by default; the caller's int64/int32 arrays without them.
-@pytest.mark.parametrize("fused", [2, 1])
+@pytest.mark.parametrize("fused", [2, 3, 1])
 @pytest.mark.parametrize("name,itn", [("c0", 60), ("huge_instr", 30), ("wide_att_f32", 30)])
 def test_solve_without_compact_index(torch_cuda, name, itn, fused):
     _solve_fixed(torch_cuda, name, itn, 1, VARIANTS[0], fused=fused, compact=0)
@@ -354,7 +406,7 @@ def test_option_errors(torch_cuda):
     say("option validation: few_rows")
     g = gpu_system(torch, S)
     bad = [("att_mode", 2), ("ktile", 3), ("chunk", 0), ("att_buckets", -1), ("outer_tol", -1.0),
-           ("fused", 3), ("att_rhs", 3), ("att_rhs", 0)]
+           ("fused", 4), ("att_rhs", 3), ("att_rhs", 0)]
     for name, value in bad:
         with pytest.raises(LsqrError) as ei:
             g.set_option(name, value)
@@ -459,15 +511,18 @@ F32_WIDE = synth.tiny(seed=32, n_stars=700, obs=(60, 100), n_dfa=200, n_instr_co
                       value_dtype="f32", astro_scale=(-2.0, 2.0))
 
 
+@pytest.mark.parametrize("fused", [2, 3])
 @pytest.mark.parametrize("spec", [F32_SPEC, F32_WIDE], ids=["f32", "f32_wide_instr"])
-def test_refined_matches_fp64_oracle(torch_cuda, spec):
+def test_refined_matches_fp64_oracle(torch_cuda, spec, fused):
     torch = torch_cuda
     S = synth.make_system(spec)
     o = oracle.OracleSystem.from_synth(S)
     b = _b(S, o)
     x_ref, i_ref = o.lsqr(b, 500, atol=1e-14, btol=1e-14, conlim=0.0)
-    say(f"refined solve: FP32 values m={S.m}; oracle itn={i_ref.itn} istop={i_ref.istop}")
+    say(f"refined solve: FP32 values m={S.m} fused={fused}; oracle itn={i_ref.itn} "
+        f"istop={i_ref.istop}")
     g = gpu_system(torch, S)
+    g.set_option("fused", fused)
     x, info = g.solve_refined(torch.from_numpy(b).cuda(), 200, atol=1e-6, btol=1e-6,
                               outer_limit=8)
     xg = x.cpu().numpy()
