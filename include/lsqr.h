@@ -189,7 +189,8 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         memory; the caller's arrays are used otherwise and
  *                         by every other pass; 0: never (frees the copies)
  *   LSQR_OPT_KTILE        batched solves: right-hand sides advanced together per
- *                         pass over A (1, 2, 4, 8), 0 (default) = autotune (see
+ *                         pass over A (1, 2, 4, 8, 16; 16 in fused modes 2 and 3
+ *                         with LSQR_OPT_RHS_LANES), 0 (default) = autotune (see
  *                         lsqr_batch_tuning)
  *   LSQR_OPT_ATT_RHS      right-hand sides one sweep of the bucket-order
  *                         attitude passes holds (1 default, 2, 4, 8): the
@@ -204,6 +205,13 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *                         store (or LDS atomics) of the current one, so that no
  *                         row waits for the previous row's store; 0: one row at
  *                         a time (same results)
+ *   LSQR_OPT_RHS_LANES    batched k-tiles of K >= 2 RHS in fused modes 2 and 3:
+ *                         1 (default) the fused pass and the first aprod2 of a
+ *                         solve put the K right-hand sides of a row in K lanes
+ *                         (a wave covers 64 / K rows, a lane holds one value
+ *                         per vector entry); 0: one row per lane with K values
+ *                         (K <= 8). Same results up to rounding order; the
+ *                         16-RHS tile needs 1
  */
 #define LSQR_OPT_CONLIM 1
 #define LSQR_OPT_TESTS 2
@@ -221,6 +229,7 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
 #define LSQR_OPT_COMPACT_INDEX 14
 #define LSQR_OPT_ATT_RHS 15
 #define LSQR_OPT_PIPELINE 16
+#define LSQR_OPT_RHS_LANES 17
 lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value);
 
 /* Below, m counts every row: n_rows observation rows plus n_con constraint
@@ -334,7 +343,7 @@ lsqr_status lsqr_solve_batched_refined(lsqr_handle* h, const double* B, double* 
 
 /* Autotuner result of this handle: the k-tile of its last autotuned batched
  * solve (0 if none yet) and the measured milliseconds per RHS-iteration for
- * K = 1, 2, 4, 8 of that tuning (4 host doubles, 0 where not measured). The
+ * K = 1, 2, 4, 8, 16 of that tuning (5 host doubles, 0 where not measured). The
  * tuner runs on the first batched call for each precision (FP64 tiles,
  * FP32 inner tiles of the refined form) and each min(k, 8), and again after
  * an option that selects kernels changes. Host pointers; either may be

@@ -1521,7 +1521,7 @@ __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val
 // issue order, so a store issued before the next row's loads would be waited
 // for together with them (one store round trip per row); after them it is
 // not.
-template <typename T, typename Acc, int K, int KS, int NT, bool SEP = false, bool PIPE = true>
+template <typename T, typename Acc, int K, int KS, int NT, bool SEP = false, bool PIPE = (K == 1)>
 __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__ att_sorted,
                                                  const int32_t* __restrict__ tloc,
                                                  const int64_t* __restrict__ bstart,
@@ -1667,7 +1667,8 @@ __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__
 // PIPE: each thread issues the loads of its next row before the atomics of
 // the current one (with GATHER, the current row's read through the
 // permutation first: its index came with the previous loads).
-template <typename T, typename Acc, int K, int KS, int NT, bool GATHER = false, bool PIPE = true>
+template <typename T, typename Acc, int K, int KS, int NT, bool GATHER = false,
+          bool PIPE = (K == 1)>
 __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict__ att_sorted,
                                                   const int32_t* __restrict__ tloc,
                                                   const int64_t* __restrict__ bstart,
@@ -2378,6 +2379,204 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
     for (int64_t j = threadIdx.x; j < hcols * K; j += NT) {
         const double v = hist[j];
         if (v != 0.0) atomicAdd(&qins[j], (Acc)v);
+    }
+}
+
+// ---- right-hand sides across lanes (k_fused_rl)
+// In this layout lane l of a wave handles row slot l / K and right-hand side
+// l % K, so a wave steps over R = 64 / K rows at a time and every lane holds
+// one RHS value, as in the single-RHS pass (registers do not grow with K).
+// Sum over the R row slots of the lanes of one RHS (lanes equal mod K); the
+// result is in every lane.
+template <int K, typename V>
+__device__ __forceinline__ V rhs_sum(V v)
+{
+#pragma unroll
+    for (int off = K; off < kWave; off <<= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Per-star segmented sums (SegAcc) in the RHS-across-lanes layout: the keys
+// of the K lanes of a row slot are equal, segments are runs of row slots;
+// emit(key, totals) runs on lanes 0..K-1 (lane j for RHS j) once per
+// finished segment.
+template <typename Acc, int K, typename Emit>
+__device__ __forceinline__ void seg_chunk_rl(SegAcc<Acc, kAstro>& S, int64_t key,
+                                             const Acc (&v)[kAstro], int lane, Emit&& emit)
+{
+    const bool cont = key == S.key;
+#pragma unroll
+    for (int j = 0; j < kAstro; ++j) S.acc[j] += cont ? v[j] : (Acc)0;
+    uint64_t rest = __ballot(!cont);
+    if (rest == 0) return;
+    if (S.key >= 0) {
+        Acc t[kAstro];
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j) t[j] = rhs_sum<K>(S.acc[j]);
+        if (lane < K) emit(S.key, t);
+    }
+    S.key = -1;
+#pragma unroll
+    for (int j = 0; j < kAstro; ++j) S.acc[j] = (Acc)0;
+    while (rest != 0) {
+        const int l0 = __ffsll((unsigned long long)rest) - 1;
+        const int64_t k2 = __shfl(key, l0);
+        if (k2 == kNoStar) break;
+        const bool mine = key == k2;
+        const uint64_t same = __ballot(mine);
+        if ((same >> (kWave - 1)) & 1ull) {  // reaches the last row slot: stays open
+            S.key = k2;
+#pragma unroll
+            for (int j = 0; j < kAstro; ++j) S.acc[j] = mine ? v[j] : (Acc)0;
+            break;
+        }
+        Acc t[kAstro];
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j) t[j] = rhs_sum<K>(mine ? v[j] : (Acc)0);
+        if (lane < K) emit(k2, t);
+        rest &= ~same;
+    }
+}
+
+template <typename Acc, int K, typename Emit>
+__device__ __forceinline__ void seg_finish_rl(SegAcc<Acc, kAstro>& S, int lane, Emit&& emit)
+{
+    if (S.key < 0) return;
+    Acc t[kAstro];
+#pragma unroll
+    for (int j = 0; j < kAstro; ++j) t[j] = rhs_sum<K>(S.acc[j]);
+    if (lane < K) emit(S.key, t);
+    S.key = -1;
+}
+
+// The fused pass of a K-tile after the attitude pre-pass (fused modes 2 and
+// 3) with the K right-hand sides of a row in K lanes: per row and live RHS r,
+// U~_r = (attitude part already in U) + the other sections' products with
+// VP_r, written with its FP64 sum of squares, and the same value scattered
+// into Q += A^T U~ for the astrometric (per-star segments), instrumental (LDS
+// histogram [hcols][K], the rest to k_instr_tail) and global (partials
+// gpart[blk][K]) columns. A2: aprod2 alone (Q += A^T U, U not changed, no
+// sums of squares), the start of a tile's solve. U row i at U[inv[i] K + r].
+template <typename T, typename Acc, int K, int NT, bool LDSX, bool CIDX, bool A2>
+__global__ __launch_bounds__(NT) void k_fused_rl(SysView s, const Acc* __restrict__ VP,
+                                                  Acc* __restrict__ U, Acc* __restrict__ Q,
+                                                  const int64_t* __restrict__ wb,
+                                                  Acc* __restrict__ gpart,
+                                                  double* __restrict__ part, int64_t hcols,
+                                                  const Scalars* __restrict__ sc,
+                                                  const int32_t* __restrict__ inv)
+{
+    constexpr int R = kWave / K;  // row slots of a wave
+    constexpr int W = NT / kWave;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ Acc gred[W * K];
+    __shared__ double sred[W * K];
+    uint32_t live = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+        live |= ((sc[r].done || (A2 && sc[r].beta_zero)) ? 0u : 1u) << r;
+    if (live == 0) return;
+    const T* __restrict__ val = static_cast<const T*>(s.val);
+    const int64_t m = s.m;
+    const int64_t ninst = s.n_instr_cols;
+    double* hist = reinterpret_cast<double*>(smem_raw);
+    const Acc* xi = VP + s.instr_base * K;
+    for (int64_t e = threadIdx.x; e < hcols * K; e += NT) hist[e] = 0.0;
+    if (LDSX && !A2) {
+        const int64_t off = (hcols * K * 8 + 15) & ~(int64_t)15;
+        Acc* xl = reinterpret_cast<Acc*>(smem_raw + off);
+        for (int64_t e = threadIdx.x; e < ninst * K; e += NT) xl[e] = xi[e];
+        xi = xl;
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int rj = lane & (K - 1);    // this lane's right-hand side
+    const int slot = lane / K;        // and row slot
+    const bool lj = (live >> rj) & 1u;
+    const Acc xg = A2 ? (Acc)0 : VP[s.glob_base * K + rj];
+    const int64_t wave = (int64_t)blockIdx.x * W + threadIdx.x / kWave;
+    const int64_t rb = wb[wave], re = wb[wave + 1];
+    Acc* __restrict__ qins = Q + s.instr_base * K;
+    double ssq = 0.0;
+    Acc gsum = (Acc)0;
+    SegAcc<Acc, kAstro> seg;
+    auto astro_emit = [Q, lane](int64_t star, const Acc (&tot)[kAstro]) {
+        Acc* dst = Q + kAstro * star * K + lane;
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j) dst[j * K] += tot[j];
+    };
+    // R-row steps aligned to R rows (every coefficient stream read in whole
+    // R-row pieces); slots outside [rb, re) use a clamped row and contribute
+    // nothing
+    for (int64_t r0 = rb < re ? (rb & ~(int64_t)(R - 1)) : re; r0 < re; r0 += R) {
+        const int64_t i = r0 + slot;
+        const bool ok = i >= rb && i < re;
+        const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
+        const int64_t stc = star_of<CIDX>(s, ic);
+        const int64_t st = i < re ? stc : kNoStar;
+        T a[kPar];
+#pragma unroll
+        for (int c = 0; c < kPar; ++c)
+            if (c < kOffAtt || c >= kOffInstr) a[c] = ldnt(&val[c * m + ic]);
+        int32_t ix[kInstr];
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) ix[j] = instr_of<CIDX>(s, j, ic);
+        const int64_t pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
+        const Acc uo = U[pu * K + rj];
+        const bool on = ok && lj;
+        Acc d;
+        if (A2) {
+            d = on ? uo : (Acc)0;
+        } else {
+            // Eq. (2): the row's non-attitude products with VP_r, added to
+            // the attitude part the pre-pass left in U
+            Acc dot = (Acc)0;
+            const Acc* xa = VP + kAstro * stc * K + rj;
+#pragma unroll
+            for (int j = 0; j < kAstro; ++j) dot += (Acc)a[j] * xa[j * K];
+#pragma unroll
+            for (int j = 0; j < kInstr; ++j) dot += (Acc)a[kOffInstr + j] * xi[ix[j] * K + rj];
+            dot += (Acc)a[kOffGlob] * xg;
+            const Acc nu = dot + uo;
+            if (on) U[pu * K + rj] = nu;
+            d = on ? nu : (Acc)0;
+            ssq += (double)d * (double)d;
+        }
+        // Eq. (3) with the new value, attitude columns excluded
+        if (on) {
+#pragma unroll
+            for (int j = 0; j < kInstr; ++j)
+                if (ix[j] < hcols)
+                    atomicAdd(&hist[ix[j] * K + rj], (double)((Acc)a[kOffInstr + j] * d));
+        }
+        gsum += (Acc)a[kOffGlob] * d;
+        Acc pa[kAstro];
+#pragma unroll
+        for (int j = 0; j < kAstro; ++j) pa[j] = (Acc)a[j] * d;
+        seg_chunk_rl<Acc, K>(seg, st, pa, lane, astro_emit);
+    }
+    seg_finish_rl<Acc, K>(seg, lane, astro_emit);
+    gsum = rhs_sum<K>(gsum);
+    ssq = rhs_sum<K>(ssq);
+    if (lane < K) {
+        gred[(threadIdx.x / kWave) * K + lane] = gsum;
+        sred[(threadIdx.x / kWave) * K + lane] = ssq;
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        Acc g = (Acc)0;
+        double q2 = 0.0;
+        for (int w = 0; w < W; ++w) {
+            g += gred[w * K + threadIdx.x];
+            q2 += sred[w * K + threadIdx.x];
+        }
+        gpart[(int64_t)blockIdx.x * K + threadIdx.x] = g;
+        if (!A2) part[(int64_t)blockIdx.x * K + threadIdx.x] = q2;
+    }
+    for (int64_t e = threadIdx.x; e < hcols * K; e += NT) {
+        const double v = hist[e];
+        if (v != 0.0) atomicAdd(&qins[e], (Acc)v);
     }
 }
 

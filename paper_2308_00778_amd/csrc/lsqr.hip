@@ -87,6 +87,7 @@ lsqr_status dalloc(V** p, int64_t count)
     hipError_t e = hipMalloc(reinterpret_cast<void**>(p), (size_t)count * sizeof(V));
     if (e != hipSuccess) {
         *p = nullptr;
+        (void)hipGetLastError();  // a caller may free memory and try again
         return fail(e == hipErrorOutOfMemory ? LSQR_E_NOMEM : LSQR_E_HIP,
                     "hipMalloc of %lld bytes failed: %s", (long long)(count * sizeof(V)),
                     hipGetErrorString(e));
@@ -118,6 +119,7 @@ constexpr int kWavesPerCU = 16;                 // row ranges per compute unit i
 // split into (measured on 1e8 rows: +0.17 ms at 16 buckets, +0.65 ms at 25,
 // +1.6 ms at 100).
 constexpr int kAttBlock = 1024;  // attitude-pass workgroup (one per CU: the histogram fills LDS)
+constexpr int kMaxTile = 16;     // right-hand sides of the widest k-tile
 
 // Working vectors of one arithmetic precision of the LSQR loop.
 template <typename Acc>
@@ -217,16 +219,16 @@ struct lsqr_handle {
         float *U32 = nullptr, *VP32 = nullptr, *Q32 = nullptr, *gpart32 = nullptr, *X332 = nullptr;
         Scalars* sc = nullptr;
         int32_t* flag = nullptr;
-        hipGraphExec_t graph[9] = {};    // FP64 tiles, by K
-        int graph_chunk[9] = {};
-        hipGraphExec_t graph32[9] = {};  // FP32 inner tiles, by K
-        int graph32_chunk[9] = {};
+        hipGraphExec_t graph[17] = {};    // FP64 tiles, by K
+        int graph_chunk[17] = {};
+        hipGraphExec_t graph32[17] = {};  // FP32 inner tiles, by K
+        int graph32_chunk[17] = {};
         // autotuner: chosen k-tile per precision (0, 1) and per cap min(k, 8)
         // (index log2), and the measured ms per RHS-iteration by K of the last
         // tuning
-        int tuned_k[2][4] = {};
+        int tuned_k[2][5] = {};
         int last_tuned = 0;
-        double tuned_ms[9] = {};
+        double tuned_ms[17] = {};
     } batch;
 
     // options
@@ -244,6 +246,7 @@ struct lsqr_handle {
                          // order (pre-pass output gathered); 0: separate aprod1 and aprod2
     int last_mode = 0;   // fused mode of the last single-RHS solve
     int pipe = 1;        // bucket-order passes load the next row before storing the current
+    int rhs_lanes = 1;   // k-tiles: the fused pass puts the K RHS of a row in K lanes
     int compact = 1;     // compact index copies for the fused passes when they fit
     int compact_tried = 0;
     int32_t* star32 = nullptr;    // [m] compact star index (or null)
@@ -277,6 +280,11 @@ inline int fused_mode(const lsqr_handle* h) { return use_fused(h) ? h->fused : 0
 // pass reads and writes it sequentially, and the bucket-order passes reach it
 // (or the pre-pass's separate output) through the permutation, read-only.
 inline bool star_order_u(const lsqr_handle* h) { return fused_mode(h) == 3; }
+
+// k-tiles of K >= 2 after the attitude pre-pass run the fused pass (and the
+// first aprod2 of a solve) with the K right-hand sides of a row in K lanes
+// (k_fused_rl), which the 16-RHS tile needs
+inline bool rhs_lanes_on(const lsqr_handle* h) { return h->rhs_lanes && use_fused(h) && h->fused >= 2; }
 
 // Partials of ||u||^2 that a scalar kernel sums: the row-pass partials plus,
 // with constraint rows, their share stored right after them.
@@ -789,7 +797,7 @@ void drop_graphs(lsqr_handle* h)
         *g = nullptr;
     }
     for (auto* gs : {h->batch.graph, h->batch.graph32})
-        for (int k = 0; k < 9; ++k) {
+        for (int k = 0; k < 17; ++k) {
             if (gs[k]) (void)hipGraphExecDestroy(gs[k]);
             gs[k] = nullptr;
         }
@@ -991,7 +999,7 @@ void batch_free(lsqr_handle* h)
 {
     auto& B = h->batch;
     for (auto* gs : {B.graph, B.graph32})
-        for (int k = 0; k < 9; ++k) {
+        for (int k = 0; k < 17; ++k) {
             if (gs[k]) (void)hipGraphExecDestroy(gs[k]);
             gs[k] = nullptr;
         }
@@ -1118,6 +1126,7 @@ int fused_grid(const lsqr_handle* h) { return (int)(h->nw / (fused_nt<K, AM>() /
 template <int K>
 int batch_fused_grid(const lsqr_handle* h)
 {
+    if (K >= 2 && rhs_lanes_on(h)) return h->nb2;  // k_fused_rl: 1024-thread workgroups
     return h->fused >= 2 ? fused_grid<K, kAttPre>(h) : fused_grid<K, kAttX>(h);
 }
 
@@ -1130,15 +1139,14 @@ int att_sweep(const lsqr_handle* h, int64_t vbytes = 8)
 {
     const int64_t fit = kLdsInstrBudget / (kAxes * att_span(h) * vbytes);
     int ks = 1;
-    while (ks * 2 <= K && ks * 2 <= fit) ks *= 2;
+    // at most 4 per sweep: 8 or 16 running dot products per row spill registers
+    while (ks * 2 <= K && ks * 2 <= fit && ks * 2 <= 4) ks *= 2;
     return ks;
 }
 
 template <int K, typename F>
 void by_sweep(int ks, F&& f)
 {
-    if constexpr (K >= 8)
-        if (ks == 8) return f(std::integral_constant<int, 8>());
     if constexpr (K >= 4)
         if (ks == 4) return f(std::integral_constant<int, 4>());
     if constexpr (K >= 2)
@@ -1175,15 +1183,27 @@ void batch_aprod2(lsqr_handle* h, hipStream_t st)
     const int64_t hc = instr_hcols(h, K);
     const size_t lds = (size_t)(hc * K * 8);
     constexpr int NT = batch_nt<K>();
-    const int grid = batch_grid<K>(h);
-    if (h->att_mode == 0)
-        hipLaunchKernelGGL((batched::k_aprod2<T, Acc, K, true, NT>), dim3(grid), dim3(NT), lds, st,
-                           h->sv, (const Acc*)tb.U, tb.Q, h->wb, tb.gpart, hc, B.sc,
-                           batch_row_map(h));
-    else
-        hipLaunchKernelGGL((batched::k_aprod2<T, Acc, K, false, NT>), dim3(grid), dim3(NT), lds,
-                           st, h->sv, (const Acc*)tb.U, tb.Q, h->wb, tb.gpart, hc, B.sc,
-                           batch_row_map(h));
+    int grid = batch_grid<K>(h);
+    if (K >= 2 && rhs_lanes_on(h)) {
+        grid = h->nb2;
+        if (h->sv.star32)
+            hipLaunchKernelGGL((batched::k_fused_rl<T, Acc, K, kBlock2, false, true, true>),
+                               dim3(grid), dim3(kBlock2), lds, st, h->sv, (const Acc*)tb.VP, tb.U,
+                               tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc, batch_row_map(h));
+        else
+            hipLaunchKernelGGL((batched::k_fused_rl<T, Acc, K, kBlock2, false, false, true>),
+                               dim3(grid), dim3(kBlock2), lds, st, h->sv, (const Acc*)tb.VP, tb.U,
+                               tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc, batch_row_map(h));
+    } else if constexpr (K <= 8) {
+        if (h->att_mode == 0)
+            hipLaunchKernelGGL((batched::k_aprod2<T, Acc, K, true, NT>), dim3(grid), dim3(NT), lds,
+                               st, h->sv, (const Acc*)tb.U, tb.Q, h->wb, tb.gpart, hc, B.sc,
+                               batch_row_map(h));
+        else
+            hipLaunchKernelGGL((batched::k_aprod2<T, Acc, K, false, NT>), dim3(grid), dim3(NT),
+                               lds, st, h->sv, (const Acc*)tb.U, tb.Q, h->wb, tb.gpart, hc, B.sc,
+                               batch_row_map(h));
+    }
     hipLaunchKernelGGL((batched::k_glob_sum<Acc, K>), dim3(1), dim3(kBlock), 0, st,
                        (const Acc*)tb.gpart, grid, tb.Q + h->sv.glob_base * K, B.sc);
     launch_instr_tail<T, Acc, K, false>(h, (const Acc*)tb.U, batch_row_map(h), tb.Q, hc, B.sc, st);
@@ -1195,15 +1215,33 @@ void batch_fused_as(lsqr_handle* h, const Acc* X3, int64_t hc, size_t lds, hipSt
 {
     auto& B = h->batch;
     const TileBufs<Acc> tb = tile_bufs<Acc>(h);
-    constexpr int NT = fused_nt<K, AM>();
-    if (h->sv.star32)
-        hipLaunchKernelGGL((batched::k_fused<T, Acc, K, NT, LDSX, AM, true>),
-                           dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv, (const Acc*)tb.VP,
-                           X3, tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc, batch_row_map(h));
-    else
-        hipLaunchKernelGGL((batched::k_fused<T, Acc, K, NT, LDSX, AM, false>),
-                           dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv, (const Acc*)tb.VP,
-                           X3, tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc, batch_row_map(h));
+    if constexpr (AM == kAttPre)
+        if (K >= 2 && rhs_lanes_on(h)) {  // the K right-hand sides of a row in K lanes
+            if (h->sv.star32)
+                hipLaunchKernelGGL((batched::k_fused_rl<T, Acc, K, kBlock2, LDSX, true, false>),
+                                   dim3(h->nb2), dim3(kBlock2), lds, st, h->sv, (const Acc*)tb.VP,
+                                   tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc,
+                                   batch_row_map(h));
+            else
+                hipLaunchKernelGGL((batched::k_fused_rl<T, Acc, K, kBlock2, LDSX, false, false>),
+                                   dim3(h->nb2), dim3(kBlock2), lds, st, h->sv, (const Acc*)tb.VP,
+                                   tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc,
+                                   batch_row_map(h));
+            return;
+        }
+    if constexpr (K <= 8) {  // 16-RHS tiles are built in the RHS-across-lanes form only
+        constexpr int NT = fused_nt<K, AM>();
+        if (h->sv.star32)
+            hipLaunchKernelGGL((batched::k_fused<T, Acc, K, NT, LDSX, AM, true>),
+                               dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv,
+                               (const Acc*)tb.VP, X3, tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc,
+                               B.sc, batch_row_map(h));
+        else
+            hipLaunchKernelGGL((batched::k_fused<T, Acc, K, NT, LDSX, AM, false>),
+                               dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv,
+                               (const Acc*)tb.VP, X3, tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc,
+                               B.sc, batch_row_map(h));
+    }
 }
 
 // The fused pass of a k-tile; in fused mode 2 the attitude pre-pass
@@ -1261,7 +1299,7 @@ void batch_iteration(lsqr_handle* h, hipStream_t st, hipEvent_t* ev)
                            (const Acc*)tb.gpart, batch_fused_grid<K>(h),
                            tb.Q + h->sv.glob_base * K, B.sc);
         batch_att_pass<T, Acc, K>(h, st);
-    } else {
+    } else if constexpr (K <= 8) {
         hipLaunchKernelGGL((batched::k_aprod1<T, Acc, K>), dim3(h->nb1), dim3(kBlock), 0, st,
                            h->sv, (const Acc*)tb.VP, tb.U, B.sc, B.part1, batch_row_map(h));
         if (ev) (void)hipEventRecord(ev[1], st);
@@ -1288,7 +1326,7 @@ template <int K>
 lsqr_status batch_controls(lsqr_handle* h, int32_t itn_limit, double atol, double btol,
                            double rel_ar = 0.0)
 {
-    Scalars host[8];
+    Scalars host[kMaxTile];
     memset(host, 0, sizeof host);
     for (int r = 0; r < K; ++r) {
         host[r].atol = atol;
@@ -1429,7 +1467,7 @@ lsqr_status batch_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X,
     hipLaunchKernelGGL((batched::k_copy_ssq<double, K>), dim3(h->nb1), dim3(kBlock), 0, st, m, Bm,
                        ldb, B.U, B.part1, batch_row_map(h));
     LSQR_TRY((batch_init<T, double, K>(h)));
-    Scalars host[8];
+    Scalars host[kMaxTile];
     LSQR_TRY((batch_run<T, double, K>(h, itn_limit, max_chunks, host)));
     hipLaunchKernelGGL((batched::k_unprecond<K>), dim3(h->nbc), dim3(kBlock), 0, st, n, h->p,
                        (const double*)B.Y, X, ldx);
@@ -1459,9 +1497,9 @@ lsqr_status batch_refined_tile(lsqr_handle* h, const double* Bm, int64_t ldb, do
     const int64_t m = h->sv.m, n = h->sv.n;
     hipLaunchKernelGGL((batched::k_zero_cols<K>), dim3(h->nbc), dim3(kBlock), 0, st, n, X, ldx);
     uint32_t live = (1u << K) - 1u;
-    int32_t total_itn[8] = {}, steps[8] = {};
-    double bnorm[8] = {};
-    Scalars last[8], host[8];
+    int32_t total_itn[kMaxTile] = {}, steps[kMaxTile] = {};
+    double bnorm[kMaxTile] = {};
+    Scalars last[kMaxTile], host[kMaxTile];
     memset(last, 0, sizeof last);
     for (int outer = 1; outer <= outer_limit && live; ++outer) {
         LSQR_TRY(batch_controls<K>(h, itn_limit, 0.0, 0.0, std::max(atol, 1e-300)));
@@ -1502,13 +1540,17 @@ lsqr_status batch_tile_k(lsqr_handle* h, bool refined, int K, const double* Bm, 
                          double* X, int64_t ldx, int32_t itn_limit, double atol, double btol,
                          int32_t outer_limit, lsqr_info* infos, int max_chunks)
 {
+    if (K > 8 && !rhs_lanes_on(h))
+        return fail(LSQR_E_UNSUPPORTED, "16-RHS tiles need fused mode 2 or 3, attitude mode 1 "
+                                        "and LSQR_OPT_RHS_LANES = 1");
     if (refined) {
         switch (K) {
         case 1: return batch_refined_tile<T, 1>(h, Bm, ldb, X, ldx, itn_limit, atol, outer_limit, infos);
         case 2: return batch_refined_tile<T, 2>(h, Bm, ldb, X, ldx, itn_limit, atol, outer_limit, infos);
         case 4: return batch_refined_tile<T, 4>(h, Bm, ldb, X, ldx, itn_limit, atol, outer_limit, infos);
         case 8: return batch_refined_tile<T, 8>(h, Bm, ldb, X, ldx, itn_limit, atol, outer_limit, infos);
-        default: return fail(LSQR_E_INVALID, "k-tile must be 1, 2, 4 or 8");
+        case 16: return batch_refined_tile<T, 16>(h, Bm, ldb, X, ldx, itn_limit, atol, outer_limit, infos);
+        default: return fail(LSQR_E_INVALID, "k-tile must be 1, 2, 4, 8 or 16");
         }
     }
     switch (K) {
@@ -1516,7 +1558,8 @@ lsqr_status batch_tile_k(lsqr_handle* h, bool refined, int K, const double* Bm, 
     case 2: return batch_tile<T, 2>(h, Bm, ldb, X, ldx, itn_limit, atol, btol, infos, max_chunks);
     case 4: return batch_tile<T, 4>(h, Bm, ldb, X, ldx, itn_limit, atol, btol, infos, max_chunks);
     case 8: return batch_tile<T, 8>(h, Bm, ldb, X, ldx, itn_limit, atol, btol, infos, max_chunks);
-    default: return fail(LSQR_E_INVALID, "k-tile must be 1, 2, 4 or 8");
+    case 16: return batch_tile<T, 16>(h, Bm, ldb, X, ldx, itn_limit, atol, btol, infos, max_chunks);
+    default: return fail(LSQR_E_INVALID, "k-tile must be 1, 2, 4, 8 or 16");
     }
 }
 
@@ -1532,7 +1575,7 @@ lsqr_status batch_probe(lsqr_handle* h, const double* Bm, int64_t ldb, double* m
     hipLaunchKernelGGL((batched::k_copy_ssq<Acc, K>), dim3(h->nb1), dim3(kBlock), 0, h->stream,
                        h->sv.m, Bm, ldb, tb.U, B.part1, batch_row_map(h));
     LSQR_TRY((batch_init<T, Acc, K>(h)));
-    Scalars host[8];
+    Scalars host[kMaxTile];
     h->ms1 = h->ms2 = h->ms_pre = 0.0;
     h->n1 = h->n2 = 0;
     LSQR_TRY((batch_run<T, Acc, K>(h, 1 << 20, 1, host)));
@@ -1558,7 +1601,8 @@ lsqr_status batch_autotune(lsqr_handle* h, bool refined, const double* Bm, int64
     h->profile = 1;
     h->tests = 0;
     h->chunk = 3;
-    for (int K = 1; K <= 8 && K <= k; K *= 2) {
+    for (int K = 1; K <= kMaxTile && K <= k; K *= 2) {
+        if (K > 8 && !rhs_lanes_on(h)) break;  // 16-RHS tiles need the RHS-across-lanes pass
         double ms = 0.0;
         auto probe = [&](auto KK) {
             constexpr int Kc = decltype(KK)::value;
@@ -1569,7 +1613,8 @@ lsqr_status batch_autotune(lsqr_handle* h, bool refined, const double* Bm, int64
         case 1: rc = probe(std::integral_constant<int, 1>()); break;
         case 2: rc = probe(std::integral_constant<int, 2>()); break;
         case 4: rc = probe(std::integral_constant<int, 4>()); break;
-        default: rc = probe(std::integral_constant<int, 8>()); break;
+        case 8: rc = probe(std::integral_constant<int, 8>()); break;
+        default: rc = probe(std::integral_constant<int, 16>()); break;
         }
         if (rc != LSQR_OK) break;
         B.tuned_ms[K] = ms;
@@ -1593,7 +1638,7 @@ lsqr_status batch_autotune(lsqr_handle* h, bool refined, const double* Bm, int64
 
 inline int log2_cap(int32_t k)
 {
-    return k >= 8 ? 3 : (k >= 4 ? 2 : (k >= 2 ? 1 : 0));
+    return k >= 16 ? 4 : (k >= 8 ? 3 : (k >= 4 ? 2 : (k >= 2 ? 1 : 0)));
 }
 
 template <typename T>
@@ -1989,8 +2034,9 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         return LSQR_OK;
     }
     case LSQR_OPT_KTILE:
-        if (!(value == 0.0 || value == 1.0 || value == 2.0 || value == 4.0 || value == 8.0))
-            return fail(LSQR_E_INVALID, "k-tile must be 0 (autotune), 1, 2, 4 or 8");
+        if (!(value == 0.0 || value == 1.0 || value == 2.0 || value == 4.0 || value == 8.0 ||
+              value == 16.0))
+            return fail(LSQR_E_INVALID, "k-tile must be 0 (autotune), 1, 2, 4, 8 or 16");
         h->ktile = (int)value;
         return LSQR_OK;
     case LSQR_OPT_ATT_RHS:
@@ -2027,6 +2073,12 @@ lsqr_status lsqr_set_option(lsqr_handle* h, int32_t option, double value)
         }
         if (v && !h->compact) h->compact_tried = 0;
         h->compact = v;
+        return LSQR_OK;
+    }
+    case LSQR_OPT_RHS_LANES: {
+        const int v = value != 0.0 ? 1 : 0;
+        if (h->rhs_lanes != v) drop_graphs(h);
+        h->rhs_lanes = v;
         return LSQR_OK;
     }
     case LSQR_OPT_PIPELINE: {
@@ -2313,7 +2365,7 @@ lsqr_status lsqr_batch_tuning(lsqr_handle* h, int32_t* k_tile, double* ms_per_rh
     if (!h) return fail(LSQR_E_INVALID, "null handle");
     if (k_tile) *k_tile = h->batch.last_tuned;
     if (ms_per_rhs_iter)
-        for (int K = 1, i = 0; K <= 8; K *= 2, ++i) ms_per_rhs_iter[i] = h->batch.tuned_ms[K];
+        for (int K = 1, i = 0; K <= kMaxTile; K *= 2, ++i) ms_per_rhs_iter[i] = h->batch.tuned_ms[K];
     return LSQR_OK;
 }
 

@@ -25,7 +25,7 @@ LSQR_F32 = 1
 OPTIONS = {"conlim": 1, "tests": 2, "chunk": 3, "graph": 4, "profile": 5, "outer_tol": 6,
            "att_mode": 7, "astro_scan": 8, "ktile": 9, "att_buckets": 10,
            "att_interleave": 11, "fused": 12, "variance": 13, "compact_index": 14,
-           "att_rhs": 15, "pipeline": 16}
+           "att_rhs": 15, "pipeline": 16, "rhs_lanes": 17}
 
 SYMBOLS = ("lsqr_create", "lsqr_destroy", "lsqr_set_option", "lsqr_aprod1", "lsqr_aprod2",
            "lsqr_aprod1_noalloc", "lsqr_aprod1_f32", "lsqr_aprod2_f32",
@@ -352,9 +352,9 @@ class LsqrSystem:
 
     def batch_tuning(self):
         k = ctypes.c_int32()
-        ms = (ctypes.c_double * 4)()
+        ms = (ctypes.c_double * 5)()
         _check(_lib.lsqr_batch_tuning(self._h, ctypes.byref(k), ms))
-        return {"k_tile": k.value, "ms_per_rhs_iter": {1 << i: ms[i] for i in range(4)}}
+        return {"k_tile": k.value, "ms_per_rhs_iter": {1 << i: ms[i] for i in range(5)}}
 
     def kernel_times(self):
         a, b = ctypes.c_double(), ctypes.c_double()

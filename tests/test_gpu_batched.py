@@ -63,6 +63,62 @@ def test_batched_fixed_iterations(torch_cuda, c0, ktile, att_mode, fused, compac
         assert abs(infos[j].rnorm - i_ref.rnorm) <= 1e-8 * i_ref.rnorm
 
 
+# The 16-RHS tile (the fused pass and the first aprod2 with the right-hand
+# sides of a row across 16 lanes) on 18 right-hand sides: one 16-tile and a
+# ragged 2-tile; against the oracle at a fixed iteration count. Also the
+# K-values-per-lane layout of the 2- to 8-RHS tiles (LSQR_OPT_RHS_LANES 0).
+@pytest.fixture(scope="module")
+def c0_18():
+    S = synth.make_system(synth.WORKLOADS[0])
+    o = oracle.OracleSystem.from_synth(S)
+    xt = synth.x_true(S.spec)
+    B = np.stack([o.aprod1(xt, synth.noise(S.spec, S.m, rhs=j)) for j in range(18)], axis=1)
+    return S, o, B
+
+
+@pytest.mark.parametrize("fused,compact,lanes,ktile", [(2, 1, 1, 16), (3, 0, 1, 16),
+                                                       (2, 1, 0, 8), (2, 1, 0, 4),
+                                                       (2, 0, 1, 8)])
+def test_batched_wide_tiles(torch_cuda, c0_18, fused, compact, lanes, ktile):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LsqrSystem
+
+    S, o, B = c0_18
+    itn = 30
+    say(f"batched parity: c0 k=18 ktile={ktile} fused={fused} compact={compact} "
+        f"rhs_lanes={lanes} itn={itn}")
+    g = LsqrSystem.from_host(S, "cuda:0")
+    g.set_option("fused", fused)
+    g.set_option("compact_index", compact)
+    g.set_option("rhs_lanes", lanes)
+    g.set_option("att_buckets", 4)
+    g.set_option("tests", 0)
+    g.set_option("ktile", ktile)
+    X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(B)).cuda(), itn, 0.0, 0.0)
+    Xh = X.cpu().numpy()
+    g.close()
+    for j in range(B.shape[1]):
+        x_ref, i_ref = o.lsqr(B[:, j], itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)
+        assert infos[j].itn == itn and infos[j].istop == 7
+        assert rel_inf(Xh[:, j], x_ref) <= 1e-10, j
+        assert abs(infos[j].rnorm - i_ref.rnorm) <= 1e-8 * i_ref.rnorm
+
+
+def test_batched_16_tile_needs_the_lane_layout(torch_cuda, c0_18):
+    torch = torch_cuda
+    from paper_2308_00778_amd import LSQR_E_UNSUPPORTED, LsqrError, LsqrSystem
+
+    S, o, B = c0_18
+    say("batched 16-RHS tile in fused mode 1: LSQR_E_UNSUPPORTED")
+    g = LsqrSystem.from_host(S, "cuda:0")
+    g.set_option("fused", 1)
+    g.set_option("ktile", 16)
+    with pytest.raises(LsqrError) as ei:
+        g.solve_batched(torch.from_numpy(np.ascontiguousarray(B[:, :16])).cuda(), 5, 0.0, 0.0)
+    g.close()
+    assert ei.value.status == LSQR_E_UNSUPPORTED
+
+
 def test_batched_masks_freeze_converged_rhs(torch_cuda, c0):
     # RHS 0 is consistent (b = one column of A) and stops early by S1; the
     # others stop later by S2. Each must equal its own single solve.
