@@ -1494,7 +1494,7 @@ lsqr_status batch_refined_tile(lsqr_handle* h, const double* Bm, int64_t ldb, do
 {
     auto& B = h->batch;
     hipStream_t st = h->stream;
-    const int64_t m = h->sv.m, n = h->sv.n;
+    const int64_t n = h->sv.n;
     hipLaunchKernelGGL((batched::k_zero_cols<K>), dim3(h->nbc), dim3(kBlock), 0, st, n, X, ldx);
     uint32_t live = (1u << K) - 1u;
     int32_t total_itn[kMaxTile] = {}, steps[kMaxTile] = {};
