@@ -132,8 +132,10 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *   LSQR_OPT_PROFILE      1: time every aprod1 / aprod2 launch of a solve with
  *                         HIP events on the handle's stream (forces GRAPH 0);
  *                         read back with lsqr_kernel_times
- *   LSQR_OPT_OUTER_TOL    refinement: stop when ||d||_inf <= tol ||x||_inf
- *                         (default 1e-10)
+ *   LSQR_OPT_OUTER_TOL    refinement: stop when ||d||_inf <= tol ||x||_inf, or
+ *                         when the corrections contract (||d_k|| <= ||d_k-1|| / 2)
+ *                         and the next one, estimated as ||d_k||^2 / ||d_k-1||,
+ *                         is below tol ||x||_inf / 100 (default 1e-10)
  *   LSQR_OPT_ATT_MODE     attitude part of aprod2: 1 (default) a pass over the
  *                         rows stably sorted by the bucket of their attitude start
  *                         (W starts per bucket), each bucket's 3 x (W + 3)
@@ -297,7 +299,10 @@ lsqr_status lsqr_solve(lsqr_handle* h, const double* b, double* x, int32_t itn_l
  * atol times its initial value ||Abar^T r|| (btol is unused: the residual of
  * a correction problem is dominated by the irreducible least-squares
  * residual, so the absolute tests S1/S2 cannot measure its progress), or
- * after itn_limit iterations; then x += d in FP64. The outer loop ends when ||d||_inf <= OUTER_TOL ||x||_inf,
+ * after itn_limit iterations; then x += d in FP64. The outer loop ends when
+ * ||d||_inf <= OUTER_TOL ||x||_inf, or when the corrections contract
+ * (||d_k||_inf <= ||d_k-1||_inf / 2) and the next one, estimated as
+ * ||d_k||^2 / ||d_k-1|| (infinity norms), is below OUTER_TOL ||x||_inf / 100,
  * when r is zero or orthogonal to the range of A, or after outer_limit steps.
  * b: FP64 [m]; x: FP64 [n] output (x_0 = 0). info->itn counts the inner
  * iterations of all steps, info->outer_steps the outer steps, info->istop and
@@ -328,8 +333,9 @@ lsqr_status lsqr_solve_batched(lsqr_handle* h, const double* B, double* X, int32
  * LSQR with FP32 products and accumulation and FP64 scalars, stopped once
  * ||Abar^T (r_j - A d_j)|| <= atol ||Abar^T r_j|| or after itn_limit
  * iterations (btol unused), then x_j += d_j in FP64; RHS j stops refining
- * when ||d_j||_inf <= OUTER_TOL ||x_j||_inf, when r_j is zero or orthogonal
- * to the range of A, or after outer_limit steps, and is frozen while the
+ * by the outer test of lsqr_solve_refined on its own corrections, when r_j
+ * is zero or orthogonal to the range of A, or after outer_limit steps, and
+ * is frozen while the
  * others continue. Each x[:, j] is the result lsqr_solve_refined would give
  * for b[:, j] up to rounding order. B: FP64 [m][k], X: FP64 [n][k] output,
  * layouts as in lsqr_solve_batched. infos (host, may be NULL): per RHS, itn

@@ -1478,15 +1478,30 @@ lsqr_status batch_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X,
     return LSQR_OK;
 }
 
+// Outer test of the refinement after a correction of size d (infinity norm)
+// on a solution of size xmax, the previous correction being dprev (0 before
+// the second step): stop once d <= tol xmax, or once the corrections contract
+// (d <= dprev / 2) fast enough that the next one, estimated as d (d / dprev),
+// is below kRefinePredict tol xmax. The second rule spares the step whose
+// only effect would be a correction far below the tolerance (the inner solves
+// gain a fixed factor per step, so one more step shrinks the error by that
+// factor again).
+constexpr double kRefinePredict = 1e-2;
+inline bool refine_done(double d, double dprev, double xmax, double tol)
+{
+    if (d <= tol * xmax) return true;
+    return dprev > 0.0 && d <= 0.5 * dprev && d * (d / dprev) <= kRefinePredict * tol * xmax;
+}
+
 // One tile of the refined form: K right-hand sides of an FP32-stored system,
 // each with its own FP64 refinement loop (as lsqr_solve_refined) around FP32
 // inner LSQR solves that advance together. Outer step: for every RHS still
 // refining, r = b - A x in FP64 (stored as the FP32 start vector), then the
 // inner tile solve (relative normal-equation stop atol, itn_limit), then
-// x += p .* y. A RHS stops refining when ||d||_inf <= outer_tol ||x||_inf,
-// when its residual is zero or orthogonal to range(A), or after outer_limit
-// steps; from then on it is masked (zero start vector: frozen at once) and
-// its x no longer changes.
+// x += p .* y. A RHS stops refining by refine_done (its correction against
+// its solution and its previous correction), when its residual is zero or
+// orthogonal to range(A), or after outer_limit steps; from then on it is
+// masked (zero start vector: frozen at once) and its x no longer changes.
 template <typename T, int K>
 lsqr_status batch_refined_tile(lsqr_handle* h, const double* Bm, int64_t ldb, double* X,
                                int64_t ldx, int32_t itn_limit, double atol, int32_t outer_limit,
@@ -1498,7 +1513,7 @@ lsqr_status batch_refined_tile(lsqr_handle* h, const double* Bm, int64_t ldb, do
     hipLaunchKernelGGL((batched::k_zero_cols<K>), dim3(h->nbc), dim3(kBlock), 0, st, n, X, ldx);
     uint32_t live = (1u << K) - 1u;
     int32_t total_itn[kMaxTile] = {}, steps[kMaxTile] = {};
-    double bnorm[kMaxTile] = {};
+    double bnorm[kMaxTile] = {}, dprev[kMaxTile] = {};
     Scalars last[kMaxTile], host[kMaxTile];
     memset(last, 0, sizeof last);
     for (int outer = 1; outer <= outer_limit && live; ++outer) {
@@ -1526,8 +1541,10 @@ lsqr_status batch_refined_tile(lsqr_handle* h, const double* Bm, int64_t ldb, do
             last[r] = host[r];
             // residual zero or orthogonal to range(A) (stopped at the start),
             // or a correction small against the solution
-            if (host[r].itn == 0 || host[r].dmax <= h->outer_tol * host[r].xmax)
+            if (host[r].itn == 0 ||
+                refine_done(host[r].dmax, dprev[r], host[r].xmax, h->outer_tol))
                 live &= ~(1u << r);
+            dprev[r] = host[r].dmax;
         }
     }
     if (infos)
@@ -2270,7 +2287,7 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
     double* part_x = h->partxx;
     hipLaunchKernelGGL((k_fill<double>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n, x, 0.0);
     int32_t total_itn = 0, outer = 0;
-    double bnorm = 0.0;
+    double bnorm = 0.0, dprev = 0.0;
     Scalars last{};
     for (outer = 1; outer <= outer_limit; ++outer) {
         // Each correction problem min ||A d - r|| has a residual dominated by the
@@ -2303,7 +2320,8 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
                            h->nbc, h->sc);
         HIP_TRY(hipGetLastError());
         LSQR_TRY(read_scalars(h));
-        if (h->sc_host->dmax <= h->outer_tol * h->sc_host->xmax) break;
+        if (refine_done(h->sc_host->dmax, dprev, h->sc_host->xmax, h->outer_tol)) break;
+        dprev = h->sc_host->dmax;
     }
     if (outer > outer_limit) outer = outer_limit;
     *h->sc_host = last;
