@@ -2449,6 +2449,82 @@ __device__ __forceinline__ void seg_finish_rl(SegAcc<Acc, kAstro>& S, int lane, 
     S.key = -1;
 }
 
+// Lane q of each group of K in {2, 4} lanes broadcast to the group (a quad
+// permutation: lane p of a quad reads lane (p & ~(K - 1)) + q), in VALU
+// cross-lane moves, without LDS. Every lane of the wave must be active.
+template <int K, int Q>
+__device__ __forceinline__ int32_t group_bcast(int32_t v)
+{
+    static_assert((K == 2 || K == 4) && Q < K, "groups of 2 or 4 lanes");
+    constexpr int s0 = Q, s1 = Q, s2 = (K == 4 ? 0 : 2) + Q, s3 = s2;
+    constexpr int ctrl = s0 | (s1 << 2) | (s2 << 4) | (s3 << 6);
+    return __builtin_amdgcn_mov_dpp(v, ctrl, 0xf, 0xf, false);
+}
+template <int K, int Q, typename V>
+__device__ __forceinline__ V group_bcast_v(V v)
+{
+    if constexpr (sizeof(V) == 8) {
+        const int64_t b = __builtin_bit_cast(int64_t, v);
+        const int32_t lo = group_bcast<K, Q>((int32_t)(b & 0xffffffff));
+        const int32_t hi = group_bcast<K, Q>((int32_t)(b >> 32));
+        return __builtin_bit_cast(V, (int64_t)(uint32_t)lo | ((int64_t)hi << 32));
+    } else if constexpr (sizeof(V) == 4) {
+        return __builtin_bit_cast(V, group_bcast<K, Q>(__builtin_bit_cast(int32_t, v)));
+    } else {
+        return (V)group_bcast<K, Q>((int32_t)v);
+    }
+}
+
+// The 12 coefficients of row ic outside the attitude section (astrometric,
+// instrumental, global) and its 6 instrumental indices, loaded by the K lanes
+// of its row slot together: lane r of the slot loads entries r, r + K, ...
+// and each entry is then broadcast to the K lanes (K in {2, 4}); for other
+// K every lane loads all of them.
+template <typename T, int K, bool CIDX>
+__device__ __forceinline__ void load_row_rl(const SysView& s, const T* __restrict__ val,
+                                            int64_t ic, int rj, T (&a)[kPar],
+                                            int32_t (&ix)[kInstr])
+{
+    constexpr int kNa = kAstro + kInstr + 1;  // 12 coefficients outside the attitude section
+    auto col = [](int e) { return e < kAstro ? e : kOffInstr + (e - kAstro); };
+    const int64_t m = s.m;
+    if constexpr (K == 2 || K == 4) {
+        constexpr int nv = kNa / K, ni = (kInstr + K - 1) / K;
+        T tv[nv];
+        int32_t ti[ni];
+#pragma unroll
+        for (int t = 0; t < nv; ++t) tv[t] = ldnt(&val[col(t * K + rj) * m + ic]);
+#pragma unroll
+        for (int t = 0; t < ni; ++t) {
+            const int j = t * K + rj < kInstr ? t * K + rj : kInstr - 1;
+            ti[t] = instr_of<CIDX>(s, j, ic);
+        }
+#pragma unroll
+        for (int t = 0; t < nv; ++t) {
+            a[col(t * K + 0)] = group_bcast_v<K, 0>(tv[t]);
+            a[col(t * K + 1)] = group_bcast_v<K, 1>(tv[t]);
+            if constexpr (K == 4) {
+                a[col(t * K + 2)] = group_bcast_v<K, 2>(tv[t]);
+                a[col(t * K + 3)] = group_bcast_v<K, 3>(tv[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < ni; ++t) {
+            if (t * K + 0 < kInstr) ix[t * K + 0] = group_bcast<K, 0>(ti[t]);
+            if (t * K + 1 < kInstr) ix[t * K + 1] = group_bcast<K, 1>(ti[t]);
+            if constexpr (K == 4) {
+                if (t * K + 2 < kInstr) ix[t * K + 2] = group_bcast<K, 2>(ti[t]);
+                if (t * K + 3 < kInstr) ix[t * K + 3] = group_bcast<K, 3>(ti[t]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < kNa; ++e) a[col(e)] = ldnt(&val[col(e) * m + ic]);
+#pragma unroll
+        for (int j = 0; j < kInstr; ++j) ix[j] = instr_of<CIDX>(s, j, ic);
+    }
+}
+
 // The fused pass of a K-tile after the attitude pre-pass (fused modes 2 and
 // 3) with the K right-hand sides of a row in K lanes: per row and live RHS r,
 // U~_r = (attitude part already in U) + the other sections' products with
@@ -2477,7 +2553,6 @@ __global__ __launch_bounds__(NT) void k_fused_rl(SysView s, const Acc* __restric
         live |= ((sc[r].done || (A2 && sc[r].beta_zero)) ? 0u : 1u) << r;
     if (live == 0) return;
     const T* __restrict__ val = static_cast<const T*>(s.val);
-    const int64_t m = s.m;
     const int64_t ninst = s.n_instr_cols;
     double* hist = reinterpret_cast<double*>(smem_raw);
     const Acc* xi = VP + s.instr_base * K;
@@ -2516,12 +2591,8 @@ __global__ __launch_bounds__(NT) void k_fused_rl(SysView s, const Acc* __restric
         const int64_t stc = star_of<CIDX>(s, ic);
         const int64_t st = i < re ? stc : kNoStar;
         T a[kPar];
-#pragma unroll
-        for (int c = 0; c < kPar; ++c)
-            if (c < kOffAtt || c >= kOffInstr) a[c] = ldnt(&val[c * m + ic]);
         int32_t ix[kInstr];
-#pragma unroll
-        for (int j = 0; j < kInstr; ++j) ix[j] = instr_of<CIDX>(s, j, ic);
+        load_row_rl<T, K, CIDX>(s, val, ic, rj, a, ix);
         const int64_t pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
         const Acc uo = U[pu * K + rj];
         const bool on = ok && lj;
