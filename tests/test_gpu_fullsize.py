@@ -1,8 +1,9 @@
 """GPU parity at the full workload sizes, in the configuration the benchmark
 times (system generated on the GPU, default options: fused mode 2, graph
-replay). The oracle cannot hold or iterate these systems, so it checks
-sampled outputs it can compute on their own, and the rest is checked through
-properties that hold at any size:
+replay). Here the oracle checks sampled outputs it can compute on their own,
+and the rest is checked through properties that hold at any size (the
+equal-iteration comparison with the oracle at 1e8 rows, which needs its
+OpenMP timing build and a minute per solve, is tests/test_gpu_fullsize_iterates.py):
   * aprod1 on sampled row ranges: the host generator produces just those rows
     and the oracle computes their products exactly;
   * aprod2 on sampled stars' astrometric columns, which only that star's rows
