@@ -587,6 +587,9 @@ __global__ __launch_bounds__(NT) void k_aprod2(SysView s, const VU* __restrict__
 // bucket order, the row reads it at datt[inv[i]] and keeps u~ in star order
 // (u[i]), so that u~ is read and written sequentially and the only permuted
 // access is that read.
+// us (optional): a star-order copy of the new u~ (us[i]), written
+// sequentially for the instrumental tail passes that follow, which then read
+// it without the permutation.
 enum { kAttX = 0, kAttX3 = 1, kAttPre = 2, kAttGather = 3 };
 template <typename T, typename Acc, int NT, bool LDSX, int AM, bool CIDX>
 __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ x,
@@ -595,7 +598,8 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
                                                Acc* __restrict__ gpart, double* __restrict__ part,
                                                int64_t hcols, const Scalars* __restrict__ sc,
                                                const int32_t* __restrict__ inv,
-                                               const Acc* __restrict__ datt = nullptr)
+                                               const Acc* __restrict__ datt = nullptr,
+                                               Acc* __restrict__ us = nullptr)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ Acc gred[NT / kWave];
@@ -678,6 +682,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
         else
             d -= coef * uo;
         if (ok) u[pu] = d;
+        if (ok && us) us[ic] = d;
         if (!ok) d = (Acc)0;
         ssq += (double)d * (double)d;
 

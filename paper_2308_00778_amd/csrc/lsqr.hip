@@ -130,11 +130,13 @@ struct Path {
     Acc* gpart = nullptr;  // [nb2] global-column partials
     Acc* vp3 = nullptr;    // [3 n_dfa] attitude section of vp interleaved by axis
     Acc* datt = nullptr;   // [m] fused mode 3: attitude part of A vp in bucket order
+    Acc* ustar = nullptr;  // [m] fused mode 2 with instrumental tail windows: u~ in star order
     int64_t hcols = 0;     // instrumental columns kept in the row passes' LDS histogram
     size_t lds = 0;        // dynamic LDS bytes of aprod2's main pass
     size_t lds_f = 0;      // dynamic LDS bytes of the fused pass
     int f_ldsx = 0;        // fused pass: instrumental slice of vp in LDS
     int64_t f_hcols = 0;   // fused pass: instrumental columns in its histogram
+    bool ustar_tried = false;
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0;
     bool ready = false;
@@ -443,11 +445,11 @@ void launch_fused_as(const lsqr_handle* h, Path<Acc>& P, const Acc* x3, hipStrea
     if (h->sv.star32)
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, LDSX, AM, true>), dim3(h->nb2), dim3(kBlock2),
                            P.lds_f, st, h->sv, (const Acc*)P.vp, x3, P.u, P.q, h->wb, P.gpart,
-                           h->part1, P.f_hcols, h->sc, inv, datt);
+                           h->part1, P.f_hcols, h->sc, inv, datt, P.ustar);
     else
         hipLaunchKernelGGL((k_fused<T, Acc, kBlock2, LDSX, AM, false>), dim3(h->nb2),
                            dim3(kBlock2), P.lds_f, st, h->sv, (const Acc*)P.vp, x3, P.u, P.q,
-                           h->wb, P.gpart, h->part1, P.f_hcols, h->sc, inv, datt);
+                           h->wb, P.gpart, h->part1, P.f_hcols, h->sc, inv, datt, P.ustar);
 }
 
 // Attitude part of aprod1 in bucket order (x3 must hold the interleaved
@@ -494,7 +496,11 @@ void launch_fused(const lsqr_handle* h, Path<Acc>& P, hipStream_t st, bool pre)
         if (x3) launch_fused_as<T, Acc, false, kAttX3>(h, P, x3, st);
         else launch_fused_as<T, Acc, false, kAttX>(h, P, x3, st);
     }
-    launch_instr_tail<T, Acc, 1, false>(h, P.u, row_map(h), P.q, P.f_hcols, h->sc, st);
+    // the tail windows read u~ in star order when the fused pass wrote a copy
+    if (P.ustar)
+        launch_instr_tail<T, Acc, 1, false>(h, P.ustar, nullptr, P.q, P.f_hcols, h->sc, st);
+    else
+        launch_instr_tail<T, Acc, 1, false>(h, P.u, row_map(h), P.q, P.f_hcols, h->sc, st);
 }
 
 // Attitude part of aprod2 in bucket order: per-workgroup LDS histograms of
@@ -688,6 +694,14 @@ lsqr_status prepare_path(lsqr_handle* h, Path<Acc>& P)
             LSQR_TRY(dalloc(&P.datt, h->sv.m));
         }
     }
+    // a fused pass that places u~ through the permutation and leaves
+    // instrumental tail windows: a star-order copy of u~ for the tails (an
+    // optimisation only: without the memory they read u~ through invperm)
+    if (!P.ustar && !P.ustar_tried && use_fused(h) && row_map(h) &&
+        P.f_hcols < h->sv.n_instr_cols) {
+        P.ustar_tried = true;
+        if (dalloc(&P.ustar, h->sv.m) != LSQR_OK) g_last_error.clear();
+    }
     return LSQR_OK;
 }
 
@@ -848,6 +862,8 @@ void release_path(Path<Acc>& P)
     dfree(P.gpart);
     dfree(P.vp3);
     dfree(P.datt);
+    dfree(P.ustar);
+    P.ustar_tried = false;
     P.ready = false;
 }
 
