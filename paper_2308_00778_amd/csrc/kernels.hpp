@@ -2228,14 +2228,16 @@ __global__ __launch_bounds__(kBlock) void k_zero_cols(int64_t n, double* __restr
 // 1024-thread workgroups (128 registers per lane) a multi-RHS tile would
 // reduce its star segments chunk by chunk instead of carrying 5K running sums;
 // the tiles run in 512 or 256 threads, which have the registers. AM as in the single-RHS pass (kAttPre after
-// k_att_dot over the tile's K right-hand sides).
+// k_att_dot over the tile's K right-hand sides). us (optional): a star-order
+// copy of the new U~ (us[i K + r]) for the instrumental tail passes.
 template <typename T, typename Acc, int K, int NT, bool LDSX, int AM, bool CIDX>
 __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__ VP,
                                                const Acc* __restrict__ X3, Acc* __restrict__ U,
                                                Acc* __restrict__ Q, const int64_t* __restrict__ wb,
                                                Acc* __restrict__ gpart, double* __restrict__ part,
                                                int64_t hcols, const Scalars* __restrict__ sc,
-                                               const int32_t* __restrict__ inv)
+                                               const int32_t* __restrict__ inv,
+                                               Acc* __restrict__ us = nullptr)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ Acc gred[K * (NT / kWave)];
@@ -2327,6 +2329,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
             // kAttPre: U already holds the attitude part minus coef U
             const Acc nu = AM == kAttPre ? d[r] + U[pu * K + r] : d[r] - coef[r] * U[pu * K + r];
             if (on) U[pu * K + r] = nu;
+            if (on && us) us[ic * K + r] = nu;
             d[r] = on ? nu : (Acc)0;
             ssq[r] += (double)d[r] * (double)d[r];
         }

@@ -219,6 +219,11 @@ struct lsqr_handle {
         double *gpart = nullptr, *part1 = nullptr, *partc = nullptr, *partdd = nullptr,
                *partxx = nullptr, *S2 = nullptr, *X3 = nullptr;
         float *U32 = nullptr, *VP32 = nullptr, *Q32 = nullptr, *gpart32 = nullptr, *X332 = nullptr;
+        // 1-RHS tiles whose fused pass leaves instrumental tail windows: the
+        // star-order copy of U the tails read (as the single-RHS path's
+        // ustar), or null
+        double* US1 = nullptr;
+        float* US1_32 = nullptr;
         Scalars* sc = nullptr;
         int32_t* flag = nullptr;
         hipGraphExec_t graph[17] = {};    // FP64 tiles, by K
@@ -1023,6 +1028,7 @@ void batch_free(lsqr_handle* h)
     dfree(B.gpart); dfree(B.part1); dfree(B.partc); dfree(B.partdd); dfree(B.partxx);
     dfree(B.sc); dfree(B.flag); dfree(B.S2); dfree(B.X3);
     dfree(B.U32); dfree(B.VP32); dfree(B.Q32); dfree(B.gpart32); dfree(B.X332);
+    dfree(B.US1); dfree(B.US1_32);
     B.kmax = 0;
     B.has64 = B.has32 = false;
 }
@@ -1058,6 +1064,22 @@ lsqr_status batch_alloc_once(lsqr_handle* h, int kmax, bool want64, bool want32)
         LSQR_TRY(dalloc(&B.X332, (int64_t)kAxes * h->sv.n_dfa * kmax));
         hipLaunchKernelGGL((k_fill<float>), dim3(h->nbc), dim3(kBlock), 0, h->stream, n * kmax,
                            B.Q32, 0.0f);
+    }
+    // the star-order copy for 1-RHS tiles (an optimisation: when the memory
+    // is short the single-RHS working vectors are released for it, as for the
+    // tile buffers, and without it the tails read U through the permutation)
+    if (use_fused(h) && batch_row_map(h) && h->sv.ni > 0) {
+        auto copy = [&](auto** buf, int64_t vbytes) {
+            int64_t hc1 = 0;
+            int ldsx = 0;
+            fused_lds_plan(h, 1, vbytes, &hc1, &ldsx);
+            if (hc1 >= h->sv.n_instr_cols || dalloc(buf, m) == LSQR_OK) return;
+            release_path(h->p64);
+            release_path(h->p32);
+            if (dalloc(buf, m) != LSQR_OK) g_last_error.clear();
+        };
+        if (want64) copy(&B.US1, 8);
+        if (want32) copy(&B.US1_32, 4);
     }
     HIP_TRY(hipGetLastError());
     B.kmax = kmax;
@@ -1095,6 +1117,7 @@ struct TileBufs {
     Acc *U, *VP, *Q, *gpart, *X3;
     hipGraphExec_t* graph;
     int* graph_chunk;
+    Acc* US1;  // star-order copy of U for 1-RHS tiles with tail windows, or null
 };
 
 template <typename Acc>
@@ -1104,14 +1127,14 @@ template <>
 TileBufs<double> tile_bufs<double>(lsqr_handle* h)
 {
     auto& B = h->batch;
-    return {B.U, B.VP, B.Q, B.gpart, B.X3, B.graph, B.graph_chunk};
+    return {B.U, B.VP, B.Q, B.gpart, B.X3, B.graph, B.graph_chunk, B.US1};
 }
 
 template <>
 TileBufs<float> tile_bufs<float>(lsqr_handle* h)
 {
     auto& B = h->batch;
-    return {B.U32, B.VP32, B.Q32, B.gpart32, B.X332, B.graph32, B.graph32_chunk};
+    return {B.U32, B.VP32, B.Q32, B.gpart32, B.X332, B.graph32, B.graph32_chunk, B.US1_32};
 }
 
 // Workgroup shape of the batched row passes over the star-aligned ranges: K <= 2
@@ -1247,16 +1270,17 @@ void batch_fused_as(lsqr_handle* h, const Acc* X3, int64_t hc, size_t lds, hipSt
         }
     if constexpr (K <= 8) {  // 16-RHS tiles are built in the RHS-across-lanes form only
         constexpr int NT = fused_nt<K, AM>();
+        Acc* us = K == 1 ? tb.US1 : nullptr;
         if (h->sv.star32)
             hipLaunchKernelGGL((batched::k_fused<T, Acc, K, NT, LDSX, AM, true>),
                                dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv,
                                (const Acc*)tb.VP, X3, tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc,
-                               B.sc, batch_row_map(h));
+                               B.sc, batch_row_map(h), us);
         else
             hipLaunchKernelGGL((batched::k_fused<T, Acc, K, NT, LDSX, AM, false>),
                                dim3(fused_grid<K, AM>(h)), dim3(NT), lds, st, h->sv,
                                (const Acc*)tb.VP, X3, tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc,
-                               B.sc, batch_row_map(h));
+                               B.sc, batch_row_map(h), us);
     }
 }
 
@@ -1295,7 +1319,12 @@ void batch_fused(lsqr_handle* h, hipStream_t st)
         if (X3) batch_fused_as<T, Acc, K, false, kAttX3>(h, X3, hc, lds, st);
         else batch_fused_as<T, Acc, K, false, kAttX>(h, X3, hc, lds, st);
     }
-    launch_instr_tail<T, Acc, K, false>(h, (const Acc*)tb.U, batch_row_map(h), tb.Q, hc, B.sc, st);
+    // a 1-RHS tile's tail windows read the star-order copy its fused pass wrote
+    if (K == 1 && tb.US1)
+        launch_instr_tail<T, Acc, K, false>(h, (const Acc*)tb.US1, nullptr, tb.Q, hc, B.sc, st);
+    else
+        launch_instr_tail<T, Acc, K, false>(h, (const Acc*)tb.U, batch_row_map(h), tb.Q, hc, B.sc,
+                                            st);
 }
 
 template <typename T, typename Acc, int K>
