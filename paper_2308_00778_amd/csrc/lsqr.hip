@@ -1563,12 +1563,18 @@ lsqr_status batch_refined_tile(lsqr_handle* h, const double* Bm, int64_t ldb, do
     memset(last, 0, sizeof last);
     for (int outer = 1; outer <= outer_limit && live; ++outer) {
         LSQR_TRY(batch_controls<K>(h, itn_limit, 0.0, 0.0, std::max(atol, 1e-300)));
-        // FP64 residual of the full problem of every live RHS
-        hipLaunchKernelGGL((batched::k_interleave_att<double, K>), dim3(h->nbc), dim3(kBlock), 0,
-                           st, (const double*)X, ldx, h->sv.att_base, h->sv.n_dfa, B.X3);
-        hipLaunchKernelGGL((batched::k_resid<T, float, K>), dim3(h->nb1), dim3(kBlock), 0, st,
-                           h->sv, (const double*)X, ldx, (const double*)B.X3, Bm, ldb, B.U32,
-                           B.part1, batch_row_map(h), live);
+        // FP64 residual of the full problem of every live RHS (B itself at the
+        // first step, where X = 0 and every RHS is live)
+        if (outer == 1) {
+            hipLaunchKernelGGL((batched::k_copy_ssq<float, K>), dim3(h->nb1), dim3(kBlock), 0, st,
+                               h->sv.m, Bm, ldb, B.U32, B.part1, batch_row_map(h));
+        } else {
+            hipLaunchKernelGGL((batched::k_interleave_att<double, K>), dim3(h->nbc), dim3(kBlock),
+                               0, st, (const double*)X, ldx, h->sv.att_base, h->sv.n_dfa, B.X3);
+            hipLaunchKernelGGL((batched::k_resid<T, float, K>), dim3(h->nb1), dim3(kBlock), 0, st,
+                               h->sv, (const double*)X, ldx, (const double*)B.X3, Bm, ldb, B.U32,
+                               B.part1, batch_row_map(h), live);
+        }
         LSQR_TRY((batch_init<T, float, K>(h)));
         LSQR_TRY((batch_run<T, float, K>(h, itn_limit, 0, host)));
         hipLaunchKernelGGL((batched::k_refine_update<K>), dim3(h->nbc), dim3(kBlock), 0, st, n,
@@ -2340,14 +2346,24 @@ lsqr_status lsqr_solve_refined(lsqr_handle* h, const double* b, double* x, int32
         // relative decrease of ||Abar^T r|| (tolerance atol) or the itn limit.
         LSQR_TRY(upload_controls(h, itn_limit, 0.0, 0.0, std::max(atol, 1e-300)));
         // FP64 residual of the full problem, stored as the FP32 start vector
-        const double* x3 = nullptr;
-        if (h->att_il && h->sv.natt > 0 && !h->generic) {
-            if (!h->x3_raw) LSQR_TRY(dalloc(&h->x3_raw, (int64_t)kAxes * h->sv.n_dfa));
-            launch_interleave_att<double>(h, x, h->x3_raw, nullptr, h->stream);
-            x3 = h->x3_raw;
+        // (b itself at the first step, where x = 0)
+        if (outer == 1) {
+            hipLaunchKernelGGL((k_copy_ssq<float>), dim3(h->nb1), dim3(kBlock), 0, h->stream,
+                               h->sv.m, b, P.u, h->part1, row_map(h));
+            if (h->nc > 0)
+                hipLaunchKernelGGL((k_copy_ssq<float>), dim3(1), dim3(kBlock), 0, h->stream,
+                                   h->nc, b + h->sv.m, P.u + h->sv.m, h->part1 + h->nb1,
+                                   (const int32_t*)nullptr);
+        } else {
+            const double* x3 = nullptr;
+            if (h->att_il && h->sv.natt > 0 && !h->generic) {
+                if (!h->x3_raw) LSQR_TRY(dalloc(&h->x3_raw, (int64_t)kAxes * h->sv.n_dfa));
+                launch_interleave_att<double>(h, x, h->x3_raw, nullptr, h->stream);
+                x3 = h->x3_raw;
+            }
+            launch_aprod1<float, double, double, float, A1_RESID>(
+                h, (const double*)x, P.u, b, nullptr, h->part1, h->stream, row_map(h), x3);
         }
-        launch_aprod1<float, double, double, float, A1_RESID>(h, (const double*)x, P.u, b, nullptr,
-                                                              h->part1, h->stream, row_map(h), x3);
         launch_init<float, float>(h, P, h->stream);
         HIP_TRY(hipGetLastError());
         LSQR_TRY(read_scalars(h));
