@@ -754,8 +754,19 @@ __global__ __launch_bounds__(NT) void k_instr_tail(SysView s, const Acc* __restr
     const int64_t m = s.m, w = c1 - c0;
     for (int64_t e = threadIdx.x; e < w * K; e += NT) hist[e] = 0.0;
     __syncthreads();
+    // the workgroup's rows [r0, r1) as one contiguous range per wave, walked
+    // in 64-row steps aligned to 64 rows: a line that two steps share is read
+    // by the same wave one step apart (an L2 hit), not by two waves at once
+    // (which fetches it twice; also where the caller's columns are not
+    // line-aligned)
+    static_assert(NT % kWave == 0, "whole waves");
     const int64_t r0 = blockIdx.x * m / gridDim.x, r1 = (blockIdx.x + 1) * m / gridDim.x;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += NT) {
+    constexpr int kW = NT / kWave;
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int64_t rb = r0 + (r1 - r0) * wv / kW, re = r0 + (r1 - r0) * (wv + 1) / kW;
+    for (int64_t i0 = rb & ~(int64_t)(kWave - 1); i0 < re; i0 += kWave) {
+        const int64_t i = i0 + lane;
+        if (i < rb || i >= re) continue;
         int32_t ix[kInstr];
         T a[kInstr];
 #pragma unroll
@@ -1488,13 +1499,14 @@ __global__ __launch_bounds__(kBlock) void k_bucket_starts(const int32_t* __restr
     }
 }
 
-// att_sorted[c][k] = values[off_att + c][perm[k]], c < 12 ;
-// tloc[k] = t of row perm[k] minus its bucket's first start.
+// att_sorted[c ld + k] = values[off_att + c][perm[k]], c < 12 (ld >= m: the
+// column stride of the copy) ; tloc[k] = t of row perm[k] minus its bucket's
+// first start.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val,
                                                         const int64_t* __restrict__ att, int64_t m,
                                                         const int32_t* __restrict__ perm,
-                                                        int64_t width, int off_att,
+                                                        int64_t width, int off_att, int64_t ld,
                                                         T* __restrict__ att_sorted,
                                                         int32_t* __restrict__ tloc)
 {
@@ -1503,7 +1515,7 @@ __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val
          k += (int64_t)gridDim.x * kBlock) {
         const int64_t i = perm[k];
 #pragma unroll
-        for (int c = 0; c < kAtt; ++c) att_sorted[c * m + k] = val[(off_att + c) * m + i];
+        for (int c = 0; c < kAtt; ++c) att_sorted[c * ld + k] = val[(off_att + c) * m + i];
         const int64_t t = att[i];
         tloc[k] = (int32_t)(t - (t / width) * width);
     }
@@ -1520,14 +1532,20 @@ __global__ __launch_bounds__(kBlock) void k_att_gather(const T* __restrict__ val
 // K / KS sweeps cover the tile. Frozen RHS (done) keep u~. The fused pass
 // (kAttPre) then adds the other sections. SEP: u is a separate bucket-order
 // vector that receives the attitude part alone (u[k] <- sum_c a_c x[col_c],
-// nothing read), for the fused pass's kAttGather form.
+// nothing read), for the fused pass's kAttGather form. att_sorted holds
+// coefficient c of bucket-order row k at c ld + k, ld a multiple of 64.
+// Row blocks start at the 64-row boundary at or below the bucket's first row
+// b0, so every wave reads whole 128-byte lines: a line shared by two waves
+// that load at the same time is fetched from memory twice (measured: 1.15x
+// the streamed bytes when the blocks started at b0). Lanes below b0 load row
+// b0 and store nothing.
 // PIPE: each thread issues the loads of its next row before the store of the
 // current one. A wave's vector-memory counter retires loads and stores in
 // issue order, so a store issued before the next row's loads would be waited
 // for together with them (one store round trip per row); after them it is
 // not.
 template <typename T, typename Acc, int K, int KS, int NT, bool SEP = false, bool PIPE = (K == 1)>
-__global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__ att_sorted,
+__global__ __launch_bounds__(NT) void k_att_dot(int64_t ld, const T* __restrict__ att_sorted,
                                                  const int32_t* __restrict__ tloc,
                                                  const int64_t* __restrict__ bstart,
                                                  int64_t width, int G, int64_t n_dfa,
@@ -1543,6 +1561,7 @@ __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__
     // columns past n_dfa - 1 are never referenced (t + 3 <= n_dfa - 1)
     const int64_t ncol = span < n_dfa - c0 ? span : n_dfa - c0;
     const int64_t b0 = bstart[bk], r1 = bstart[bk + 1];
+    const int64_t a0 = b0 & ~(int64_t)(kWave - 1);
     for (int s0 = 0; s0 < K; s0 += KS) {
         uint32_t live = 0;
         Acc coef[KS];
@@ -1591,13 +1610,15 @@ __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__
                 Acc uo[KS];
             };
             auto load = [&](Row& r, int64_t k) {
-                r.tl = ldnt(&tloc[k]);
+                const int64_t kk = k < b0 ? b0 : k;
+                r.tl = ldnt(&tloc[kk]);
 #pragma unroll
-                for (int c = 0; c < kAtt; ++c) r.a[c] = ldnt(&att_sorted[c * m + k]);
+                for (int c = 0; c < kAtt; ++c) r.a[c] = ldnt(&att_sorted[c * ld + kk]);
 #pragma unroll
-                for (int j = 0; j < KS; ++j) r.uo[j] = SEP ? (Acc)0 : u[k * K + s0 + j];
+                for (int j = 0; j < KS; ++j) r.uo[j] = SEP ? (Acc)0 : u[kk * K + s0 + j];
             };
             auto finish = [&](const Row& r, int64_t k) {
+                if (k < b0) return;
                 Acc d[KS];
                 row_dot_win(r.tl, r.a, d);
 #pragma unroll
@@ -1605,8 +1626,8 @@ __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__
                     if (KS == 1 || ((live >> j) & 1u))
                         u[k * K + s0 + j] = SEP ? d[j] : d[j] - coef[j] * r.uo[j];
             };
-            int64_t k0 = b0 + g * NT + threadIdx.x;
-            if (k0 < r1) {
+            int64_t k0 = a0 + g * NT + threadIdx.x;
+            if (b0 < r1 && k0 < r1) {
                 const int64_t klast = k0 + (r1 - 1 - k0) / stride * stride;
                 auto next = [&](int64_t k) { return k < klast ? k + stride : klast; };
                 Row A, B, C;
@@ -1637,11 +1658,12 @@ __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__
                 }
             }
         } else {
-            for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += stride) {
+            for (int64_t k = a0 + g * NT + threadIdx.x; k < r1; k += stride) {
+                if (k < b0) continue;
                 const int64_t tl = ldnt(&tloc[k]);
                 T a[kAtt];
 #pragma unroll
-                for (int c = 0; c < kAtt; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
+                for (int c = 0; c < kAtt; ++c) a[c] = ldnt(&att_sorted[c * ld + k]);
                 Acc d[KS];
                 row_dot_win(tl, a, d);
 #pragma unroll
@@ -1672,9 +1694,11 @@ __global__ __launch_bounds__(NT) void k_att_dot(int64_t m, const T* __restrict__
 // PIPE: each thread issues the loads of its next row before the atomics of
 // the current one (with GATHER, the current row's read through the
 // permutation first: its index came with the previous loads).
+// att_sorted and the row blocks as in k_att_dot (64-row aligned; lanes below
+// the bucket's first row load that row with a zero weight).
 template <typename T, typename Acc, int K, int KS, int NT, bool GATHER = false,
           bool PIPE = (K == 1)>
-__global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict__ att_sorted,
+__global__ __launch_bounds__(NT) void k_att_hist(int64_t ld, const T* __restrict__ att_sorted,
                                                   const int32_t* __restrict__ tloc,
                                                   const int64_t* __restrict__ bstart,
                                                   int64_t width, int G, const Acc* __restrict__ U,
@@ -1688,6 +1712,7 @@ __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict_
     const int64_t span = width + kParAxis - 1;
     const int64_t bk = blockIdx.x / G, g = blockIdx.x - bk * G;
     const int64_t b0 = bstart[bk], r1 = bstart[bk + 1];
+    const int64_t a0 = b0 & ~(int64_t)(kWave - 1);
     for (int s0 = 0; s0 < K; s0 += KS) {
         uint32_t live = 0;
 #pragma unroll
@@ -1720,29 +1745,31 @@ __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict_
                 double uk[KS];
             };
             auto load = [&](Row& r, int64_t k) {
-                r.tl = ldnt(&tloc[k]);
-                r.ku = GATHER ? (int64_t)ldnt(&perm[k]) : k;
+                const int64_t kk = k < b0 ? b0 : k;
+                r.tl = ldnt(&tloc[kk]);
+                r.ku = GATHER ? (int64_t)ldnt(&perm[kk]) : kk;
 #pragma unroll
-                for (int c = 0; c < kAtt; ++c) r.a[c] = ldnt(&att_sorted[c * m + k]);
+                for (int c = 0; c < kAtt; ++c) r.a[c] = ldnt(&att_sorted[c * ld + kk]);
                 if (!GATHER)
 #pragma unroll
-                    for (int j = 0; j < KS; ++j) r.uk[j] = (double)U[k * K + s0 + j];
+                    for (int j = 0; j < KS; ++j) r.uk[j] = (double)U[kk * K + s0 + j];
             };
             auto value = [&](Row& r, double w) {
 #pragma unroll
                 for (int j = 0; j < KS; ++j)
                     r.uk[j] = w * (GATHER ? (double)U[r.ku * K + s0 + j] : r.uk[j]);
             };
-            int64_t k0 = b0 + g * NT + threadIdx.x;
-            if (k0 < r1) {
+            int64_t k0 = a0 + g * NT + threadIdx.x;
+            if (b0 < r1 && k0 < r1) {
                 const int64_t klast = k0 + (r1 - 1 - k0) / stride * stride;
-                // next row and its weight (0 for a repeat of the last row)
+                // next row and its weight (0 for a repeat of the last row;
+                // only a thread's first row can lie below b0)
                 auto next = [&](int64_t k) { return k < klast ? k + stride : klast; };
                 Row A, B, C;
                 int64_t k1 = next(k0);
                 load(A, k0);
                 load(B, k1);
-                value(A, 1.0);
+                value(A, k0 >= b0 ? 1.0 : 0.0);
                 for (;;) {
                     const int64_t k2 = next(k1);
                     value(B, k1 > k0 ? 1.0 : 0.0);
@@ -1768,7 +1795,8 @@ __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict_
                 }
             }
         } else {
-            for (int64_t k = b0 + g * NT + threadIdx.x; k < r1; k += stride) {
+            for (int64_t k = a0 + g * NT + threadIdx.x; k < r1; k += stride) {
+                if (k < b0) continue;
                 const int64_t tl = ldnt(&tloc[k]);
                 const int64_t ku = GATHER ? (int64_t)ldnt(&perm[k]) : k;
                 double uk[KS];
@@ -1776,7 +1804,7 @@ __global__ __launch_bounds__(NT) void k_att_hist(int64_t m, const T* __restrict_
                 for (int j = 0; j < KS; ++j) uk[j] = (double)U[ku * K + s0 + j];
                 T a[kAtt];  // all loads issued before the first atomic
 #pragma unroll
-                for (int c = 0; c < kAtt; ++c) a[c] = ldnt(&att_sorted[c * m + k]);
+                for (int c = 0; c < kAtt; ++c) a[c] = ldnt(&att_sorted[c * ld + k]);
                 scatter(tl, a, uk);
             }
         }

@@ -189,7 +189,8 @@ struct lsqr_handle {
     int32_t* perm = nullptr;      // [m] rows in bucket order
     int32_t* invperm = nullptr;   // [m] bucket-order position of each row
     int32_t* tloc = nullptr;      // [m] attitude start minus its bucket's first start
-    void* att_sorted = nullptr;   // [12][m] attitude coefficients in bucket order
+    void* att_sorted = nullptr;   // [12][att_ld] attitude coefficients in bucket order
+    int64_t att_ld = 0;           // its column stride: m rounded up to 64 rows
     int64_t* bstart = nullptr;    // [nbk + 1] first position of each bucket
     int64_t nbk = 0;              // buckets
     int64_t bwidth = 0;           // attitude starts per bucket (W)
@@ -465,7 +466,7 @@ void launch_att_dot_as(const lsqr_handle* h, Path<Acc>& P, hipStream_t st)
 {
     const size_t lds = (size_t)(kAxes * att_span(h)) * sizeof(Acc);
     hipLaunchKernelGGL((k_att_dot<T, Acc, 1, 1, kAttBlock, SEP, PIPE>), dim3(att_slices(h)),
-                       dim3(kAttBlock), lds, st, h->sv.m, (const T*)h->att_sorted,
+                       dim3(kAttBlock), lds, st, h->att_ld, (const T*)h->att_sorted,
                        (const int32_t*)h->tloc, (const int64_t*)h->bstart, h->bwidth, h->att_g,
                        h->sv.n_dfa, (const Acc*)P.vp3, SEP ? P.datt : P.u, h->sc);
 }
@@ -519,7 +520,7 @@ void launch_att_pass(lsqr_handle* h, const Acc* ub, Acc* q, const Scalars* sc, h
     auto go = [&](auto gather, auto pipe) {
         hipLaunchKernelGGL((k_att_hist<T, Acc, 1, 1, kAttBlock, decltype(gather)::value,
                                        decltype(pipe)::value>),
-                           dim3(att_slices(h)), dim3(kAttBlock), lds, st, h->sv.m,
+                           dim3(att_slices(h)), dim3(kAttBlock), lds, st, h->att_ld,
                            (const T*)h->att_sorted, (const int32_t*)h->tloc,
                            (const int64_t*)h->bstart, h->bwidth, h->att_g, ub, h->S2, sc, gperm);
     };
@@ -764,7 +765,9 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
     LSQR_TRY(dalloc(&h->bstart, h->nbk + 1));
     LSQR_TRY(dalloc(&h->S2, att_slices(h) * kAxes * att_span(h)));
     T* att_sorted = nullptr;
-    LSQR_TRY(dalloc(&att_sorted, (int64_t)kAxes * kParAxis * m));
+    // columns 64-row aligned, so that the bucket-order passes read whole lines
+    h->att_ld = cdiv(m, (int64_t)kWave) * kWave;
+    LSQR_TRY(dalloc(&att_sorted, (int64_t)kAxes * kParAxis * h->att_ld));
     h->att_sorted = att_sorted;
     LSQR_TRY(dalloc(&keys, m));
     lsqr_status rc = dalloc(&rows, m);
@@ -782,8 +785,8 @@ lsqr_status prepare_att_sorted(lsqr_handle* h)
                                       bits, st);
     if (rc == LSQR_OK && e == hipSuccess) {
         hipLaunchKernelGGL((k_att_gather<T>), gm, bb, 0, st, (const T*)h->sv.val, h->sv.att, m,
-                           (const int32_t*)h->perm, h->bwidth, h->sv.off_att, att_sorted,
-                           h->tloc);
+                           (const int32_t*)h->perm, h->bwidth, h->sv.off_att, h->att_ld,
+                           att_sorted, h->tloc);
         hipLaunchKernelGGL(k_invert_perm, gm, bb, 0, st, (const int32_t*)h->perm, m, h->invperm);
         hipLaunchKernelGGL(k_bucket_starts, dim3(std::min<int64_t>(cdiv(m + 1, kBlock), 65536)), bb,
                            0, st, (const int32_t*)skeys, m, h->nbk, h->bstart);
@@ -1204,7 +1207,7 @@ void batch_att_pass(lsqr_handle* h, hipStream_t st)
     const int ks = std::min(2, att_sweep<K>(h));
     by_sweep<K>(ks, [&](auto KS) {
         hipLaunchKernelGGL((k_att_hist<T, Acc, K, KS(), kAttBlock>), dim3(att_slices(h)),
-                           dim3(kAttBlock), (size_t)(kAxes * att_span(h) * 8 * ks), st, h->sv.m,
+                           dim3(kAttBlock), (size_t)(kAxes * att_span(h) * 8 * ks), st, h->att_ld,
                            (const T*)h->att_sorted, (const int32_t*)h->tloc,
                            (const int64_t*)h->bstart, h->bwidth, h->att_g, (const Acc*)tb.U,
                            B.S2, B.sc, (const int32_t*)nullptr);
@@ -1306,7 +1309,7 @@ void batch_fused(lsqr_handle* h, hipStream_t st)
         by_sweep<K>(ks, [&](auto KS) {
             hipLaunchKernelGGL((k_att_dot<T, Acc, K, KS(), kAttBlock>), dim3(att_slices(h)),
                                dim3(kAttBlock), (size_t)(kAxes * att_span(h) * sizeof(Acc) * ks),
-                               st, h->sv.m, (const T*)h->att_sorted, (const int32_t*)h->tloc,
+                               st, h->att_ld, (const T*)h->att_sorted, (const int32_t*)h->tloc,
                                (const int64_t*)h->bstart, h->bwidth, h->att_g, h->sv.n_dfa, X3,
                                tb.U, (const Scalars*)B.sc);
         });
