@@ -318,6 +318,57 @@ def _solve_fixed(torch_cuda, name, itn, graph, variant, interleave=1, fused=2, c
         assert abs(a - r) <= tol * abs(r), (k, a, r)
 
 
+# Buckets shorter than a wave, and empty ones. The bucket-order passes start
+# each bucket's row blocks on the 64-row boundary at or below its first row:
+# here most lanes' rows lie before their bucket (they load its first row and
+# contribute nothing), many threads have no row of their own (19 and 149
+# buckets of about 50 rows on "short_stars" and "wide_instr"), and in
+# "sparse_rows" (39 rows over 197 attitude starts, 99 buckets) most buckets
+# hold no row. aprod2 (the attitude pass), a fixed-iteration solve (the
+# attitude pre-pass) and a 2-RHS k-tile against the oracle.
+TINY_BUCKETS = {"short_stars": 36, "wide_instr": 290, "sparse_rows": 150}
+_SPARSE = synth.tiny(seed=31, n_stars=20, obs=(1, 3), n_dfa=200, n_instr_cols=5)
+
+
+@pytest.mark.parametrize("name", list(TINY_BUCKETS))
+def test_tiny_buckets_parity(torch_cuda, name):
+    torch = torch_cuda
+    if name == "sparse_rows":
+        if name not in _SYS:
+            S = synth.make_system(_SPARSE)
+            _SYS[name] = (S, oracle.OracleSystem.from_synth(S))
+    S, o = system(name)
+    nbk, itn = TINY_BUCKETS[name], 10
+    say(f"tiny buckets: {name} m={S.m} n={o.n} att_buckets={nbk}")
+    rng = np.random.default_rng(9)
+    y = rng.standard_normal(o.m)
+    x0 = rng.standard_normal(o.n)
+    want = o.aprod2(y, x0)
+    bound = abs_system(S).aprod2(np.abs(y), np.abs(x0))
+    g = gpu_system(torch, S)
+    g.set_option("att_buckets", nbk)
+    g.set_option("tests", 0)
+    xd = torch.from_numpy(x0).cuda()
+    g.aprod2(xd, torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    got = xd.cpu().numpy()
+    c = 2.0 * np.sqrt(S.m) + 32
+    assert np.all(np.abs(got - want) <= c * EPS * bound + 1e-300)
+    bs = [_b(S, o, rhs=j) for j in range(2)]
+    refs = [o.lsqr(b, itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)[0] for b in bs]
+    x, info = g.solve(torch.from_numpy(bs[0]).cuda(), itn, atol=0.0, btol=0.0)
+    torch.cuda.synchronize()
+    assert info.itn == itn and rel_inf(x.cpu().numpy(), refs[0]) <= 1e-10
+    g.set_option("ktile", 2)
+    X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(np.stack(bs, axis=1))).cuda(),
+                               itn, 0.0, 0.0)
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    g.close()
+    for j in range(2):
+        assert infos[j].itn == itn and rel_inf(Xh[:, j], refs[j]) <= 1e-10, j
+
+
 # Iteration counts before convergence: the variance sums (w/rho)^2 over all
 # iterations, and past convergence those terms depend on rounding like the
 # anorm/acond estimates. On "ragged" the oracle and SciPy's LSQR (calc_var)
