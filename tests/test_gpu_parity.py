@@ -327,7 +327,7 @@ def _solve_fixed(torch_cuda, name, itn, graph, variant, interleave=1, fused=2, c
 # hold no row. aprod2 (the attitude pass), a fixed-iteration solve (the
 # attitude pre-pass) and a 2-RHS k-tile against the oracle.
 TINY_BUCKETS = {"short_stars": 36, "wide_instr": 290, "sparse_rows": 150}
-_SPARSE = synth.tiny(seed=31, n_stars=20, obs=(1, 3), n_dfa=200, n_instr_cols=5)
+_SPARSE = synth.tiny(seed=31, n_stars=20, obs=(1, 3), n_dfa=200, n_instr_cols=8)
 
 
 @pytest.mark.parametrize("name", list(TINY_BUCKETS))
