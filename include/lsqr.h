@@ -205,8 +205,12 @@ lsqr_status lsqr_destroy(lsqr_handle* h);
  *   LSQR_OPT_PIPELINE     1 (default): each thread of the single-RHS bucket-order
  *                         passes issues the loads of its next row before the
  *                         store (or LDS atomics) of the current one, so that no
- *                         row waits for the previous row's store; 0: one row at
- *                         a time (same results)
+ *                         row waits for the previous row's store, and the
+ *                         RHS-across-lanes fused pass of 4-RHS tiles (and of
+ *                         2-RHS tiles unless both values and vectors are
+ *                         FP64) issues the next row step's loads before the
+ *                         gathers of the current one; 0: one row at a time
+ *                         (same results)
  *   LSQR_OPT_RHS_LANES    batched k-tiles of K >= 2 RHS in fused modes 2 and 3:
  *                         1 (default) the fused pass and the first aprod2 of a
  *                         solve put the K right-hand sides of a row in K lanes

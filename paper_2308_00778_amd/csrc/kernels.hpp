@@ -2516,6 +2516,62 @@ __device__ __forceinline__ V group_bcast_v(V v)
 // of its row slot together: lane r of the slot loads entries r, r + K, ...
 // and each entry is then broadcast to the K lanes (K in {2, 4}); for other
 // K every lane loads all of them.
+constexpr int kNaRl = kAstro + kInstr + 1;  // coefficients outside the attitude section
+template <int K>
+constexpr int rl_nv() { return kNaRl / K; }                // value loads per lane (K = 2, 4)
+template <int K>
+constexpr int rl_ni() { return (kInstr + K - 1) / K; }     // index loads per lane
+__device__ __forceinline__ constexpr int rl_col(int e)
+{
+    return e < kAstro ? e : kOffInstr + (e - kAstro);
+}
+
+// The loads of load_row_rl for K in {2, 4}, before the broadcast: lane r of a
+// row slot loads entries r, r + K, ... of the 12 coefficients and 6 indices.
+template <typename T, int K, bool CIDX>
+__device__ __forceinline__ void load_raw_rl(const SysView& s, const T* __restrict__ val,
+                                            int64_t ic, int rj, T (&tv)[rl_nv<K>()],
+                                            int32_t (&ti)[rl_ni<K>()])
+{
+    static_assert(K == 2 || K == 4, "row slots of 2 or 4 lanes");
+    const int64_t m = s.m;
+#pragma unroll
+    for (int t = 0; t < rl_nv<K>(); ++t) tv[t] = ldnt(&val[rl_col(t * K + rj) * m + ic]);
+#pragma unroll
+    for (int t = 0; t < rl_ni<K>(); ++t) {
+        const int j = t * K + rj < kInstr ? t * K + rj : kInstr - 1;
+        ti[t] = instr_of<CIDX>(s, j, ic);
+    }
+}
+
+// The broadcast of load_row_rl: each loaded entry to the K lanes of its slot.
+template <typename T, int K>
+__device__ __forceinline__ void bcast_row_rl(const T (&tv)[rl_nv<K>()],
+                                             const int32_t (&ti)[rl_ni<K>()], T (&a)[kPar],
+                                             int32_t (&ix)[kInstr])
+{
+    constexpr int nv = rl_nv<K>(), ni = rl_ni<K>();
+    auto col = [](int e) { return rl_col(e); };
+#pragma unroll
+    for (int t = 0; t < nv; ++t) {
+        a[col(t * K + 0)] = group_bcast_v<K, 0>(tv[t]);
+        a[col(t * K + 1)] = group_bcast_v<K, 1>(tv[t]);
+        if constexpr (K == 4) {
+            a[col(t * K + 2)] = group_bcast_v<K, 2>(tv[t]);
+            a[col(t * K + 3)] = group_bcast_v<K, 3>(tv[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < ni; ++t) {
+        if (t * K + 0 < kInstr) ix[t * K + 0] = group_bcast<K, 0>(ti[t]);
+        if (t * K + 1 < kInstr) ix[t * K + 1] = group_bcast<K, 1>(ti[t]);
+        if constexpr (K == 4) {
+            if (t * K + 2 < kInstr) ix[t * K + 2] = group_bcast<K, 2>(ti[t]);
+            if (t * K + 3 < kInstr) ix[t * K + 3] = group_bcast<K, 3>(ti[t]);
+        }
+    }
+}
+
 template <typename T, int K, bool CIDX>
 __device__ __forceinline__ void load_row_rl(const SysView& s, const T* __restrict__ val,
                                             int64_t ic, int rj, T (&a)[kPar],
@@ -2569,7 +2625,14 @@ __device__ __forceinline__ void load_row_rl(const SysView& s, const T* __restric
 // histogram [hcols][K], the rest to k_instr_tail) and global (partials
 // gpart[blk][K]) columns. A2: aprod2 alone (Q += A^T U, U not changed, no
 // sums of squares), the start of a tile's solve. U row i at U[inv[i] K + r].
-template <typename T, typename Acc, int K, int NT, bool LDSX, bool CIDX, bool A2>
+// PIPE (K in {2, 4}, not A2): two row steps in flight per wave. A step waits
+// for its coefficient, index, star and permutation loads, then for the
+// gathers they address (U through inv, the astrometric and instrumental
+// values of VP); the loads of the next step are issued before the gathers of
+// the current one, so each step waits one round trip instead of two. Each
+// step keeps its loads in its own registers (no copies, which would wait).
+template <typename T, typename Acc, int K, int NT, bool LDSX, bool CIDX, bool A2,
+          bool PIPE = false>
 __global__ __launch_bounds__(NT) void k_fused_rl(SysView s, const Acc* __restrict__ VP,
                                                   Acc* __restrict__ U, Acc* __restrict__ Q,
                                                   const int64_t* __restrict__ wb,
@@ -2617,19 +2680,13 @@ __global__ __launch_bounds__(NT) void k_fused_rl(SysView s, const Acc* __restric
 #pragma unroll
         for (int j = 0; j < kAstro; ++j) dst[j * K] += tot[j];
     };
-    // R-row steps aligned to R rows (every coefficient stream read in whole
-    // R-row pieces); slots outside [rb, re) use a clamped row and contribute
-    // nothing
-    for (int64_t r0 = rb < re ? (rb & ~(int64_t)(R - 1)) : re; r0 < re; r0 += R) {
+    // one R-row step: the row of slot `slot` (clamped), its coefficients,
+    // indices, star and place in U already loaded
+    auto step = [&](int64_t r0, int64_t stc, const T (&a)[kPar], const int32_t (&ix)[kInstr],
+                    int64_t pu) {
         const int64_t i = r0 + slot;
         const bool ok = i >= rb && i < re;
-        const int64_t ic = i < rb ? rb : (i < re ? i : re - 1);
-        const int64_t stc = star_of<CIDX>(s, ic);
         const int64_t st = i < re ? stc : kNoStar;
-        T a[kPar];
-        int32_t ix[kInstr];
-        load_row_rl<T, K, CIDX>(s, val, ic, rj, a, ix);
-        const int64_t pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
         const Acc uo = U[pu * K + rj];
         const bool on = ok && lj;
         Acc d;
@@ -2662,6 +2719,64 @@ __global__ __launch_bounds__(NT) void k_fused_rl(SysView s, const Acc* __restric
 #pragma unroll
         for (int j = 0; j < kAstro; ++j) pa[j] = (Acc)a[j] * d;
         seg_chunk_rl<Acc, K>(seg, st, pa, lane, astro_emit);
+    };
+    // R-row steps aligned to R rows (every coefficient stream read in whole
+    // R-row pieces); slots outside [rb, re) use a clamped row and contribute
+    // nothing
+    auto row_of = [&](int64_t r0) {
+        const int64_t i = r0 + slot;
+        return i < rb ? rb : (i < re ? i : re - 1);
+    };
+    const int64_t rstart = rb < re ? (rb & ~(int64_t)(R - 1)) : re;
+    if constexpr (PIPE && (K == 2 || K == 4) && !A2) {
+        struct Raw {
+            T tv[rl_nv<K>()];
+            int32_t ti[rl_ni<K>()];
+            int64_t stc, pu;
+        };
+        auto load = [&](Raw& w, int64_t r0) {
+            const int64_t ic = row_of(r0);
+            w.stc = star_of<CIDX>(s, ic);
+            load_raw_rl<T, K, CIDX>(s, val, ic, rj, w.tv, w.ti);
+            w.pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
+        };
+        auto run = [&](const Raw& w, int64_t r0) {
+            T a[kPar];
+            int32_t ix[kInstr];
+            bcast_row_rl<T, K>(w.tv, w.ti, a, ix);
+            step(r0, w.stc, a, ix, w.pu);
+        };
+        // r0, re and R are uniform over the wave, so are the branches
+        if (rstart < re) {
+            Raw A, B;
+            int64_t r0 = rstart;
+            load(A, r0);
+            for (;;) {
+                const int64_t r1 = r0 + R;
+                if (r1 < re) load(B, r1);
+                __builtin_amdgcn_sched_barrier(0);
+                run(A, r0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (r1 >= re) break;
+                const int64_t r2 = r1 + R;
+                if (r2 < re) load(A, r2);
+                __builtin_amdgcn_sched_barrier(0);
+                run(B, r1);
+                __builtin_amdgcn_sched_barrier(0);
+                if (r2 >= re) break;
+                r0 = r2;
+            }
+        }
+    } else {
+        for (int64_t r0 = rstart; r0 < re; r0 += R) {
+            const int64_t ic = row_of(r0);
+            const int64_t stc = star_of<CIDX>(s, ic);
+            T a[kPar];
+            int32_t ix[kInstr];
+            load_row_rl<T, K, CIDX>(s, val, ic, rj, a, ix);
+            const int64_t pu = inv ? (int64_t)ldnt(&inv[ic]) : ic;
+            step(r0, stc, a, ix, pu);
+        }
     }
     seg_finish_rl<Acc, K>(seg, lane, astro_emit);
     gsum = rhs_sum<K>(gsum);

@@ -1259,16 +1259,28 @@ void batch_fused_as(lsqr_handle* h, const Acc* X3, int64_t hc, size_t lds, hipSt
     const TileBufs<Acc> tb = tile_bufs<Acc>(h);
     if constexpr (AM == kAttPre)
         if (K >= 2 && rhs_lanes_on(h)) {  // the K right-hand sides of a row in K lanes
-            if (h->sv.star32)
-                hipLaunchKernelGGL((batched::k_fused_rl<T, Acc, K, kBlock2, LDSX, true, false>),
-                                   dim3(h->nb2), dim3(kBlock2), lds, st, h->sv, (const Acc*)tb.VP,
-                                   tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc,
-                                   batch_row_map(h));
-            else
-                hipLaunchKernelGGL((batched::k_fused_rl<T, Acc, K, kBlock2, LDSX, false, false>),
-                                   dim3(h->nb2), dim3(kBlock2), lds, st, h->sv, (const Acc*)tb.VP,
-                                   tb.U, tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc,
-                                   batch_row_map(h));
+            // two row steps in flight (LSQR_OPT_PIPELINE): K = 4, and K = 2
+            // except with FP64 values and vectors, whose second register set
+            // would spill
+            auto go = [&](auto pipe) {
+                constexpr bool P = decltype(pipe)::value;
+                if (h->sv.star32)
+                    hipLaunchKernelGGL(
+                        (batched::k_fused_rl<T, Acc, K, kBlock2, LDSX, true, false, P>),
+                        dim3(h->nb2), dim3(kBlock2), lds, st, h->sv, (const Acc*)tb.VP, tb.U,
+                        tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc, batch_row_map(h));
+                else
+                    hipLaunchKernelGGL(
+                        (batched::k_fused_rl<T, Acc, K, kBlock2, LDSX, false, false, P>),
+                        dim3(h->nb2), dim3(kBlock2), lds, st, h->sv, (const Acc*)tb.VP, tb.U,
+                        tb.Q, h->wb, tb.gpart, B.part1, hc, B.sc, batch_row_map(h));
+            };
+            if constexpr (K == 4 || (K == 2 && (sizeof(T) == 4 || sizeof(Acc) == 4))) {
+                if (h->pipe) go(std::true_type());
+                else go(std::false_type());
+            } else {
+                go(std::false_type());
+            }
             return;
         }
     if constexpr (K <= 8) {  // 16-RHS tiles are built in the RHS-across-lanes form only
