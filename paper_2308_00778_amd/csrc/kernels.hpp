@@ -113,6 +113,20 @@ __device__ __forceinline__ T ldnt(const T* p)
     return __builtin_nontemporal_load(p);
 }
 
+// A load of a streamed column: nontemporal, or PLAIN where the columns do not
+// start on a 128-byte line, so that the line a wave's step shares with its
+// next step stays in L2 until that step reads it (nontemporal lines go
+// first: at 1e9 rows, m = 8 mod 16, about 2-3 ms less per instrumental tail
+// window of 10.7-11.4 ms; with aligned columns plain loads gain nothing).
+template <bool PLAIN, typename T>
+__device__ __forceinline__ T ld_stream(const T* p)
+{
+    if constexpr (PLAIN)
+        return *p;
+    else
+        return ldnt(p);
+}
+
 // ---------------------------------------------------------------- reductions
 // Deterministic block sum of one double per thread; result valid on thread 0.
 __device__ __forceinline__ double block_sum(double v, double* lds /* >= kWavesPerBlock */)
@@ -736,7 +750,7 @@ __global__ __launch_bounds__(NT) void k_fused(SysView s, const Acc* __restrict__
 // RHS (done or beta_zero) are skipped.
 // GEN: section sizes from the system view (general layouts); otherwise the
 // full layout's constants.
-template <typename T, typename Acc, int K, bool SQUARE, int NT, bool GEN>
+template <typename T, typename Acc, int K, bool SQUARE, int NT, bool GEN, bool PLAIN = false>
 __global__ __launch_bounds__(NT) void k_instr_tail(SysView s, const Acc* __restrict__ U,
                                                     const int32_t* __restrict__ inv,
                                                     Acc* __restrict__ Q, int64_t c0, int64_t c1,
@@ -771,8 +785,8 @@ __global__ __launch_bounds__(NT) void k_instr_tail(SysView s, const Acc* __restr
         T a[kInstr];
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) {
-            ix[j] = j < ni ? ldnt(&s.instr[j * m + i]) : -1;
-            a[j] = j < ni ? ldnt(&val[(oins + j) * m + i]) : (T)0;
+            ix[j] = j < ni ? ld_stream<PLAIN>(&s.instr[j * m + i]) : -1;
+            a[j] = j < ni ? ld_stream<PLAIN>(&val[(oins + j) * m + i]) : (T)0;
         }
         double u[K];
         if (!SQUARE) {

@@ -332,16 +332,27 @@ void launch_instr_tail(const lsqr_handle* h, const Acc* U, const int32_t* inv, A
 {
     const int64_t ninst = h->sv.ni > 0 ? h->sv.n_instr_cols : 0;
     const int64_t tw = std::max<int64_t>(1, kLdsInstrBudget / (8 * K));
+    // plain loads where the caller's instrumental columns are not line-aligned
+    const uintptr_t vb = (uintptr_t)h->sv.val, ib = (uintptr_t)h->sv.instr;
+    const bool lined = vb % 128 == 0 && ib % 128 == 0 &&
+                       (h->sv.m * (int64_t)sizeof(T)) % 128 == 0 && (h->sv.m * 4) % 128 == 0;
     for (int64_t c0 = hcols; c0 < ninst; c0 += tw) {
         const int64_t c1 = std::min(ninst, c0 + tw);
-        if (h->generic)
-            hipLaunchKernelGGL((k_instr_tail<T, Acc, K, SQUARE, kAttBlock, true>), dim3(h->num_cu),
-                               dim3(kAttBlock), (size_t)((c1 - c0) * K * 8), st, h->sv, U, inv, Q,
-                               c0, c1, sc);
-        else
-            hipLaunchKernelGGL((k_instr_tail<T, Acc, K, SQUARE, kAttBlock, false>),
+        auto go = [&](auto gen, auto plain) {
+            hipLaunchKernelGGL((k_instr_tail<T, Acc, K, SQUARE, kAttBlock, decltype(gen)::value,
+                                             decltype(plain)::value>),
                                dim3(h->num_cu), dim3(kAttBlock), (size_t)((c1 - c0) * K * 8), st,
                                h->sv, U, inv, Q, c0, c1, sc);
+        };
+        using Y = std::true_type;
+        using N = std::false_type;
+        if (h->generic) {
+            if (lined) go(Y(), N());
+            else go(Y(), Y());
+        } else {
+            if (lined) go(N(), N());
+            else go(N(), Y());
+        }
     }
 }
 
