@@ -2525,11 +2525,6 @@ __device__ __forceinline__ V group_bcast_v(V v)
     }
 }
 
-// The 12 coefficients of row ic outside the attitude section (astrometric,
-// instrumental, global) and its 6 instrumental indices, loaded by the K lanes
-// of its row slot together: lane r of the slot loads entries r, r + K, ...
-// and each entry is then broadcast to the K lanes (K in {2, 4}); for other
-// K every lane loads all of them.
 constexpr int kNaRl = kAstro + kInstr + 1;  // coefficients outside the attitude section
 template <int K>
 constexpr int rl_nv() { return kNaRl / K; }                // value loads per lane (K = 2, 4)
@@ -2586,46 +2581,25 @@ __device__ __forceinline__ void bcast_row_rl(const T (&tv)[rl_nv<K>()],
     }
 }
 
+// The 12 coefficients of row ic outside the attitude section (astrometric,
+// instrumental, global) and its 6 instrumental indices, loaded by the K lanes
+// of its row slot together: lane r of the slot loads entries r, r + K, ...
+// and each entry is then broadcast to the K lanes (K in {2, 4}); for other
+// K every lane loads all of them.
 template <typename T, int K, bool CIDX>
 __device__ __forceinline__ void load_row_rl(const SysView& s, const T* __restrict__ val,
                                             int64_t ic, int rj, T (&a)[kPar],
                                             int32_t (&ix)[kInstr])
 {
-    constexpr int kNa = kAstro + kInstr + 1;  // 12 coefficients outside the attitude section
-    auto col = [](int e) { return e < kAstro ? e : kOffInstr + (e - kAstro); };
-    const int64_t m = s.m;
     if constexpr (K == 2 || K == 4) {
-        constexpr int nv = kNa / K, ni = (kInstr + K - 1) / K;
-        T tv[nv];
-        int32_t ti[ni];
-#pragma unroll
-        for (int t = 0; t < nv; ++t) tv[t] = ldnt(&val[col(t * K + rj) * m + ic]);
-#pragma unroll
-        for (int t = 0; t < ni; ++t) {
-            const int j = t * K + rj < kInstr ? t * K + rj : kInstr - 1;
-            ti[t] = instr_of<CIDX>(s, j, ic);
-        }
-#pragma unroll
-        for (int t = 0; t < nv; ++t) {
-            a[col(t * K + 0)] = group_bcast_v<K, 0>(tv[t]);
-            a[col(t * K + 1)] = group_bcast_v<K, 1>(tv[t]);
-            if constexpr (K == 4) {
-                a[col(t * K + 2)] = group_bcast_v<K, 2>(tv[t]);
-                a[col(t * K + 3)] = group_bcast_v<K, 3>(tv[t]);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < ni; ++t) {
-            if (t * K + 0 < kInstr) ix[t * K + 0] = group_bcast<K, 0>(ti[t]);
-            if (t * K + 1 < kInstr) ix[t * K + 1] = group_bcast<K, 1>(ti[t]);
-            if constexpr (K == 4) {
-                if (t * K + 2 < kInstr) ix[t * K + 2] = group_bcast<K, 2>(ti[t]);
-                if (t * K + 3 < kInstr) ix[t * K + 3] = group_bcast<K, 3>(ti[t]);
-            }
-        }
+        T tv[rl_nv<K>()];
+        int32_t ti[rl_ni<K>()];
+        load_raw_rl<T, K, CIDX>(s, val, ic, rj, tv, ti);
+        bcast_row_rl<T, K>(tv, ti, a, ix);
     } else {
+        const int64_t m = s.m;
 #pragma unroll
-        for (int e = 0; e < kNa; ++e) a[col(e)] = ldnt(&val[col(e) * m + ic]);
+        for (int e = 0; e < kNaRl; ++e) a[rl_col(e)] = ldnt(&val[rl_col(e) * m + ic]);
 #pragma unroll
         for (int j = 0; j < kInstr; ++j) ix[j] = instr_of<CIDX>(s, j, ic);
     }
