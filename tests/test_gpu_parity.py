@@ -49,6 +49,11 @@ SPECS = {
     # rest in a tail window
     "huge_instr": synth.tiny(seed=27, n_stars=300, obs=(30, 60), n_dfa=200,
                              n_instr_cols=25000),
+    # the same with 10,240 rows: every value and index column starts on a
+    # 128-byte line, so the tail windows take their nontemporal-load form
+    # (the other small systems take the plain-load one)
+    "huge_instr_lined": synth.tiny(seed=32, n_stars=256, obs=(40, 40), n_dfa=200,
+                                   n_instr_cols=25000),
     # 70,000 instrumental columns: beyond a uint16 index (no compact index
     # copies) and four LDS windows (one histogram, three tail windows)
     "instr_70k": synth.tiny(seed=28, n_stars=300, obs=(30, 60), n_dfa=150,
@@ -222,7 +227,8 @@ def _b(S, o, rhs=0):
 # differ by 2e-9 at k = 30 on the 36-unknown "one_star" system, 1e-15 at 15).
 @pytest.mark.parametrize("name,itn", [("c0", 50), ("c0", 200), ("ragged", 120),
                                        ("one_star", 15), ("few_rows", 15), ("wide_instr", 60),
-                                       ("huge_instr", 30), ("instr_70k", 30),
+                                       ("huge_instr", 30), ("huge_instr_lined", 30),
+                                       ("instr_70k", 30),
                                        ("instr_12k", 30), ("instr_12k_f32", 30),
                                        ("wide_att_f32", 30)])
 @pytest.mark.parametrize("graph", [1, 0])
@@ -359,6 +365,28 @@ def test_tiny_buckets_parity(torch_cuda, name):
     x, info = g.solve(torch.from_numpy(bs[0]).cuda(), itn, atol=0.0, btol=0.0)
     torch.cuda.synchronize()
     assert info.itn == itn and rel_inf(x.cpu().numpy(), refs[0]) <= 1e-10
+    g.set_option("ktile", 2)
+    X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(np.stack(bs, axis=1))).cuda(),
+                               itn, 0.0, 0.0)
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    g.close()
+    for j in range(2):
+        assert infos[j].itn == itn and rel_inf(Xh[:, j], refs[j]) <= 1e-10, j
+
+
+# 2-RHS k-tile on the line-aligned system: its K-wide tail windows in the
+# nontemporal-load form, against the oracle.
+def test_batched_line_aligned_tail(torch_cuda):
+    torch = torch_cuda
+    S, o = system("huge_instr_lined")
+    itn = 20
+    say(f"batched tail windows, line-aligned columns: m={S.m} n={o.n} itn={itn}")
+    bs = [_b(S, o, rhs=j) for j in range(2)]
+    refs = [o.lsqr(b, itn, atol=0.0, btol=0.0, conlim=0.0, tests=False)[0] for b in bs]
+    g = gpu_system(torch, S)
+    g.set_option("att_buckets", 5)
+    g.set_option("tests", 0)
     g.set_option("ktile", 2)
     X, infos = g.solve_batched(torch.from_numpy(np.ascontiguousarray(np.stack(bs, axis=1))).cuda(),
                                itn, 0.0, 0.0)
